@@ -1,0 +1,186 @@
+/*
+ * fdfd.h -- C ABI of the MI355X sparse direct solver for repeated 2D FDFD
+ * solves with a cached factorisation.
+ *
+ * The operations follow the problem statement of the paper (Sec. II):
+ *   - solve the discretised Maxwell system A(eps) x = b            (Eq. 2)
+ *   - solve the adjoint system A^T lam = (dF/dx)^T                 (Eq. 4)
+ *   - form dF/deps_n = -2 Re(lam^T dA/deps_n x) = -2 w^2 Re(lam_n x_n) (Eq. 3)
+ *   - cache the symbolic factorisation across iterations and wavelengths,
+ *     and the numeric factorisation across the forward and adjoint solves and
+ *     across right-hand sides (the three caching levels of Sec. II).
+ *
+ * Operator.  Grid of nx * ny cells, unknown n = i + nx*j, grid units
+ * (dx = 1, c = 1, omega = 2*pi*dx/lambda), Dirichlet E = 0 outside the grid,
+ * stretched-coordinate PML of npml_x / npml_y cells on each side:
+ *   A = Sx_c^-1 Dxb Sx_f^-1 Dxf + Sy_c^-1 Dyb Sy_f^-1 Dyf + w^2 diag(eps_r),
+ *   s(p) = 1 + i sigma(p)/w, sigma = (32/npml) d(p)^3,
+ *   d(p) = max(npml - p, p - (n - npml), 0)/npml,
+ * at cell centres p = i + 1/2 and faces p = i.  A is not symmetric inside the
+ * PML; S*A with S = diag(sx_c[i] sy_c[j]) is complex symmetric, so the library
+ * factors S*A = L D L^T (no conjugation) in nested-dissection order and uses
+ *   x = (SA)^-1 (S b),   lam = S (SA)^-1 g   (A^T = (SA) S^-1).
+ *
+ * Memory.  Every pointer named *_dev is device memory owned by the caller and
+ * must stay valid until the work enqueued on the given stream completes.
+ * Complex vectors are interleaved complex128 (re, im doubles), laid out
+ * [nsys][nrhs][N] with N = nx*ny in grid order.  The plan owns all other
+ * device memory (analysis tables, factors of every system, workspaces).
+ *
+ * Streams and errors.  Calls enqueue on hip_stream (a hipStream_t; NULL is
+ * the null stream) and return without synchronising, except fdfd_analyze,
+ * fdfd_query and fdfd_destroy.  Argument and state errors are returned at
+ * once and enqueue nothing.  Numeric conditions found on the device (pivot
+ * perturbation, non-finite values, refinement that misses its tolerance) are
+ * recorded in a device status word and reported by fdfd_query.  No C++
+ * exception crosses this interface.  A plan is not thread safe.
+ */
+#ifndef FDFD_H_
+#define FDFD_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FDFD_OK = 0,
+  FDFD_ERR_ARG = 1,      /* invalid argument (null pointer, bad size)          */
+  FDFD_ERR_STATE = 2,    /* call out of order, e.g. solve before refactor      */
+  FDFD_ERR_NOMEM = 3,    /* device allocation failed or exceeds mem_cap_bytes  */
+  FDFD_ERR_HIP = 4,      /* a HIP runtime call failed                          */
+  FDFD_ERR_NUMERIC = 5,  /* non-finite values, or refinement missed its tolerance */
+  FDFD_WARN_PIVOT = 6    /* >= 1 pivot was perturbed; results are refined      */
+} fdfd_status;
+
+typedef enum {
+  FDFD_C128 = 0,    /* complex128 factors and solves                            */
+  FDFD_C64_IR = 1   /* complex64 factors; FP64 residuals and iterative refinement */
+} fdfd_prec;
+
+/* fdfd_desc.flags */
+#define FDFD_ANALYZE_HOST_ONLY 1  /* symbolic analysis only: no device memory;  */
+                                  /* only fdfd_query / fdfd_get_table work     */
+
+typedef struct {
+  int32_t nx, ny;          /* grid cells, nx, ny >= 2                           */
+  int32_t npml_x, npml_y;  /* PML cells per side, 2*npml < n                    */
+  int32_t nsys;            /* same-pattern systems factored together (>= 1)    */
+  int32_t max_rhs;         /* largest nrhs passed to the solves (>= 1)         */
+  int32_t prec;            /* fdfd_prec                                         */
+  int32_t device;          /* HIP device ordinal, -1 = current device          */
+  int32_t leaf;            /* cells per undivided dissection leaf, 0 = default */
+  int32_t flags;           /* FDFD_ANALYZE_HOST_ONLY                            */
+  int64_t mem_cap_bytes;   /* refuse plans needing more device memory, 0 = off  */
+} fdfd_desc;
+
+typedef struct fdfd_plan_s* fdfd_plan;
+
+/* Per-plan figures.  Counts are per system unless said otherwise. */
+typedef struct {
+  int64_t n;                 /* unknowns                                          */
+  int64_t nfronts;           /* fronts in the separator tree                      */
+  int64_t nlevels;           /* tree height (levels of the level schedule)        */
+  int64_t nnz_factor;        /* lower-triangular entries of L (incl. D)           */
+  int64_t factor_bytes;      /* bytes of one system's factor panels               */
+  int64_t update_bytes;      /* bytes of one system's update blocks               */
+  int64_t device_bytes;      /* all device memory held by the plan                */
+  double refactor_flops;     /* real flops of one numeric factorisation           */
+  double schur_flops;        /* of which in the Schur-complement updates          */
+  int32_t max_front, max_pivots;
+  int32_t leaf;
+  int32_t n_perturbed;       /* pivots perturbed by the last refactor, all systems */
+  double min_pivot_ratio;    /* min |d_k| / ||SA||_max over the last refactor      */
+  int32_t ir_steps_solve;    /* refinement steps taken by the last fdfd_solve      */
+  int32_t ir_steps_adjoint;  /* ... by the last fdfd_adjoint_grad                  */
+  double rel_residual_solve;   /* max over columns of ||Sb - SAx|| / ||Sb||        */
+  double rel_residual_adjoint; /* max over columns of ||g - SA lam'|| / ||g||      */
+  int32_t device_flags;      /* raw device status bits                            */
+  int32_t pad_;
+} fdfd_info;
+
+/*
+ * Symbolic analysis, once per grid (the cached symbolic factorisation of
+ * Sec. II): nested dissection, separator tree, front layout, index maps and
+ * level schedule, then device allocation of every arena.  Host work plus one
+ * upload.  *out receives a new plan on success and NULL otherwise.
+ */
+fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out);
+
+/*
+ * Numeric factorisation of S*A(eps, w_s) for every system s (Sec. II,
+ * numerical factorisation).  eps_dev: float64 [ny][nx] per system, system s at
+ * eps_dev + s*eps_sys_stride (stride 0 = one map shared by all systems).
+ * omega_host: nsys host doubles, w = 2*pi*dx/lambda.  The factor stays valid
+ * for every later solve until the next refactor (Sec. II, caching 1 and 3).
+ */
+fdfd_status fdfd_refactor(fdfd_plan plan, const double* eps_dev, int64_t eps_sys_stride,
+                          const double* omega_host, void* hip_stream);
+
+/*
+ * Forward solve A x = b for nrhs right-hand sides per system (Eq. 2 and
+ * Eq. 5) with the cached factor.  b_dev, x_dev: complex128 [nsys][nrhs][N].
+ * In FDFD_C128 mode max_ir may be 0.  Each refinement step computes the
+ * residual S b - S A x in FP64, solves for a correction with the factor and
+ * adds it in FP64; refinement stops once every column satisfies
+ * ||Sb - SAx|| <= ir_tol ||Sb|| (ir_tol <= 0: 1e-12), after at most max_ir
+ * steps.  1 <= nrhs <= max_rhs.
+ */
+fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t nrhs,
+                       int32_t max_ir, double ir_tol, void* hip_stream);
+
+/*
+ * Adjoint solve A^T lam = g (Eq. 4 and Eq. 6) with the same cached factor
+ * (S A is symmetric, so lam = S (SA)^-1 g needs no second factorisation),
+ * then the gradient of Eq. (3): grad_n = -2 w_s^2 Re(lam_n x_n), summed over
+ * the nrhs right-hand sides.
+ *   x_dev       complex128 [nsys][nrhs][N]   forward fields from fdfd_solve
+ *   g_dev       complex128 [nsys][nrhs][N]   (dF/dx)^T per column
+ *   lambda_dev  complex128 [nsys][nrhs][N]   adjoint fields, may be NULL
+ *   grad_dev    float64 [nsys][N], or [N] with FDFD_GRAD_SUM_SYSTEMS
+ * FDFD_GRAD_ACCUMULATE adds to grad_dev instead of overwriting it.
+ * Refinement as in fdfd_solve.
+ */
+#define FDFD_GRAD_ACCUMULATE 1
+#define FDFD_GRAD_SUM_SYSTEMS 2
+fdfd_status fdfd_adjoint_grad(fdfd_plan plan, const void* x_dev, const void* g_dev,
+                              int32_t nrhs, int32_t max_ir, double ir_tol,
+                              void* lambda_dev, double* grad_dev, int32_t flags,
+                              void* hip_stream);
+
+/*
+ * Synchronises the plan's last stream, then fills *info.  Returns
+ * FDFD_ERR_NUMERIC if the device recorded non-finite values or a refinement
+ * that missed its tolerance, FDFD_WARN_PIVOT if pivots were perturbed, else
+ * FDFD_OK.
+ */
+fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info);
+
+/*
+ * Host copies of the analysis tables, for inspection and tests:
+ *   FDFD_TABLE_PERM    int32 [N]        elimination position -> grid index
+ *   FDFD_TABLE_FRONTS  int32 [nfronts][4] (first position, pivots, update rows, parent)
+ *   FDFD_TABLE_UPDATE  int32 [sum of update rows] update rows (positions), front by front
+ * count is the capacity of out in int32 elements.  Returns FDFD_ERR_ARG if it
+ * is too small.  Works for host-only plans.
+ */
+#define FDFD_TABLE_PERM 0
+#define FDFD_TABLE_FRONTS 1
+#define FDFD_TABLE_UPDATE 2
+fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t count);
+
+/* Static text of a status code. */
+const char* fdfd_status_str(fdfd_status s);
+
+/* Text of the plan's last error (empty string if none; never NULL). */
+const char* fdfd_last_error(fdfd_plan plan);
+
+/* Frees the plan and all its device memory after synchronising its stream. */
+void fdfd_destroy(fdfd_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDFD_H_ */

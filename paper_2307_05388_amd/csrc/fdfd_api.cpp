@@ -1,0 +1,499 @@
+// C ABI of the solver (declared in include/fdfd.h): argument checking, plan
+// construction (analysis, level schedule, task lists, device arenas) and the
+// calls that enqueue the kernels of fdfd_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "analysis.h"
+#include "plan.hpp"
+
+namespace fdfd {
+hipError_t configure_kernels(Plan& P, int lds_limit);
+}
+
+struct fdfd_plan_s {
+  fdfd::Plan p;
+};
+
+namespace {
+
+using fdfd::Plan;
+
+thread_local std::string g_error;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) changed = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+fdfd_status fail(Plan* P, fdfd_status s, const std::string& msg) {
+  if (P) P->last_error = msg;
+  g_error = msg;
+  return s;
+}
+
+fdfd_status hip_fail(Plan* P, hipError_t e, const char* what) {
+  return fail(P, FDFD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+template <typename T>
+fdfd_status upload(Plan& P, T** dst, const std::vector<T>& src) {
+  const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(&P, FDFD_ERR_NOMEM, "hipMalloc of an analysis table failed");
+  P.allocations.push_back(d);
+  P.device_bytes += (int64_t)bytes;
+  if (!src.empty()) {
+    e = hipMemcpy(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(&P, e, "uploading an analysis table");
+  }
+  *dst = static_cast<T*>(d);
+  return FDFD_OK;
+}
+
+fdfd_status alloc(Plan& P, void** dst, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(&P, FDFD_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  P.allocations.push_back(d);
+  P.device_bytes += (int64_t)bytes;
+  *dst = d;
+  return FDFD_OK;
+}
+
+void free_all(Plan& P) {
+  for (void* d : P.allocations) (void)hipFree(d);
+  P.allocations.clear();
+  if (P.status_host) (void)hipHostFree(P.status_host);
+  P.status_host = nullptr;
+}
+
+// Level schedule: fused small-front kernel where the panel fits the LDS budget,
+// else the blocked multi-workgroup path with precomputed task lists.
+void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std::vector<int32_t>& mslot) {
+  const fdfd::Analysis& A = P.an;
+  const int NB = P.nb_large;
+  const size_t cs = P.csize;
+  mslot.assign(A.nfronts, 0);
+  P.levels.clear();
+  P.nmslot = 0;
+  for (int l = 0; l < A.nlevels; ++l) {
+    fdfd::LevelPlan L;
+    L.first = A.level_ptr[l];
+    L.count = A.level_ptr[l + 1] - A.level_ptr[l];
+    L.max_m = L.max_p = L.max_u = 0;
+    size_t need = 0;
+    for (int k = L.first; k < L.first + L.count; ++k) {
+      const int f = A.level_fronts[k];
+      L.max_m = std::max(L.max_m, A.m(f));
+      L.max_p = std::max(L.max_p, A.npiv[f]);
+      L.max_u = std::max(L.max_u, A.nupd[f]);
+      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f]) * cs);
+    }
+    L.small = need <= small_cap;
+    L.small_lds = need;
+    L.asm_off = 0;
+    L.nasm = 0;
+    if (!L.small) {
+      L.asm_off = (int64_t)tasks.size();
+      for (int k = L.first; k < L.first + L.count; ++k) {
+        const int f = A.level_fronts[k];
+        const int m = A.m(f);
+        const int cw = std::max(1, 4096 / m);
+        for (int c0 = 0; c0 < m; c0 += cw) {
+          tasks.push_back(f);
+          tasks.push_back(c0);
+          tasks.push_back(std::min(m, c0 + cw));
+          ++L.nasm;
+        }
+        mslot[f] = P.nmslot++;
+      }
+      for (int kb = 0; kb < L.max_p; kb += NB) {
+        fdfd::BlockStep S;
+        S.kb = kb;
+        S.nb = NB;
+        S.diag_off = (int64_t)tasks.size();
+        S.ndiag = 0;
+        for (int k = L.first; k < L.first + L.count; ++k) {
+          const int f = A.level_fronts[k];
+          if (A.npiv[f] > kb) {
+            tasks.push_back(f);
+            ++S.ndiag;
+          }
+        }
+        S.trsm_off = (int64_t)tasks.size();
+        S.ntrsm = 0;
+        for (int k = L.first; k < L.first + L.count; ++k) {
+          const int f = A.level_fronts[k];
+          if (A.npiv[f] <= kb) continue;
+          const int nbk = std::min(NB, A.npiv[f] - kb);
+          for (int r0 = kb + nbk; r0 < A.m(f); r0 += 64) {
+            tasks.push_back(f);
+            tasks.push_back(r0);
+            ++S.ntrsm;
+          }
+        }
+        S.upd_off = (int64_t)tasks.size();
+        S.nupd = 0;
+        for (int k = L.first; k < L.first + L.count; ++k) {
+          const int f = A.level_fronts[k];
+          if (A.npiv[f] <= kb) continue;
+          const int nbk = std::min(NB, A.npiv[f] - kb);
+          const int t0 = kb + nbk, m = A.m(f);
+          for (int c0 = t0; c0 < m; c0 += 64)
+            for (int r0 = c0; r0 < m; r0 += 64) {
+              tasks.push_back(f);
+              tasks.push_back(r0);
+              tasks.push_back(c0);
+              ++S.nupd;
+            }
+        }
+        L.steps.push_back(S);
+      }
+    }
+    P.levels.push_back(L);
+  }
+}
+
+fdfd_status check_desc(const fdfd_desc* d) {
+  if (!d) return fail(nullptr, FDFD_ERR_ARG, "desc is NULL");
+  if (d->nx < 2 || d->ny < 2) return fail(nullptr, FDFD_ERR_ARG, "nx and ny must be >= 2");
+  if (d->npml_x < 0 || d->npml_y < 0 || 2 * d->npml_x >= d->nx || 2 * d->npml_y >= d->ny)
+    return fail(nullptr, FDFD_ERR_ARG, "need 0 <= 2*npml < n on both axes");
+  if (d->nsys < 1 || d->nsys > 64) return fail(nullptr, FDFD_ERR_ARG, "nsys must be in [1, 64]");
+  if (d->max_rhs < 1 || d->max_rhs > 64) return fail(nullptr, FDFD_ERR_ARG, "max_rhs must be in [1, 64]");
+  if (d->prec != FDFD_C128 && d->prec != FDFD_C64_IR) return fail(nullptr, FDFD_ERR_ARG, "unknown precision");
+  if (d->leaf < 0) return fail(nullptr, FDFD_ERR_ARG, "leaf must be >= 0");
+  if (d->mem_cap_bytes < 0) return fail(nullptr, FDFD_ERR_ARG, "mem_cap_bytes must be >= 0");
+  if ((int64_t)d->nx * d->ny > ((int64_t)1 << 28)) return fail(nullptr, FDFD_ERR_ARG, "grid too large");
+  return FDFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdfd_status_str(fdfd_status s) {
+  switch (s) {
+    case FDFD_OK: return "ok";
+    case FDFD_ERR_ARG: return "invalid argument";
+    case FDFD_ERR_STATE: return "call out of order";
+    case FDFD_ERR_NOMEM: return "out of device memory";
+    case FDFD_ERR_HIP: return "HIP runtime error";
+    case FDFD_ERR_NUMERIC: return "numerical failure";
+    case FDFD_WARN_PIVOT: return "pivots perturbed";
+  }
+  return "unknown status";
+}
+
+const char* fdfd_last_error(fdfd_plan plan) {
+  if (!plan) return g_error.c_str();
+  return plan->p.last_error.c_str();
+}
+
+fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
+  if (!out) return fail(nullptr, FDFD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  fdfd_status s = check_desc(desc);
+  if (s != FDFD_OK) return s;
+  fdfd_plan_s* h = new (std::nothrow) fdfd_plan_s();
+  if (!h) return fail(nullptr, FDFD_ERR_NOMEM, "host allocation failed");
+  Plan& P = h->p;
+  P.desc = *desc;
+  P.host_only = (desc->flags & FDFD_ANALYZE_HOST_ONLY) != 0;
+  P.is_c64 = desc->prec == FDFD_C64_IR;
+  P.csize = P.is_c64 ? 8 : 16;
+  const int leaf = desc->leaf > 0 ? desc->leaf : env_int("FDFD_LEAF", 36);
+  const std::string err = fdfd::analyze_grid(desc->nx, desc->ny, leaf, P.an);
+  if (!err.empty()) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_ARG, err);
+  }
+  if (P.host_only) {
+    *out = h;
+    return FDFD_OK;
+  }
+
+  int dev = desc->device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_HIP, "no HIP device");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_HIP, "HIP device not available");
+  }
+  P.device = dev;
+  DeviceGuard guard(dev);
+  int lds_limit = 65536;
+  (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  const size_t cs = P.csize;
+  P.nb_large = 64;
+  while (P.nb_large > 16 && ((size_t)(P.nb_large * P.nb_large + 65 * P.nb_large) * cs > (size_t)lds_limit ||
+                             (size_t)(2 * P.nb_large * 64) * cs > (size_t)lds_limit))
+    P.nb_large /= 2;
+  size_t small_cap = (size_t)env_int("FDFD_SMALL_LDS", 65536);
+  small_cap = std::min(small_cap, (size_t)lds_limit);
+
+  std::vector<int32_t> tasks, mslot;
+  build_schedule(P, small_cap, tasks, mslot);
+  size_t max_solve_lds = 0;
+  for (const auto& L : P.levels)
+    max_solve_lds = std::max(max_solve_lds, ((size_t)L.max_m * desc->max_rhs + 64 * 65) * cs);
+  if (max_solve_lds > (size_t)lds_limit) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_ARG, "front too large for the solve kernels at this max_rhs");
+  }
+
+  // memory plan
+  const int64_t N = P.an.N, nsys = desc->nsys, R = desc->max_rhs;
+  const int64_t sum_u = P.an.upd_ptr.back();
+  P.res_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
+  const int64_t NB = P.nb_large;
+  const int64_t need = nsys * P.an.fac_total * (int64_t)cs + nsys * P.an.upd_total * (int64_t)cs +
+                       nsys * std::max<int64_t>(1, P.nmslot) * NB * NB * (int64_t)cs +
+                       nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16 + nsys * 8 + nsys * N * 8 +
+                       nsys * R * N * (int64_t)cs + nsys * R * sum_u * (int64_t)cs + 2 * nsys * R * N * 16 +
+                       nsys * R * P.res_blocks * 16 + (int64_t)sizeof(fdfd::DevStatus);
+  if (desc->mem_cap_bytes > 0 && need > desc->mem_cap_bytes) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_NOMEM,
+                "plan needs " + std::to_string(need) + " device bytes, above mem_cap_bytes");
+  }
+
+  fdfd_status st = FDFD_OK;
+#define TRY(x)                   \
+  do {                           \
+    st = (x);                    \
+    if (st != FDFD_OK) goto bad; \
+  } while (0)
+  {
+    const fdfd::Analysis& A = P.an;
+    TRY(upload(P, &P.t.pbeg, A.pbeg));
+    TRY(upload(P, &P.t.npiv, A.npiv));
+    TRY(upload(P, &P.t.nupd, A.nupd));
+    TRY(upload(P, &P.t.child_ptr, A.child_ptr));
+    TRY(upload(P, &P.t.child_list, A.child_list));
+    TRY(upload(P, &P.t.upd_ptr, A.upd_ptr));
+    TRY(upload(P, &P.t.upd_idx, A.upd_idx));
+    TRY(upload(P, &P.t.gmap, A.gmap));
+    TRY(upload(P, &P.t.nbr_row, A.nbr_row));
+    TRY(upload(P, &P.t.perm, A.perm));
+    TRY(upload(P, &P.t.iperm, A.iperm));
+    TRY(upload(P, &P.t.level_fronts, A.level_fronts));
+    TRY(upload(P, &P.t.mslot, mslot));
+    TRY(upload(P, &P.t.fac_off, A.fac_off));
+    TRY(upload(P, &P.t.upd_off, A.upd_off));
+    TRY(upload(P, &P.t.gmap_ptr, A.gmap_ptr));
+    TRY(upload(P, &P.t.tasks, tasks));
+    TRY(alloc(P, &P.fac, nsys * A.fac_total * cs));
+    TRY(alloc(P, &P.upd, nsys * A.upd_total * cs));
+    TRY(alloc(P, &P.mscr, nsys * std::max<int64_t>(1, P.nmslot) * NB * NB * cs));
+    TRY(alloc(P, (void**)&P.pml, nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16));
+    TRY(alloc(P, (void**)&P.omega, nsys * 8));
+    TRY(alloc(P, (void**)&P.eps, nsys * N * 8));
+    TRY(alloc(P, &P.y, nsys * R * N * cs));
+    TRY(alloc(P, &P.wv, nsys * R * std::max<int64_t>(1, sum_u) * cs));
+    TRY(alloc(P, (void**)&P.xw, nsys * R * N * 16));
+    TRY(alloc(P, (void**)&P.res, nsys * R * N * 16));
+    TRY(alloc(P, (void**)&P.partial, nsys * R * P.res_blocks * 16));
+    TRY(alloc(P, (void**)&P.status, sizeof(fdfd::DevStatus)));
+    hipError_t e = hipMemset(P.status, 0, sizeof(fdfd::DevStatus));
+    if (e != hipSuccess) {
+      st = hip_fail(&P, e, "hipMemset");
+      goto bad;
+    }
+    e = hipHostMalloc((void**)&P.status_host, sizeof(fdfd::DevStatus), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      st = fail(&P, FDFD_ERR_NOMEM, "pinned host allocation failed");
+      goto bad;
+    }
+    e = fdfd::configure_kernels(P, lds_limit);
+    if (e != hipSuccess) {
+      st = hip_fail(&P, e, "hipFuncSetAttribute");
+      goto bad;
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      st = hip_fail(&P, e, "analysis upload");
+      goto bad;
+    }
+  }
+#undef TRY
+  P.solve_lds_max = max_solve_lds;
+  *out = h;
+  return FDFD_OK;
+bad:
+  g_error = P.last_error;
+  free_all(P);
+  delete h;
+  return st;
+}
+
+fdfd_status fdfd_refactor(fdfd_plan plan, const double* eps_dev, int64_t eps_sys_stride,
+                          const double* omega_host, void* hip_stream) {
+  if (!plan) return fail(nullptr, FDFD_ERR_ARG, "plan is NULL");
+  Plan& P = plan->p;
+  if (P.host_only) return fail(&P, FDFD_ERR_STATE, "host-only plan cannot factor");
+  if (!eps_dev || !omega_host) return fail(&P, FDFD_ERR_ARG, "eps_dev and omega_host must be non-NULL");
+  if (eps_sys_stride < 0 || (eps_sys_stride > 0 && eps_sys_stride < P.an.N))
+    return fail(&P, FDFD_ERR_ARG, "eps_sys_stride must be 0 or >= nx*ny");
+  std::vector<double> om(omega_host, omega_host + P.desc.nsys);
+  for (double w : om)
+    if (!(w > 0.0) || !std::isfinite(w)) return fail(&P, FDFD_ERR_ARG, "omega must be positive and finite");
+  DeviceGuard guard(P.device);
+  P.omega_host = om;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = fdfd::launch_refactor(P, eps_dev, eps_sys_stride, st);
+  if (e != hipSuccess) return hip_fail(&P, e, "refactor launch");
+  P.last_stream = st;
+  P.factored = true;
+  return FDFD_OK;
+}
+
+fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t nrhs, int32_t max_ir,
+                       double ir_tol, void* hip_stream) {
+  if (!plan) return fail(nullptr, FDFD_ERR_ARG, "plan is NULL");
+  Plan& P = plan->p;
+  if (P.host_only) return fail(&P, FDFD_ERR_STATE, "host-only plan cannot solve");
+  if (!P.factored) return fail(&P, FDFD_ERR_STATE, "solve before refactor");
+  if (!b_dev || !x_dev) return fail(&P, FDFD_ERR_ARG, "b_dev and x_dev must be non-NULL");
+  if (nrhs < 1 || nrhs > P.desc.max_rhs) return fail(&P, FDFD_ERR_ARG, "nrhs must be in [1, max_rhs]");
+  if (max_ir < 0 || max_ir > 100) return fail(&P, FDFD_ERR_ARG, "max_ir must be in [0, 100]");
+  if (!(ir_tol > 0.0)) ir_tol = 1e-12;
+  DeviceGuard guard(P.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = fdfd::launch_solve(P, 0, (const double2*)b_dev, (double2*)x_dev, nrhs, max_ir, ir_tol, st);
+  if (e != hipSuccess) return hip_fail(&P, e, "solve launch");
+  P.last_stream = st;
+  return FDFD_OK;
+}
+
+fdfd_status fdfd_adjoint_grad(fdfd_plan plan, const void* x_dev, const void* g_dev, int32_t nrhs,
+                              int32_t max_ir, double ir_tol, void* lambda_dev, double* grad_dev,
+                              int32_t flags, void* hip_stream) {
+  if (!plan) return fail(nullptr, FDFD_ERR_ARG, "plan is NULL");
+  Plan& P = plan->p;
+  if (P.host_only) return fail(&P, FDFD_ERR_STATE, "host-only plan cannot solve");
+  if (!P.factored) return fail(&P, FDFD_ERR_STATE, "adjoint before refactor");
+  if (!x_dev || !g_dev || !grad_dev) return fail(&P, FDFD_ERR_ARG, "x_dev, g_dev and grad_dev must be non-NULL");
+  if (nrhs < 1 || nrhs > P.desc.max_rhs) return fail(&P, FDFD_ERR_ARG, "nrhs must be in [1, max_rhs]");
+  if (max_ir < 0 || max_ir > 100) return fail(&P, FDFD_ERR_ARG, "max_ir must be in [0, 100]");
+  if (flags & ~(FDFD_GRAD_ACCUMULATE | FDFD_GRAD_SUM_SYSTEMS)) return fail(&P, FDFD_ERR_ARG, "unknown flags");
+  if (!(ir_tol > 0.0)) ir_tol = 1e-12;
+  DeviceGuard guard(P.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = fdfd::launch_solve(P, 1, (const double2*)g_dev, nullptr, nrhs, max_ir, ir_tol, st);
+  if (e != hipSuccess) return hip_fail(&P, e, "adjoint launch");
+  e = fdfd::launch_gradient(P, (const double2*)x_dev, P.xw, nrhs, (double2*)lambda_dev, grad_dev, flags, st);
+  if (e != hipSuccess) return hip_fail(&P, e, "gradient launch");
+  P.last_stream = st;
+  return FDFD_OK;
+}
+
+fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
+  if (!plan || !info) return fail(nullptr, FDFD_ERR_ARG, "plan and info must be non-NULL");
+  Plan& P = plan->p;
+  std::memset(info, 0, sizeof(*info));
+  const fdfd::Analysis& A = P.an;
+  info->n = A.N;
+  info->nfronts = A.nfronts;
+  info->nlevels = A.nlevels;
+  info->nnz_factor = A.nnz_l;
+  info->factor_bytes = A.fac_total * (int64_t)P.csize;
+  info->update_bytes = A.upd_total * (int64_t)P.csize;
+  info->device_bytes = P.device_bytes;
+  info->refactor_flops = A.flops_factor;
+  info->schur_flops = A.flops_schur;
+  info->max_front = A.max_front;
+  info->max_pivots = A.max_piv;
+  info->leaf = A.leaf;
+  info->min_pivot_ratio = -1.0;
+  info->rel_residual_solve = -1.0;
+  info->rel_residual_adjoint = -1.0;
+  if (P.host_only) return FDFD_OK;
+  DeviceGuard guard(P.device);
+  hipError_t e = hipMemcpyAsync(P.status_host, P.status, sizeof(fdfd::DevStatus), hipMemcpyDeviceToHost,
+                                P.last_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(P.last_stream);
+  if (e != hipSuccess) return hip_fail(&P, e, "status read-back");
+  const fdfd::DevStatus& S = *P.status_host;
+  info->n_perturbed = S.n_perturbed;
+  double mr;
+  std::memcpy(&mr, &S.min_ratio_bits, sizeof(double));
+  info->min_pivot_ratio = P.factored ? mr : -1.0;
+  info->ir_steps_solve = S.ir_steps_solve;
+  info->ir_steps_adjoint = S.ir_steps_adj;
+  info->rel_residual_solve = S.rel_solve;
+  info->rel_residual_adjoint = S.rel_adj;
+  info->device_flags = (S.nonfinite ? 1 : 0) | (S.ir_failed_solve ? 2 : 0) | (S.ir_failed_adj ? 4 : 0) |
+                       (S.spin_timeout ? 8 : 0);
+  if (S.nonfinite) return fail(&P, FDFD_ERR_NUMERIC, "non-finite value in the factor or residual");
+  if (S.spin_timeout) return fail(&P, FDFD_ERR_NUMERIC, "a device dependency wait timed out");
+  if (S.ir_failed_solve || S.ir_failed_adj)
+    return fail(&P, FDFD_ERR_NUMERIC, "iterative refinement did not reach its tolerance");
+  if (S.n_perturbed > 0) return FDFD_WARN_PIVOT;
+  return FDFD_OK;
+}
+
+fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t count) {
+  if (!plan || !out) return fail(nullptr, FDFD_ERR_ARG, "plan and out must be non-NULL");
+  Plan& P = plan->p;
+  const fdfd::Analysis& A = P.an;
+  if (which == FDFD_TABLE_PERM) {
+    if (count < A.N) return fail(&P, FDFD_ERR_ARG, "buffer too small");
+    std::copy(A.perm.begin(), A.perm.end(), out);
+    return FDFD_OK;
+  }
+  if (which == FDFD_TABLE_FRONTS) {
+    if (count < 4 * (int64_t)A.nfronts) return fail(&P, FDFD_ERR_ARG, "buffer too small");
+    for (int f = 0; f < A.nfronts; ++f) {
+      out[4 * f] = A.pbeg[f];
+      out[4 * f + 1] = A.npiv[f];
+      out[4 * f + 2] = A.nupd[f];
+      out[4 * f + 3] = A.parent[f];
+    }
+    return FDFD_OK;
+  }
+  if (which == FDFD_TABLE_UPDATE) {
+    if (count < (int64_t)A.upd_idx.size()) return fail(&P, FDFD_ERR_ARG, "buffer too small");
+    std::copy(A.upd_idx.begin(), A.upd_idx.end(), out);
+    return FDFD_OK;
+  }
+  return fail(&P, FDFD_ERR_ARG, "unknown table");
+}
+
+void fdfd_destroy(fdfd_plan plan) {
+  if (!plan) return;
+  Plan& P = plan->p;
+  if (!P.host_only) {
+    DeviceGuard guard(P.device);
+    if (P.last_stream) (void)hipStreamSynchronize(P.last_stream);
+    (void)hipDeviceSynchronize();
+    free_all(P);
+  }
+  delete plan;
+}
+
+}  // extern "C"

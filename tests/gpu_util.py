@@ -1,0 +1,64 @@
+"""Helpers shared by the GPU tests: run the HIP path and the CPU oracle on the
+same seeded inputs."""
+import os
+import sys
+
+import numpy as np
+
+from paper_2307_05388_amd import problems as P
+
+
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_plan(p, prec="c128", max_rhs=None, leaf=0, small_lds=None):
+    """Plan for problem p; small_lds overrides the LDS budget of the fused
+    small-front kernel (0 forces the blocked large-front path everywhere)."""
+    from paper_2307_05388_amd.fdfd import Plan
+    old = os.environ.get("FDFD_SMALL_LDS")
+    if small_lds is not None:
+        os.environ["FDFD_SMALL_LDS"] = str(small_lds)
+    try:
+        return Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=max_rhs or p.nrhs, prec=prec, leaf=leaf)
+    finally:
+        if small_lds is not None:
+            if old is None:
+                os.environ.pop("FDFD_SMALL_LDS", None)
+            else:
+                os.environ["FDFD_SMALL_LDS"] = old
+
+
+def gpu_iteration(plan, p, eps, b, g=None, c=None, max_ir=0, tol=0.0):
+    """refactor + forward solve + adjoint/gradient; returns host arrays."""
+    torch = torch_cuda()
+    dev = torch.device("cuda:0")
+    eps_t = torch.from_numpy(np.ascontiguousarray(eps)).to(dev)
+    b_t = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    plan.refactor(eps_t, P.omegas(p))
+    x_t = plan.solve(b_t, max_ir=max_ir, tol=tol)
+    if g is None:
+        c_t = torch.from_numpy(c).to(dev)
+        ov = torch.matmul(x_t, c_t.conj())
+        g_t = (c_t.conj()[None, None, :] * ov.conj()[..., None]).contiguous()
+    else:
+        g_t = torch.from_numpy(np.ascontiguousarray(g)).to(dev)
+    lam_t = torch.empty_like(b_t)
+    grad_t = plan.adjoint_grad(x_t, g_t, lam=lam_t, max_ir=max_ir, tol=tol)
+    torch.cuda.synchronize()
+    info = plan.query()
+    return {"x": x_t.cpu().numpy(), "lam": lam_t.cpu().numpy(), "grad": grad_t.cpu().numpy(),
+            "g": g_t.cpu().numpy(), "info": info}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
