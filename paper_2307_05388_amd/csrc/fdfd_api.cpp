@@ -13,10 +13,6 @@
 #include "analysis.h"
 #include "plan.hpp"
 
-namespace fdfd {
-hipError_t configure_kernels(Plan& P, int lds_limit);
-}
-
 struct fdfd_plan_s {
   fdfd::Plan p;
 };
@@ -173,6 +169,12 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     }
     P.levels.push_back(L);
   }
+  P.small_prefix = 0;
+  P.small_lds_prefix = 0;
+  while (P.small_prefix < (int)P.levels.size() && P.levels[P.small_prefix].small) {
+    P.small_lds_prefix = std::max(P.small_lds_prefix, P.levels[P.small_prefix].small_lds);
+    ++P.small_prefix;
+  }
 }
 
 fdfd_status check_desc(const fdfd_desc* d) {
@@ -248,20 +250,27 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   DeviceGuard guard(dev);
   int lds_limit = 65536;
   (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  int ncu = 0;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  P.n_cu = ncu > 0 ? ncu : 256;
+  P.lds_limit = (size_t)lds_limit;
   const size_t cs = P.csize;
   P.nb_large = 64;
-  while (P.nb_large > 16 && ((size_t)(P.nb_large * P.nb_large + 65 * P.nb_large) * cs > (size_t)lds_limit ||
-                             (size_t)(2 * P.nb_large * 64) * cs > (size_t)lds_limit))
+  while (P.nb_large > 16 && ((size_t)(2 * P.nb_large * P.nb_large + 65 * P.nb_large) * cs > (size_t)lds_limit - 512 ||
+                             (size_t)(2 * P.nb_large * 64) * cs > (size_t)lds_limit - 512))
     P.nb_large /= 2;
   size_t small_cap = (size_t)env_int("FDFD_SMALL_LDS", 65536);
-  small_cap = std::min(small_cap, (size_t)lds_limit);
+  // a few hundred bytes stay free for the kernels' static LDS
+  const size_t lds_dyn = (size_t)lds_limit - 512;
+  small_cap = std::min(small_cap, lds_dyn);
 
+  P.sweep_levels = env_int("FDFD_SWEEP_LEVELS", 0) != 0;
+  P.small_levels = env_int("FDFD_SMALL_LEVELS", 0) != 0;
   std::vector<int32_t> tasks, mslot;
   build_schedule(P, small_cap, tasks, mslot);
-  size_t max_solve_lds = 0;
-  for (const auto& L : P.levels)
-    max_solve_lds = std::max(max_solve_lds, ((size_t)L.max_m * desc->max_rhs + 64 * 65) * cs);
-  if (max_solve_lds > (size_t)lds_limit) {
+  if (P.small_levels) P.small_prefix = 0;
+  const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
+  if (max_solve_lds > lds_dyn) {
     delete h;
     return fail(nullptr, FDFD_ERR_ARG, "front too large for the solve kernels at this max_rhs");
   }
@@ -303,6 +312,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(upload(P, &P.t.iperm, A.iperm));
     TRY(upload(P, &P.t.level_fronts, A.level_fronts));
     TRY(upload(P, &P.t.mslot, mslot));
+    TRY(upload(P, &P.t.parent, A.parent));
     TRY(upload(P, &P.t.fac_off, A.fac_off));
     TRY(upload(P, &P.t.upd_off, A.upd_off));
     TRY(upload(P, &P.t.gmap_ptr, A.gmap_ptr));
@@ -319,7 +329,11 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(alloc(P, (void**)&P.res, nsys * R * N * 16));
     TRY(alloc(P, (void**)&P.partial, nsys * R * P.res_blocks * 16));
     TRY(alloc(P, (void**)&P.status, sizeof(fdfd::DevStatus)));
-    hipError_t e = hipMemset(P.status, 0, sizeof(fdfd::DevStatus));
+    TRY(alloc(P, (void**)&P.counters, 64));
+    TRY(alloc(P, (void**)&P.done, nsys * (int64_t)A.nfronts * 4));
+    hipError_t e = hipMemset(P.counters, 0, 64);
+    if (e == hipSuccess) e = hipMemset(P.done, 0, nsys * (int64_t)A.nfronts * 4);
+    if (e == hipSuccess) e = hipMemset(P.status, 0, sizeof(fdfd::DevStatus));
     if (e != hipSuccess) {
       st = hip_fail(&P, e, "hipMemset");
       goto bad;

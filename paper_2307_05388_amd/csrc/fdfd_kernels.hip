@@ -64,7 +64,7 @@ __device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_doub
 // Everything a kernel needs about the plan, passed by value.
 struct KArgs {
   const int32_t *pbeg, *npiv, *nupd, *child_ptr, *child_list, *upd_ptr, *upd_idx;
-  const int32_t *gmap, *nbr_row, *perm, *iperm, *mslot;
+  const int32_t *gmap, *nbr_row, *perm, *iperm, *mslot, *parent;
   const int64_t *fac_off, *upd_off, *gmap_ptr;
   int32_t nx, ny, N, nsys;
   int64_t fac_total, upd_total, sum_u;
@@ -76,7 +76,7 @@ struct KArgs {
   void* mscr;
   DevStatus* st;
   double tau;
-  int32_t nb, nmslot;
+  int32_t nb, nmslot, nfronts;
 };
 
 // ---------------------------------------------------------------------------
@@ -251,17 +251,87 @@ __global__ __launch_bounds__(kThreads) void k_anorm(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Persistent, dependency-driven launches.  Work items are claimed in level
+// order from an atomic counter; an item first waits (bounded spin) until the
+// items it depends on have stored this launch's epoch in their done flag.
+// Items are claimed in topological order, so every awaited item is held by a
+// workgroup that is already running and waits only on earlier items: every
+// wait ends.  The spin limit turns an unexpected stall into a status flag
+// rather than a hang.  The last workgroup to leave resets the counters for the
+// next launch on the stream.
+// ---------------------------------------------------------------------------
+constexpr int kSpinLimit = 1 << 24;
+
+struct Queue {
+  int32_t* counter;  // [0] next item, [1] workgroups that have left
+  int32_t* done;     // [nsys][nfronts] epoch of the last completion
+  DevStatus* st;
+  int32_t epoch, ntasks, wait;
+};
+
+__device__ __forceinline__ int claim(const Queue& q, int* sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) *sh = atomicAdd(&q.counter[0], 1);
+  __syncthreads();
+  return *sh;
+}
+
+__device__ __forceinline__ void leave(const Queue& q) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int n = atomicAdd(&q.counter[1], 1);
+    if (n == (int)(gridDim.x * gridDim.y * gridDim.z) - 1) {
+      q.counter[0] = 0;
+      q.counter[1] = 0;
+    }
+  }
+}
+
+// Polls with relaxed agent-scope loads (they read past the non-coherent
+// caches without invalidating them); the caller issues one acquire fence once
+// every awaited flag is seen.
+__device__ __forceinline__ void wait_flag(const Queue& q, const int32_t* p) {
+  int it = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != q.epoch) {
+    if (++it > kSpinLimit) {
+      atomicExch(&q.st->spin_timeout, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+__device__ __forceinline__ void wait_children(const Queue& q, const KArgs& a, int s, int f) {
+  if (threadIdx.x == 0) {
+    for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k)
+      wait_flag(q, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void wait_parent(const Queue& q, const KArgs& a, int s, int f) {
+  if (threadIdx.x == 0 && a.parent[f] >= 0) {
+    wait_flag(q, q.done + (int64_t)s * a.nfronts + a.parent[f]);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void publish(const Queue& q, int64_t idx) {
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(q.done + idx, q.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
 // Small fronts: one workgroup per (front, system), whole panel in LDS.
 // Assembly, partial LDL^T of the pivot columns, Schur update of the u x u
 // block straight into the front's update slot, panel write-back.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_front_small(KArgs a, const int32_t* fronts) {
+__device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_raw) {
   typedef typename Cx<R>::T C;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   C* F = reinterpret_cast<C*>(smem_raw);
-  const int s = blockIdx.y;
-  const int f = fronts[blockIdx.x];
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
   C* dd = F + (int64_t)m * p;
   C* invd = dd + p;
@@ -313,6 +383,23 @@ __global__ __launch_bounds__(kThreads) void k_front_small(KArgs a, const int32_t
     L[idx] = v;
   }
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin);
+}
+
+// Persistent launch over fronts order[0 .. ntasks/nsys): with q.wait set, a
+// front first waits for its children (claimed earlier in the same launch).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_front_small(KArgs a, Queue q, const int32_t* order) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
+  for (;;) {
+    const int t = claim(q, &sh);
+    if (t >= q.ntasks) break;
+    const int f = order[t / a.nsys], s = t % a.nsys;
+    if (q.wait) wait_children(q, a, s, f);
+    small_front<R>(a, s, f, smem_raw);
+    publish(q, s * a.nfronts + f);
+  }
+  leave(q);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,19 +476,26 @@ __global__ __launch_bounds__(kThreads) void k_diag_large(KArgs a, const int32_t*
     if (r > c) L[(int64_t)c * m + r] = B[c * NB + r];
     else if (r == c) L[(int64_t)c * m + r] = dd[c];
   }
-  // X = L11^-1 (unit lower), one column per thread, into the multiplier scratch
-  C* X = (C*)a.mscr + ((int64_t)s * a.nmslot + a.mslot[f]) * NB * NB;
-  for (int j = threadIdx.x; j < nb; j += kThreads) {
-    for (int i = 0; i < nb; ++i) {
-      C v = czero<C>();
-      if (i == j) {
-        v.x = 1;
-      } else if (i > j) {
-        for (int k = j; k < i; ++k) v = cfms(v, B[k * NB + i], X[j * NB + k]);
-      }
-      X[j * NB + i] = v;
-    }
+  // X = L11^-1 (unit lower) in LDS by row elimination: X = I, then for every k
+  // rows i > k take X[i][:] -= L[i][k] X[k][:] (only columns <= k are nonzero).
+  C* Xl = invd + NB;  // NB x NB, column major
+  for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
+    const int c = idx / nb, r = idx - c * nb;
+    C v = czero<C>();
+    if (r == c) v.x = 1;
+    Xl[c * NB + r] = v;
   }
+  __syncthreads();
+  for (int k = 0; k < nb - 1; ++k) {
+    const int Rn = nb - k - 1, Cn = k + 1;
+    for (int idx = threadIdx.x; idx < Rn * Cn; idx += kThreads) {
+      const int j = idx / Rn, i = k + 1 + (idx - j * Rn);
+      Xl[j * NB + i] = cfms(Xl[j * NB + i], B[k * NB + i], Xl[j * NB + k]);
+    }
+    __syncthreads();
+  }
+  C* X = (C*)a.mscr + ((int64_t)s * a.nmslot + a.mslot[f]) * NB * NB;
+  for (int idx = threadIdx.x; idx < nb * NB; idx += kThreads) X[idx] = Xl[idx];
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin);
 }
 
@@ -495,46 +589,14 @@ __global__ __launch_bounds__(kThreads) void k_update_large(KArgs a, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// Solves.  y holds the working vector in elimination order ([sys][rhs][N]);
-// wv holds each front's update vector ([sys][rhs][sum u]).
+// Solves.  Multifrontal sweeps over the separator tree, one persistent launch
+// per direction.  y holds the elimination-order vector ([sys][rhs][N], factor
+// precision), wv each front's update vector ([sys][rhs][sum u]).  The forward
+// sweep reads the right-hand side in grid order (optionally scaled by S) and
+// the backward sweep writes (or adds) the solution in grid order, so no
+// separate permutation passes run.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool done(const int* flag) { return flag && *(volatile const int*)flag; }
-
-// y[pos] = (S[n] if scale) * src[n], n = perm[pos]
-template <typename R>
-__global__ void k_gather(KArgs a, const double2* src, void* y, int nrhs, int scale, const int* flag) {
-  typedef typename Cx<R>::T C;
-  if (done(flag)) return;
-  const int col = blockIdx.y;  // s*nrhs + r
-  const int s = col / nrhs;
-  C* dst = (C*)y + (int64_t)col * a.N;
-  const double2* in = src + (int64_t)col * a.N;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < a.N;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int n = a.perm[q];
-    double2 v = in[n];
-    if (scale) v = dmul(v, sym_scale(a, s, n));
-    dst[q] = from_d2<C>(v);
-  }
-}
-
-// out[n] (+)= (S[n] if scale) * y[iperm[n]]
-template <typename R>
-__global__ void k_scatter(KArgs a, const void* y, double2* out, int nrhs, int accumulate, int scale,
-                          const int* flag) {
-  typedef typename Cx<R>::T C;
-  if (done(flag)) return;
-  const int col = blockIdx.y;
-  const int s = col / nrhs;
-  const C* src = (const C*)y + (int64_t)col * a.N;
-  double2* o = out + (int64_t)col * a.N;
-  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-       n += (int64_t)gridDim.x * blockDim.x) {
-    double2 v = to_d2(src[a.iperm[n]]);
-    if (scale) v = dmul(v, sym_scale(a, s, (int)n));
-    o[n] = accumulate ? dadd(o[n], v) : v;
-  }
-}
 
 template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
   v.x = __shfl(v.x, lane);
@@ -542,29 +604,41 @@ template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
   return v;
 }
 
-// Forward sweep over one level: V = [y_p; 0] + children's update vectors,
-// V <- L^-1 V over the pivot columns (in 64-column blocks: one wave solves the
-// triangle, all threads apply the rectangle below it), then y_p = D^-1 V_p and
-// the front's update vector = V_u.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_fwd(KArgs a, const int32_t* fronts, void* y, void* wv,
-                                                   int nrhs, const int* flag) {
+struct SweepArgs {
+  const double2* src;  // forward: right-hand sides, grid order
+  double2* out;        // backward: solution, grid order
+  void* y;
+  void* wv;
+  const int* flag;     // refinement converged: skip the launch
+  int32_t nrhs, scale_src, accumulate;
+};
+
+// One front of the forward sweep: V = [rhs_p; 0] + children's update vectors,
+// V <- L^-1 V over the pivot columns in BW-wide blocks (one wave solves the
+// block triangle staged in LDS, all threads apply the rows below it), then
+// y_p = D^-1 V_p and the front's update vector is V_u.
+template <typename R, int BW>
+__device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  if (done(flag)) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* V = reinterpret_cast<C*>(smem_raw);
-  const int s = blockIdx.y;
-  const int f = fronts[blockIdx.x];
-  const int p = a.npiv[f], u = a.nupd[f], m = p + u;
-  const int pb = a.pbeg[f];
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const int nrhs = w.nrhs;
+  C* T = reinterpret_cast<C*>(smem);  // BW x (BW+1)
+  C* V = T + BW * (BW + 1);          // nrhs x m
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  C* Y = (C*)y + (int64_t)s * nrhs * a.N;
-  C* W = (C*)wv + (int64_t)s * nrhs * a.sum_u;
+  C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
+  C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
+  const double2* B = w.src + (int64_t)s * nrhs * a.N;
   const int cb = a.child_ptr[f], ce = a.child_ptr[f + 1];
   const int32_t* g = a.gmap + a.gmap_ptr[f];
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
     const int col = idx / m, r = idx - col * m;
-    C v = r < p ? Y[(int64_t)col * a.N + pb + r] : czero<C>();
+    C v = czero<C>();
+    if (r < p) {
+      const int n = a.perm[pb + r];
+      double2 bv = B[(int64_t)col * a.N + n];
+      if (w.scale_src) bv = dmul(bv, sym_scale(a, s, n));
+      v = from_d2<C>(bv);
+    }
     for (int k = cb; k < ce; ++k) {
       const int gr = g[(k - cb) * m + r];
       if (gr >= 0) v = cadd(v, W[(int64_t)col * a.sum_u + a.upd_ptr[a.child_list[k]] + gr]);
@@ -572,15 +646,20 @@ __global__ __launch_bounds__(kThreads) void k_fwd(KArgs a, const int32_t* fronts
     V[col * m + r] = v;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k0 = 0; k0 < p; k0 += 64) {
-    const int k1 = min(k0 + 64, p), kn = k1 - k0;
-    if (wave == 0) {
+  for (int k0 = 0; k0 < p; k0 += BW) {
+    const int kn = min(BW, p - k0), k1 = k0 + kn;
+    for (int idx = threadIdx.x; idx < kn * kn; idx += kThreads) {
+      const int k = idx / kn, l = idx - k * kn;
+      T[k * (BW + 1) + l] = L[(int64_t)(k0 + k) * m + k0 + l];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
       for (int col = 0; col < nrhs; ++col) {
         C v = lane < kn ? V[col * m + k0 + lane] : czero<C>();
         for (int k = 0; k < kn; ++k) {
           const C vk = shfl_c(v, k);
-          if (lane > k && lane < kn) v = cfms(v, L[(int64_t)(k0 + k) * m + k0 + lane], vk);
+          if (lane > k && lane < kn) v = cfms(v, T[k * (BW + 1) + lane], vk);
         }
         if (lane < kn) V[col * m + k0 + lane] = v;
       }
@@ -602,23 +681,19 @@ __global__ __launch_bounds__(kThreads) void k_fwd(KArgs a, const int32_t* fronts
   }
 }
 
-// Backward sweep over one level: X = [z_p; x(update rows)], then for 64-column
-// blocks from the last: X_blk -= L(rows below blk, blk)^T X(below), and one
-// wave solves the block triangle transposed.  x_p is written back into y.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_bwd(KArgs a, const int32_t* fronts, void* y, int nrhs,
-                                                   const int* flag) {
+// One front of the backward sweep: X = [z_p; x(update rows)], then for BW-wide
+// blocks from the last: X_blk -= L(rows below, blk)^T X(below) (one wave per
+// column, lanes over rows) and one wave solves the transposed block triangle
+// staged in LDS.  x_p goes to y and to the grid-order output.
+template <typename R, int BW>
+__device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  if (done(flag)) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* X = reinterpret_cast<C*>(smem_raw);
-  const int s = blockIdx.y;
-  const int f = fronts[blockIdx.x];
-  const int p = a.npiv[f], u = a.nupd[f], m = p + u;
-  C* T = X + (int64_t)m * nrhs;  // 64 x 65 transposed block triangle
-  const int pb = a.pbeg[f];
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const int nrhs = w.nrhs;
+  C* T = reinterpret_cast<C*>(smem);
+  C* X = T + BW * (BW + 1);
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  C* Y = (C*)y + (int64_t)s * nrhs * a.N;
+  C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
     const int col = idx / m, r = idx - col * m;
@@ -629,14 +704,12 @@ __global__ __launch_bounds__(kThreads) void k_bwd(KArgs a, const int32_t* fronts
   constexpr int NW = kThreads / 64;
   int k1 = p;
   while (k1 > 0) {
-    const int k0 = ((k1 - 1) / 64) * 64;
+    const int k0 = ((k1 - 1) / BW) * BW;
     const int kn = k1 - k0;
-    // X[k] -= sum_{i >= k1} L[i][k] X[i]   (one wave per column k, lanes over i)
     for (int k = k0 + wave; k < k1; k += NW) {
       for (int col = 0; col < nrhs; ++col) {
         C acc = czero<C>();
-        for (int i = k1 + lane; i < m; i += 64)
-          acc = cadd(acc, cmul(L[(int64_t)k * m + i], X[col * m + i]));
+        for (int i = k1 + lane; i < m; i += 64) acc = cadd(acc, cmul(L[(int64_t)k * m + i], X[col * m + i]));
         for (int o = 32; o > 0; o >>= 1) {
           acc.x += __shfl_xor(acc.x, o);
           acc.y += __shfl_xor(acc.y, o);
@@ -644,18 +717,17 @@ __global__ __launch_bounds__(kThreads) void k_bwd(KArgs a, const int32_t* fronts
         if (lane == 0) X[col * m + k] = csub(X[col * m + k], acc);
       }
     }
-    // stage the block triangle: T[l*65 + k] = L[k0+k][k0+l] (row k, column l)
     for (int idx = threadIdx.x; idx < kn * kn; idx += kThreads) {
       const int l = idx / kn, k = idx - l * kn;
-      T[l * 65 + k] = L[(int64_t)(k0 + l) * m + k0 + k];
+      T[l * (BW + 1) + k] = L[(int64_t)(k0 + l) * m + k0 + k];
     }
     __syncthreads();
-    if (wave == 0) {
+    if (threadIdx.x < 64) {
       for (int col = 0; col < nrhs; ++col) {
         C v = lane < kn ? X[col * m + k0 + lane] : czero<C>();
         for (int k = kn - 1; k > 0; --k) {
           const C xk = shfl_c(v, k);
-          if (lane < k) v = cfms(v, T[lane * 65 + k], xk);
+          if (lane < k) v = cfms(v, T[lane * (BW + 1) + k], xk);
         }
         if (lane < kn) X[col * m + k0 + lane] = v;
       }
@@ -663,24 +735,75 @@ __global__ __launch_bounds__(kThreads) void k_bwd(KArgs a, const int32_t* fronts
     __syncthreads();
     k1 = k0;
   }
+  double2* O = w.out + (int64_t)s * nrhs * a.N;
   for (int idx = threadIdx.x; idx < p * nrhs; idx += kThreads) {
     const int col = idx / p, r = idx - col * p;
-    Y[(int64_t)col * a.N + pb + r] = X[col * m + r];
+    const C x = X[col * m + r];
+    Y[(int64_t)col * a.N + pb + r] = x;
+    double2* o = O + (int64_t)col * a.N + a.perm[pb + r];
+    const double2 xv = to_d2(x);
+    *o = w.accumulate ? dadd(*o, xv) : xv;
   }
 }
 
+// Forward sweep: items in level order (leaves first), each waits for its children.
+template <typename R, int BW>
+__global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+  if (done(w.flag)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
+  for (;;) {
+    const int t = claim(q, &sh);
+    if (t >= q.ntasks) break;
+    const int f = order[t / a.nsys], s = t % a.nsys;
+    if (q.wait) wait_children(q, a, s, f);
+    fwd_front<R, BW>(a, w, s, f, smem_raw);
+    publish(q, (int64_t)s * a.nfronts + f);
+  }
+  leave(q);
+}
+
+// Backward sweep: items in reverse level order (root first), each waits for its parent.
+template <typename R, int BW>
+__global__ __launch_bounds__(kThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+  if (done(w.flag)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
+  const int F = a.nfronts;
+  for (;;) {
+    const int t = claim(q, &sh);
+    if (t >= q.ntasks) break;
+    const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
+    if (q.wait) wait_parent(q, a, s, f);
+    bwd_front<R, BW>(a, w, s, f, smem_raw);
+    publish(q, (int64_t)s * F + f);
+  }
+  leave(q);
+}
+
 // ---------------------------------------------------------------------------
-// FP64 refinement: r = rhs_sym - (SA) x, norms, convergence flag.
+// FP64 refinement: r = rhs_sym - (SA) x with per-block partial norms; the last
+// workgroup to finish reduces them in a fixed order, records the relative
+// residual and raises the converged flag (or the failure bits).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_residual(KArgs a, const double2* rhs, const double2* x,
-                                                        double2* res, double* partial, int nrhs,
-                                                        int scale_rhs, const int* flag) {
-  if (done(flag)) return;
+struct ResArgs {
+  const double2* rhs;
+  const double2* x;
+  double2* res;
+  double* partial;
+  int32_t* counter;
+  const int* flag;
+  double tol;
+  int32_t nrhs, scale_rhs, step, last;
+};
+
+__global__ __launch_bounds__(kThreads) void k_residual(KArgs a, ResArgs ra) {
+  if (done(ra.flag)) return;
   const int col = blockIdx.y;
-  const int s = col / nrhs;
-  const double2* X = x + (int64_t)col * a.N;
-  const double2* B = rhs + (int64_t)col * a.N;
-  double2* Rv = res + (int64_t)col * a.N;
+  const int s = col / ra.nrhs;
+  const double2* X = ra.x + (int64_t)col * a.N;
+  const double2* B = ra.rhs + (int64_t)col * a.N;
+  double2* Rv = ra.res + (int64_t)col * a.N;
   double rr = 0.0, bb = 0.0;
   const int nx = a.nx, ny = a.ny;
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
@@ -693,13 +816,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs a, const double2* r
     if (j > 0) ax = dadd(ax, dmul(S.c[2], X[n - nx]));
     if (j < ny - 1) ax = dadd(ax, dmul(S.c[3], X[n + nx]));
     double2 b = B[n];
-    if (scale_rhs) b = dmul(b, sym_scale(a, s, (int)n));
+    if (ra.scale_rhs) b = dmul(b, sym_scale(a, s, (int)n));
     const double2 r = dsub(b, ax);
     Rv[n] = r;
     rr += r.x * r.x + r.y * r.y;
     bb += b.x * b.x + b.y * b.y;
   }
   __shared__ double red[2][kThreads];
+  __shared__ int last_block;
   red[0][threadIdx.x] = rr;
   red[1][threadIdx.x] = bb;
   __syncthreads();
@@ -710,10 +834,52 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs a, const double2* r
     }
     __syncthreads();
   }
+  const int nblk = gridDim.x, ncols = gridDim.y;
   if (threadIdx.x == 0) {
-    double* pp = partial + ((int64_t)col * gridDim.x + blockIdx.x) * 2;
+    double* pp = ra.partial + ((int64_t)col * nblk + blockIdx.x) * 2;
     pp[0] = red[0][0];
     pp[1] = red[1][0];
+    __threadfence();
+    last_block = atomicAdd(ra.counter, 1) == nblk * ncols - 1;
+  }
+  __syncthreads();
+  if (!last_block) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double wmax = 0.0;
+  int nf = 0;
+  for (int c = threadIdx.x; c < ncols; c += kThreads) {
+    double r2 = 0.0, b2 = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      r2 += ra.partial[((int64_t)c * nblk + b) * 2];
+      b2 += ra.partial[((int64_t)c * nblk + b) * 2 + 1];
+    }
+    const double rel = b2 > 0 ? sqrt(r2 / b2) : sqrt(r2);
+    if (!(rel <= DBL_MAX)) nf = 1;
+    wmax = fmax(wmax, rel);
+  }
+  red[0][threadIdx.x] = wmax;
+  red[1][threadIdx.x] = nf;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    int anybad = 0;
+    for (int t = 0; t < kThreads; ++t) {
+      mx = fmax(mx, red[0][t]);
+      anybad |= red[1][t] != 0.0;
+    }
+    DevStatus* st = a.st;
+    st->ir_rel = anybad ? NAN : mx;
+    st->ir_steps = ra.step;
+    if (anybad) {
+      st->nonfinite = 1;
+      st->ir_failed = 1;
+      st->ir_flag = 1;
+    } else if (mx <= ra.tol) {
+      st->ir_flag = 1;
+    } else if (ra.last) {
+      st->ir_failed = 1;
+    }
+    *ra.counter = 0;
   }
 }
 
@@ -722,49 +888,6 @@ __global__ void k_ir_begin(DevStatus* st) {
   st->ir_steps = 0;
   st->ir_failed = 0;
   st->ir_rel = -1.0;
-}
-
-// One workgroup: per-column relative residuals in fixed order; sets the flag
-// when every column meets tol (or a non-finite value stops the refinement).
-__global__ __launch_bounds__(kThreads) void k_ir_check(DevStatus* st, const double* partial, int nblk,
-                                                        int ncols, double tol, int step, int last) {
-  if (st->ir_flag) return;
-  __shared__ double worst[kThreads];
-  __shared__ int bad[kThreads];
-  double w = 0.0;
-  int nf = 0;
-  for (int col = threadIdx.x; col < ncols; col += kThreads) {
-    double rr = 0.0, bb = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      rr += partial[((int64_t)col * nblk + b) * 2];
-      bb += partial[((int64_t)col * nblk + b) * 2 + 1];
-    }
-    const double rel = bb > 0 ? sqrt(rr / bb) : sqrt(rr);
-    if (!(rel <= DBL_MAX)) nf = 1;
-    w = fmax(w, rel);
-  }
-  worst[threadIdx.x] = w;
-  bad[threadIdx.x] = nf;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double mx = 0.0;
-    int anybad = 0;
-    for (int t = 0; t < kThreads; ++t) {
-      mx = fmax(mx, worst[t]);
-      anybad |= bad[t];
-    }
-    st->ir_rel = anybad ? NAN : mx;
-    st->ir_steps = step;
-    if (anybad) {
-      st->nonfinite = 1;
-      st->ir_failed = 1;
-      st->ir_flag = 1;
-    } else if (mx <= tol) {
-      st->ir_flag = 1;
-    } else if (last) {
-      st->ir_failed = 1;
-    }
-  }
 }
 
 __global__ void k_ir_end(DevStatus* st, int mode, int with_ir) {
@@ -853,6 +976,7 @@ KArgs make_args(Plan& P) {
   a.perm = P.t.perm;
   a.iperm = P.t.iperm;
   a.mslot = P.t.mslot;
+  a.parent = P.t.parent;
   a.fac_off = P.t.fac_off;
   a.upd_off = P.t.upd_off;
   a.gmap_ptr = P.t.gmap_ptr;
@@ -874,6 +998,7 @@ KArgs make_args(Plan& P) {
   a.tau = P.is_c64 ? 2.44140625e-4 : 1.0536712127723509e-8;
   a.nb = P.nb_large;
   a.nmslot = P.nmslot;
+  a.nfronts = P.an.nfronts;
   return a;
 }
 
@@ -882,6 +1007,27 @@ inline unsigned grid1d(int64_t n, int64_t cap = 2048) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (unsigned)b;
+}
+
+Queue make_queue(Plan& P, int ntasks, int wait) {
+  Queue q;
+  q.counter = P.counters;
+  q.done = P.done;
+  q.st = P.status;
+  q.epoch = ++P.epoch;
+  q.ntasks = ntasks;
+  q.wait = wait;
+  return q;
+}
+
+// Workgroups of a persistent launch: enough to fill every CU at the occupancy
+// the LDS footprint allows, never more than the items.
+unsigned persistent_grid(const Plan& P, size_t lds, int ntasks) {
+  int per_cu = lds > 0 ? (int)(P.lds_limit / lds) : 8;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+  int g = P.n_cu * per_cu;
+  if (g > ntasks) g = ntasks;
+  return (unsigned)(g < 1 ? 1 : g);
 }
 
 template <typename R>
@@ -899,17 +1045,29 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
   hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
   const int32_t* lf = P.t.level_fronts;
   const int32_t* tk = P.t.tasks;
-  for (const LevelPlan& L : P.levels) {
+  const size_t nl = P.levels.size();
+  size_t l = 0;
+  // the small levels at the bottom of the tree: one persistent launch
+  if (P.small_prefix > 0) {
+    const int nf = P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count;
+    const Queue q = make_queue(P, nf * nsys, 1);
+    hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, nf * nsys)),
+                       dim3(kThreads), P.small_lds_prefix, st, a, q, lf);
+    l = P.small_prefix;
+  }
+  for (; l < nl; ++l) {
+    const LevelPlan& L = P.levels[l];
     if (L.small) {
-      hipLaunchKernelGGL(k_front_small<R>, dim3(L.count, nsys), dim3(kThreads), L.small_lds, st, a,
-                         lf + L.first);
+      const Queue q = make_queue(P, L.count * nsys, 0);
+      hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, L.small_lds, L.count * nsys)),
+                         dim3(kThreads), L.small_lds, st, a, q, lf + L.first);
       continue;
     }
     hipLaunchKernelGGL(k_assemble_large<R>, dim3(L.nasm, nsys), dim3(kThreads), 0, st, a,
                        tk + L.asm_off);
     for (const BlockStep& S : L.steps) {
       hipLaunchKernelGGL(k_diag_large<R>, dim3(S.ndiag, nsys), dim3(kThreads),
-                         (size_t)(NB * NB + 2 * NB) * cs, st, a, tk + S.diag_off, S.kb);
+                         (size_t)(2 * NB * NB + 2 * NB) * cs, st, a, tk + S.diag_off, S.kb);
       if (S.ntrsm)
         hipLaunchKernelGGL(k_trsm_large<R>, dim3(S.ntrsm, nsys), dim3(kThreads),
                            (size_t)(NB * NB + 64 * NB + NB) * cs, st, a, tk + S.trsm_off, S.kb);
@@ -921,27 +1079,48 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
   return hipGetLastError();
 }
 
+template <typename R> constexpr int sweep_bw() { return sizeof(R) == 8 ? 32 : 64; }
+
+size_t sweep_lds(const Plan& P, int nrhs, int bw) {
+  return ((size_t)bw * (bw + 1) + (size_t)P.an.max_front * nrhs) * P.csize;
+}
+
+// One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src.
 template <typename R>
 void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
            int accumulate, const int* flag, hipStream_t st) {
-  const int nsys = P.desc.nsys;
-  const int ncols = nsys * nrhs;
-  const size_t cs = P.csize;
-  hipLaunchKernelGGL(k_gather<R>, dim3(grid1d(P.an.N, 1024), ncols), dim3(kThreads), 0, st, a, src,
-                     P.y, nrhs, scale_in, flag);
+  constexpr int BW = sweep_bw<R>();
+  const int nt = P.an.nfronts * P.desc.nsys;
+  const size_t lds = sweep_lds(P, nrhs, BW);
+  SweepArgs w;
+  w.src = src;
+  w.out = dst;
+  w.y = P.y;
+  w.wv = P.wv;
+  w.flag = flag;
+  w.nrhs = nrhs;
+  w.scale_src = scale_in;
+  w.accumulate = accumulate;
   const int32_t* lf = P.t.level_fronts;
-  for (size_t l = 0; l < P.levels.size(); ++l) {
-    const LevelPlan& L = P.levels[l];
-    hipLaunchKernelGGL(k_fwd<R>, dim3(L.count, nsys), dim3(kThreads), (size_t)L.max_m * nrhs * cs, st,
-                       a, lf + L.first, P.y, P.wv, nrhs, flag);
+  const int nsys = P.desc.nsys;
+  if (P.sweep_levels) {
+    // one launch per tree level: kernel boundaries order the levels
+    for (const LevelPlan& L : P.levels) {
+      const int n = L.count * nsys;
+      hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
+                         make_queue(P, n, 0), lf + L.first);
+    }
+    for (size_t l = P.levels.size(); l-- > 0;) {
+      const LevelPlan& L = P.levels[l];
+      const int n = L.count * nsys;
+      hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
+                         make_queue(P, n, 0), lf + L.first);
+    }
+    return;
   }
-  for (size_t l = P.levels.size(); l-- > 0;) {
-    const LevelPlan& L = P.levels[l];
-    hipLaunchKernelGGL(k_bwd<R>, dim3(L.count, nsys), dim3(kThreads),
-                       ((size_t)L.max_m * nrhs + 64 * 65) * cs, st, a, lf + L.first, P.y, nrhs, flag);
-  }
-  hipLaunchKernelGGL(k_scatter<R>, dim3(grid1d(P.an.N, 1024), ncols), dim3(kThreads), 0, st, a, P.y,
-                     dst, nrhs, accumulate, 0, flag);
+  const unsigned g = persistent_grid(P, lds, nt);
+  hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
+  hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
 }
 
 template <typename R>
@@ -954,18 +1133,26 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
   const int* flag = &P.status->ir_flag;
   hipLaunchKernelGGL(k_ir_begin, dim3(1), dim3(1), 0, st, P.status);
   sweep<R>(P, a, rhs, xdst, nrhs, scale, 0, nullptr, st);
+  ResArgs ra;
+  ra.rhs = rhs;
+  ra.x = xdst;
+  ra.res = P.res;
+  ra.partial = P.partial;
+  ra.counter = P.counters + 2;
+  ra.flag = flag;
+  ra.tol = tol;
+  ra.nrhs = nrhs;
+  ra.scale_rhs = scale;
   for (int it = 1; it <= max_ir; ++it) {
-    hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, rhs, xdst,
-                       P.res, P.partial, nrhs, scale, flag);
-    hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(kThreads), 0, st, P.status, P.partial, P.res_blocks,
-                       ncols, tol, it - 1, 0);
+    ra.step = it - 1;
+    ra.last = 0;
+    hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
     sweep<R>(P, a, P.res, xdst, nrhs, 0, 1, flag, st);
   }
   if (max_ir > 0) {
-    hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, rhs, xdst,
-                       P.res, P.partial, nrhs, scale, flag);
-    hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(kThreads), 0, st, P.status, P.partial, P.res_blocks,
-                       ncols, tol, max_ir, 1);
+    ra.step = max_ir;
+    ra.last = 1;
+    hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
   }
   hipLaunchKernelGGL(k_ir_end, dim3(1), dim3(1), 0, st, P.status, mode, max_ir > 0 ? 1 : 0);
   return hipGetLastError();
@@ -973,12 +1160,16 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
 
 template <typename R>
 hipError_t set_lds_limits(int limit) {
+  constexpr int BW = sweep_bw<R>();
   hipError_t e = hipSuccess;
   const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_diag_large<R>,
                        (const void*)k_trsm_large<R>, (const void*)k_update_large<R>,
-                       (const void*)k_fwd<R>, (const void*)k_bwd<R>};
+                       (const void*)k_fwd_sweep<R, BW>, (const void*)k_bwd_sweep<R, BW>};
   for (const void* fn : fns) {
-    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, limit);
+    hipFuncAttributes fa;
+    hipError_t r = hipFuncGetAttributes(&fa, fn);
+    const int dyn = limit - (r == hipSuccess ? (int)fa.sharedSizeBytes : 1024);
+    if (r == hipSuccess) r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (r != hipSuccess && e == hipSuccess) e = r;
   }
   return e;
@@ -988,6 +1179,10 @@ hipError_t set_lds_limits(int limit) {
 
 hipError_t configure_kernels(Plan& P, int lds_limit) {
   return P.is_c64 ? set_lds_limits<float>(lds_limit) : set_lds_limits<double>(lds_limit);
+}
+
+size_t solve_lds_bytes(const Plan& P, int nrhs) {
+  return sweep_lds(P, nrhs, P.is_c64 ? sweep_bw<float>() : sweep_bw<double>());
 }
 
 hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st) {

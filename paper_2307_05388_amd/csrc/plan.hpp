@@ -36,7 +36,7 @@ struct DevTables {
   int32_t *gmap = nullptr, *nbr_row = nullptr;
   int32_t *perm = nullptr, *iperm = nullptr;
   int32_t *level_fronts = nullptr;
-  int32_t *mslot = nullptr;
+  int32_t *mslot = nullptr, *parent = nullptr;
   int64_t *fac_off = nullptr, *upd_off = nullptr, *gmap_ptr = nullptr;
   int32_t *tasks = nullptr;  // task lists of the large-front path
 };
@@ -72,6 +72,12 @@ struct Plan {
   int32_t tile_upd = 64;       // update tile edge
   int32_t nmslot = 0;
   size_t solve_lds_max = 0;
+  int32_t small_prefix = 0;    // leading levels run by one persistent small-front launch
+  size_t small_lds_prefix = 0;
+  int32_t n_cu = 256;
+  size_t lds_limit = 65536;
+  bool sweep_levels = false;    // sweeps as one launch per level instead of one persistent launch
+  bool small_levels = false;    // small fronts as one launch per level
 
   // arenas (device)
   void* fac = nullptr;         // nsys * fac_total scalars
@@ -87,6 +93,9 @@ struct Plan {
   double* partial = nullptr;   // nsys * max_rhs * res_blocks * 2
   int32_t res_blocks = 0;
   DevStatus* status = nullptr;
+  int32_t* counters = nullptr;  // [0..1] persistent-queue counters, [2] residual blocks
+  int32_t* done = nullptr;      // [nsys][nfronts] completion epochs
+  int32_t epoch = 0;            // last epoch handed to a persistent launch
   DevStatus* status_host = nullptr;  // pinned
   int64_t device_bytes = 0;
   std::vector<void*> allocations;
@@ -108,5 +117,7 @@ hipError_t launch_solve(Plan& P, int mode, const double2* rhs, double2* x_out, i
 hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, int32_t nrhs,
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st);
 hipError_t launch_status_reset(Plan& P, hipStream_t st);
+size_t solve_lds_bytes(const Plan& P, int nrhs);
+hipError_t configure_kernels(Plan& P, int lds_limit);
 
 }  // namespace fdfd
