@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--config", default="plain300")
     ap.add_argument("--modes", default="c128,c64")
     ap.add_argument("--max-ir", type=int, default=4)
     ap.add_argument("--ir-tol", type=float, default=1e-10)
@@ -50,11 +50,14 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(args, p, prec, eps_all, b, c, omegas):
+PEAKS = {"hbm": 8000.0, "c128": 78.6, "c64": 157.3}   # GB/s; dense FP64 / FP32 TFLOP/s
+
+
+def run_mode(args, p, prec, eps_all, b, c, omegas, profile=False):
     import torch
     from paper_2307_05388_amd.fdfd import Plan, FDFD_GRAD_SUM_SYSTEMS
 
-    plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=args.leaf)
+    plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=args.leaf, profile=profile)
     max_ir = args.max_ir if prec == "c64" else 0
     tol = args.ir_tol
     grad = torch.empty(p.N, dtype=torch.float64, device=b.device)
@@ -82,6 +85,12 @@ def run_mode(args, p, prec, eps_all, b, c, omegas):
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1) / args.steps
     info = plan.query()
+    if profile:
+        plan.kernel_stats()   # drop the warm-up launches
+        for k in range(args.steps):
+            step(args.warmup + k)
+        torch.cuda.synchronize()
+        info["kernels"] = plan.kernel_stats()
     log(args, prec, f"{ms:.3f} ms/step (wall {1e3 * wall / args.steps:.3f})", info)
     return plan, step, ms, wall, info, grad
 
@@ -157,9 +166,35 @@ def main():
         "analysis": {k: results[best]["info"][k] for k in ("nfronts", "nlevels", "nnz_factor", "refactor_flops",
                                                           "factor_bytes", "leaf")},
     }
+    # roofline of the dominant kernel, from an event-timed pass of the same steps
+    prof_plan, _, prof_ms, _, prof_info, _ = run_mode(args, p, best, eps_all, b, c, omegas, profile=True)
+    prof_plan.close()
+    out["roofline"] = roofline(prof_info["kernels"], best, args.steps)
+    out["kernels"] = {k: {"launches": v["launches"], "ms_per_step": v["total_ms"] / args.steps,
+                          "avg_us": 1e3 * v["total_ms"] / max(1, v["launches"])}
+                      for k, v in prof_info["kernels"].items() if v["launches"]}
+    out["profiled_ms_per_step"] = prof_ms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out))
+
+
+def roofline(stats, prec, steps):
+    """Achieved rate of the kernel with the largest event time: its algorithmic
+    bytes (sweeps, residual) or flops (factorisation) over its summed launch time."""
+    name, k = max(((n, v) for n, v in stats.items() if v["launches"]), key=lambda kv: kv[1]["total_ms"])
+    sec = k["total_ms"] * 1e-3
+    if k["alg_bytes"] > 0:
+        bound, unit, peak = "hbm", "GB/s", PEAKS["hbm"]
+        achieved = k["alg_bytes"] / sec / 1e9
+        per_launch = k["alg_bytes"] / k["launches"]
+    else:
+        bound, unit, peak = "mfma", "TFLOP/s", PEAKS[prec]
+        achieved = k["alg_flops"] / sec / 1e12
+        per_launch = k["alg_flops"] / k["launches"]
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "launches_per_step": k["launches"] / steps,
+            "avg_launch_us": 1e3 * k["total_ms"] / k["launches"], "alg_per_launch": per_launch}
 
 
 def cpu_baseline(p):

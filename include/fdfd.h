@@ -62,6 +62,8 @@ typedef enum {
 /* fdfd_desc.flags */
 #define FDFD_ANALYZE_HOST_ONLY 1  /* symbolic analysis only: no device memory;  */
                                   /* only fdfd_query / fdfd_get_table work     */
+#define FDFD_PROFILE 2            /* bracket every kernel launch with HIP events */
+                                  /* (read with fdfd_kernel_stats)             */
 
 typedef struct {
   int32_t nx, ny;          /* grid cells, nx, ny >= 2                           */
@@ -169,6 +171,26 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info);
 #define FDFD_TABLE_FRONTS 1
 #define FDFD_TABLE_UPDATE 2
 fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t count);
+
+/*
+ * Per-kernel measurement (not part of the method; a measurement aid).  For a
+ * plan analysed with FDFD_PROFILE, every kernel launch is bracketed by a pair
+ * of HIP events on its stream and tagged with the algorithmic work it
+ * performs: factor and vector bytes that must move for the sweeps and the
+ * residual, real flops of the partial LDL^T for the factorisation kernels.
+ * fdfd_kernel_stats synchronises the plan's stream, fills up to max_entries
+ * records (one per kernel, in a fixed order), stores the count in *n_out, and
+ * resets the totals.  Returns FDFD_ERR_STATE for a plan without FDFD_PROFILE.
+ */
+typedef struct {
+  char name[32];        /* kernel name, e.g. "fwd_sweep"                      */
+  int64_t launches;     /* launches since the previous call                   */
+  double total_ms;      /* summed event time of those launches                */
+  double alg_bytes;     /* summed algorithmic bytes (0 if flop-bound)         */
+  double alg_flops;     /* summed algorithmic real flops (0 if byte-bound)    */
+} fdfd_kernel_stat;
+fdfd_status fdfd_kernel_stats(fdfd_plan plan, fdfd_kernel_stat* out, int32_t max_entries,
+                              int32_t* n_out);
 
 /* Static text of a status code. */
 const char* fdfd_status_str(fdfd_status s);

@@ -13,6 +13,42 @@
 #include "analysis.h"
 #include "plan.hpp"
 
+namespace fdfd {
+
+const char* const kKernelClassNames[KC_COUNT] = {"setup",       "front_small", "assemble_large", "diag_large",
+                                                 "trsm_large",  "update_large", "fwd_sweep",     "bwd_sweep",
+                                                 "residual",    "gradient"};
+
+hipEvent_t profile_event(Plan& P) {
+  if (!P.event_pool.empty()) {
+    hipEvent_t e = P.event_pool.back();
+    P.event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Caller has synchronised the stream the events were recorded on.
+void profile_collect(Plan& P) {
+  for (const PendingTiming& t : P.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess) {
+      KernelTotals& k = P.totals[t.cls];
+      k.launches += 1;
+      k.ms += ms;
+      k.bytes += t.bytes;
+      k.flops += t.flops;
+    }
+    P.event_pool.push_back(t.e0);
+    P.event_pool.push_back(t.e1);
+  }
+  P.pending.clear();
+}
+
+}  // namespace fdfd
+
 struct fdfd_plan_s {
   fdfd::Plan p;
 };
@@ -78,6 +114,13 @@ fdfd_status alloc(Plan& P, void** dst, size_t bytes) {
 }
 
 void free_all(Plan& P) {
+  for (const auto& t : P.pending) {
+    (void)hipEventDestroy(t.e0);
+    (void)hipEventDestroy(t.e1);
+  }
+  P.pending.clear();
+  for (hipEvent_t e : P.event_pool) (void)hipEventDestroy(e);
+  P.event_pool.clear();
   for (void* d : P.allocations) (void)hipFree(d);
   P.allocations.clear();
   if (P.status_host) (void)hipHostFree(P.status_host);
@@ -108,6 +151,11 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     }
     L.small = need <= small_cap;
     L.small_lds = need;
+    for (int k = L.first; k < L.first + L.count; ++k) {
+      const int f = A.level_fronts[k];
+      L.lbytes += P.front_lbytes[f];
+      L.asm_bytes += 0.5 * (double)A.m(f) * (A.m(f) + 1) * cs;
+    }
     L.asm_off = 0;
     L.nasm = 0;
     if (!L.small) {
@@ -135,6 +183,11 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
           if (A.npiv[f] > kb) {
             tasks.push_back(f);
             ++S.ndiag;
+            const double nbk = std::min(NB, A.npiv[f] - kb);
+            const double t = A.m(f) - kb - nbk;
+            S.diag_flops += 8.0 * nbk * nbk * nbk / 6.0;
+            S.trsm_flops += 8.0 * t * nbk * nbk / 2.0;
+            S.upd_flops += 8.0 * nbk * t * (t + 1) / 2.0;
           }
         }
         S.trsm_off = (int64_t)tasks.size();
@@ -231,6 +284,16 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     delete h;
     return fail(nullptr, FDFD_ERR_ARG, err);
   }
+  P.front_flops.resize(P.an.nfronts);
+  P.front_lbytes.resize(P.an.nfronts);
+  P.factor_lbytes = 0;
+  for (int f = 0; f < P.an.nfronts; ++f) {
+    const double p = P.an.npiv[f], u = P.an.nupd[f];
+    P.front_flops[f] = 8.0 * (p * p * p + 3.0 * p * p * u + 3.0 * p * u * u) / 6.0;
+    P.front_lbytes[f] = (p * (p + 1) / 2 + u * p) * (double)P.csize;
+    P.factor_lbytes += P.front_lbytes[f];
+  }
+  P.profile = (desc->flags & FDFD_PROFILE) != 0;
   if (P.host_only) {
     *out = h;
     return FDFD_OK;
@@ -468,6 +531,31 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   if (S.ir_failed_solve || S.ir_failed_adj)
     return fail(&P, FDFD_ERR_NUMERIC, "iterative refinement did not reach its tolerance");
   if (S.n_perturbed > 0) return FDFD_WARN_PIVOT;
+  return FDFD_OK;
+}
+
+fdfd_status fdfd_kernel_stats(fdfd_plan plan, fdfd_kernel_stat* out, int32_t max_entries, int32_t* n_out) {
+  if (!plan || !n_out || (!out && max_entries > 0) || max_entries < 0)
+    return fail(nullptr, FDFD_ERR_ARG, "plan and n_out must be non-NULL");
+  Plan& P = plan->p;
+  *n_out = 0;
+  if (!P.profile || P.host_only) return fail(&P, FDFD_ERR_STATE, "plan was not analysed with FDFD_PROFILE");
+  DeviceGuard guard(P.device);
+  hipError_t e = hipStreamSynchronize(P.last_stream);
+  if (e != hipSuccess) return hip_fail(&P, e, "stream synchronise");
+  fdfd::profile_collect(P);
+  int n = 0;
+  for (int c = 0; c < fdfd::KC_COUNT && n < max_entries; ++c, ++n) {
+    fdfd_kernel_stat& k = out[n];
+    std::memset(&k, 0, sizeof(k));
+    std::strncpy(k.name, fdfd::kKernelClassNames[c], sizeof(k.name) - 1);
+    k.launches = P.totals[c].launches;
+    k.total_ms = P.totals[c].ms;
+    k.alg_bytes = P.totals[c].bytes;
+    k.alg_flops = P.totals[c].flops;
+    P.totals[c] = fdfd::KernelTotals();
+  }
+  *n_out = n;
   return FDFD_OK;
 }
 

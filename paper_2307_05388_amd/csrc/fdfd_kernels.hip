@@ -1020,6 +1020,27 @@ Queue make_queue(Plan& P, int ntasks, int wait) {
   return q;
 }
 
+// FDFD_PROFILE: brackets one launch with events and records its algorithmic work.
+struct Prof {
+  Plan& P;
+  hipStream_t st;
+  int cls;
+  double bytes, flops;
+  hipEvent_t e0 = nullptr;
+  Prof(Plan& P_, hipStream_t st_, int cls_, double b, double f) : P(P_), st(st_), cls(cls_), bytes(b), flops(f) {
+    if (P.profile) {
+      e0 = profile_event(P);
+      (void)hipEventRecord(e0, st);
+    }
+  }
+  ~Prof() {
+    if (!e0) return;
+    hipEvent_t e1 = profile_event(P);
+    (void)hipEventRecord(e1, st);
+    P.pending.push_back(PendingTiming{cls, e0, e1, bytes, flops});
+  }
+};
+
 // Workgroups of a persistent launch: enough to fill every CU at the occupancy
 // the LDS footprint allows, never more than the items.
 unsigned persistent_grid(const Plan& P, size_t lds, int ntasks) {
@@ -1038,11 +1059,14 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
   const int NB = P.nb_large;
   Omegas om;
   for (int s = 0; s < kMaxSys; ++s) om.w[s] = s < nsys ? P.omega_host[s] : 0.0;
-  hipLaunchKernelGGL(k_copy_eps, dim3(grid1d(P.an.N, 1024), nsys), dim3(kThreads), 0, st, a, eps,
-                     eps_stride);
-  hipLaunchKernelGGL(k_setup, dim3(nsys), dim3(kThreads), 0, st, a, om, P.desc.npml_x,
-                     P.desc.npml_y);
-  hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
+  {
+    Prof pr(P, st, KC_SETUP, 24.0 * P.an.N * nsys, 0.0);
+    hipLaunchKernelGGL(k_copy_eps, dim3(grid1d(P.an.N, 1024), nsys), dim3(kThreads), 0, st, a, eps,
+                       eps_stride);
+    hipLaunchKernelGGL(k_setup, dim3(nsys), dim3(kThreads), 0, st, a, om, P.desc.npml_x,
+                       P.desc.npml_y);
+    hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
+  }
   const int32_t* lf = P.t.level_fronts;
   const int32_t* tk = P.t.tasks;
   const size_t nl = P.levels.size();
@@ -1051,6 +1075,9 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
   if (P.small_prefix > 0) {
     const int nf = P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count;
     const Queue q = make_queue(P, nf * nsys, 1);
+    double fl = 0.0;
+    for (int k = 0; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+    Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
     hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, nf * nsys)),
                        dim3(kThreads), P.small_lds_prefix, st, a, q, lf);
     l = P.small_prefix;
@@ -1059,21 +1086,34 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
     const LevelPlan& L = P.levels[l];
     if (L.small) {
       const Queue q = make_queue(P, L.count * nsys, 0);
+      double fl = 0.0;
+      for (int k = L.first; k < L.first + L.count; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+      Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
       hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, L.small_lds, L.count * nsys)),
                          dim3(kThreads), L.small_lds, st, a, q, lf + L.first);
       continue;
     }
-    hipLaunchKernelGGL(k_assemble_large<R>, dim3(L.nasm, nsys), dim3(kThreads), 0, st, a,
-                       tk + L.asm_off);
+    {
+      Prof pr(P, st, KC_ASSEMBLE_LARGE, L.asm_bytes * nsys, 0.0);
+      hipLaunchKernelGGL(k_assemble_large<R>, dim3(L.nasm, nsys), dim3(kThreads), 0, st, a,
+                         tk + L.asm_off);
+    }
     for (const BlockStep& S : L.steps) {
-      hipLaunchKernelGGL(k_diag_large<R>, dim3(S.ndiag, nsys), dim3(kThreads),
-                         (size_t)(2 * NB * NB + 2 * NB) * cs, st, a, tk + S.diag_off, S.kb);
-      if (S.ntrsm)
+      {
+        Prof pr(P, st, KC_DIAG_LARGE, 0.0, S.diag_flops * nsys);
+        hipLaunchKernelGGL(k_diag_large<R>, dim3(S.ndiag, nsys), dim3(kThreads),
+                           (size_t)(2 * NB * NB + 2 * NB) * cs, st, a, tk + S.diag_off, S.kb);
+      }
+      if (S.ntrsm) {
+        Prof pr(P, st, KC_TRSM_LARGE, 0.0, S.trsm_flops * nsys);
         hipLaunchKernelGGL(k_trsm_large<R>, dim3(S.ntrsm, nsys), dim3(kThreads),
                            (size_t)(NB * NB + 64 * NB + NB) * cs, st, a, tk + S.trsm_off, S.kb);
-      if (S.nupd)
+      }
+      if (S.nupd) {
+        Prof pr(P, st, KC_UPDATE_LARGE, 0.0, S.upd_flops * nsys);
         hipLaunchKernelGGL(k_update_large<R>, dim3(S.nupd, nsys), dim3(kThreads),
                            (size_t)(2 * NB * 64) * cs, st, a, tk + S.upd_off, S.kb);
+      }
     }
   }
   return hipGetLastError();
@@ -1103,24 +1143,36 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   w.accumulate = accumulate;
   const int32_t* lf = P.t.level_fronts;
   const int nsys = P.desc.nsys;
+  // algorithmic bytes: the lower-trapezoid factor once, the input vector read
+  // in one precision and the output written in another
+  const double vec_bytes = (double)P.an.N * nrhs * nsys * (16.0 + (double)P.csize);
   if (P.sweep_levels) {
     // one launch per tree level: kernel boundaries order the levels
     for (const LevelPlan& L : P.levels) {
       const int n = L.count * nsys;
+      Prof pr(P, st, KC_FWD_SWEEP, L.lbytes * nsys + vec_bytes * L.count / P.an.nfronts, 0.0);
       hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
                          make_queue(P, n, 0), lf + L.first);
     }
     for (size_t l = P.levels.size(); l-- > 0;) {
       const LevelPlan& L = P.levels[l];
       const int n = L.count * nsys;
+      Prof pr(P, st, KC_BWD_SWEEP, L.lbytes * nsys + vec_bytes * L.count / P.an.nfronts, 0.0);
       hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
                          make_queue(P, n, 0), lf + L.first);
     }
     return;
   }
   const unsigned g = persistent_grid(P, lds, nt);
-  hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
-  hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
+  const double fb = P.factor_lbytes * nsys + vec_bytes;
+  {
+    Prof pr(P, st, KC_FWD_SWEEP, fb, 0.0);
+    hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
+  }
+  {
+    Prof pr(P, st, KC_BWD_SWEEP, fb, 0.0);
+    hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
+  }
 }
 
 template <typename R>
@@ -1143,15 +1195,21 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
   ra.tol = tol;
   ra.nrhs = nrhs;
   ra.scale_rhs = scale;
+  // x, b, r (complex128) and eps per cell and column
+  const double rbytes = (double)P.an.N * ncols * (16.0 * 3 + 8.0);
   for (int it = 1; it <= max_ir; ++it) {
     ra.step = it - 1;
     ra.last = 0;
-    hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
+    {
+      Prof pr(P, st, KC_RESIDUAL, rbytes, 0.0);
+      hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
+    }
     sweep<R>(P, a, P.res, xdst, nrhs, 0, 1, flag, st);
   }
   if (max_ir > 0) {
     ra.step = max_ir;
     ra.last = 1;
+    Prof pr(P, st, KC_RESIDUAL, rbytes, 0.0);
     hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
   }
   hipLaunchKernelGGL(k_ir_end, dim3(1), dim3(1), 0, st, P.status, mode, max_ir > 0 ? 1 : 0);
@@ -1200,6 +1258,8 @@ hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, in
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st) {
   const KArgs a = make_args(P);
   const int acc = (flags & FDFD_GRAD_ACCUMULATE) ? 1 : 0;
+  Prof pr(P, st, KC_GRADIENT, (double)P.an.N * P.desc.nsys * (nrhs * 32.0 + (lam_out ? nrhs * 16.0 : 0.0) + 8.0),
+          0.0);
   if (flags & FDFD_GRAD_SUM_SYSTEMS)
     hipLaunchKernelGGL(k_gradient_sum, dim3(grid1d(P.an.N, 1024)), dim3(kThreads), 0, st, a, x, lam_sym,
                        nrhs, lam_out, grad, acc);

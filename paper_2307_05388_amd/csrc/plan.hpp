@@ -47,6 +47,7 @@ struct BlockStep {
   int64_t diag_off;  int32_t ndiag;    // fronts with p > kb (task buffer offsets)
   int64_t trsm_off;  int32_t ntrsm;    // (front, first row) pairs
   int64_t upd_off;   int32_t nupd;     // (front, tile row, tile col) triples
+  double diag_flops = 0, trsm_flops = 0, upd_flops = 0;  // algorithmic work per system
 };
 
 struct LevelPlan {
@@ -56,6 +57,26 @@ struct LevelPlan {
   int64_t asm_off; int32_t nasm;   // assembly tasks (front, c0, c1), large path
   std::vector<BlockStep> steps;
   int32_t max_m, max_p, max_u;
+  double lbytes = 0;           // lower-trapezoid factor bytes of the level (one system)
+  double asm_bytes = 0;        // front entries written by the large-path assembly
+};
+
+// Kernel classes for FDFD_PROFILE timing.
+enum KernelClass {
+  KC_SETUP = 0, KC_FRONT_SMALL, KC_ASSEMBLE_LARGE, KC_DIAG_LARGE, KC_TRSM_LARGE, KC_UPDATE_LARGE,
+  KC_FWD_SWEEP, KC_BWD_SWEEP, KC_RESIDUAL, KC_GRADIENT, KC_COUNT
+};
+extern const char* const kKernelClassNames[KC_COUNT];
+
+struct PendingTiming {
+  int cls;
+  hipEvent_t e0, e1;
+  double bytes, flops;
+};
+
+struct KernelTotals {
+  int64_t launches = 0;
+  double ms = 0.0, bytes = 0.0, flops = 0.0;
 };
 
 struct Plan {
@@ -100,6 +121,16 @@ struct Plan {
   int64_t device_bytes = 0;
   std::vector<void*> allocations;
 
+  // FDFD_PROFILE
+  bool profile = false;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<PendingTiming> pending;
+  KernelTotals totals[KC_COUNT];
+  // per-front algorithmic figures (host)
+  std::vector<double> front_flops;   // real flops of the front's partial LDL^T
+  std::vector<double> front_lbytes;  // bytes of the lower-trapezoid factor
+  double factor_lbytes = 0;          // sum of front_lbytes (one system)
+
   hipStream_t last_stream = nullptr;
   std::vector<double> omega_host;
   bool factored = false;
@@ -118,6 +149,9 @@ hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, in
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st);
 hipError_t launch_status_reset(Plan& P, hipStream_t st);
 size_t solve_lds_bytes(const Plan& P, int nrhs);
+// FDFD_PROFILE helpers (fdfd_api.cpp)
+hipEvent_t profile_event(Plan& P);
+void profile_collect(Plan& P);
 hipError_t configure_kernels(Plan& P, int lds_limit);
 
 }  // namespace fdfd

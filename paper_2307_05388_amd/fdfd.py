@@ -18,11 +18,12 @@ LIB_PATH = os.path.join(_PKG, "libfdfd.so")
 FDFD_OK, FDFD_ERR_ARG, FDFD_ERR_STATE, FDFD_ERR_NOMEM, FDFD_ERR_HIP, FDFD_ERR_NUMERIC, FDFD_WARN_PIVOT = range(7)
 FDFD_C128, FDFD_C64_IR = 0, 1
 FDFD_ANALYZE_HOST_ONLY = 1
+FDFD_PROFILE = 2
 FDFD_GRAD_ACCUMULATE, FDFD_GRAD_SUM_SYSTEMS = 1, 2
 FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE = 0, 1, 2
 
 EXPORTED = ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_adjoint_grad", "fdfd_query",
-            "fdfd_get_table", "fdfd_status_str", "fdfd_last_error", "fdfd_destroy"]
+            "fdfd_kernel_stats", "fdfd_get_table", "fdfd_status_str", "fdfd_last_error", "fdfd_destroy"]
 
 
 class Desc(ctypes.Structure):
@@ -45,6 +46,11 @@ class Info(ctypes.Structure):
                 ("ir_steps_solve", ctypes.c_int32), ("ir_steps_adjoint", ctypes.c_int32),
                 ("rel_residual_solve", ctypes.c_double), ("rel_residual_adjoint", ctypes.c_double),
                 ("device_flags", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("alg_flops", ctypes.c_double)]
 
 
 class FDFDError(RuntimeError):
@@ -76,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdfd_adjoint_grad.argtypes = [vp, vp, vp, i32, i32, dbl, vp, vp, i32, vp]
     lib.fdfd_query.argtypes = [vp, ctypes.POINTER(Info)]
     lib.fdfd_get_table.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), i64]
+    lib.fdfd_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
     lib.fdfd_status_str.argtypes = [i32]
     lib.fdfd_status_str.restype = ctypes.c_char_p
     lib.fdfd_last_error.argtypes = [vp]
@@ -83,7 +90,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdfd_destroy.argtypes = [vp]
     lib.fdfd_destroy.restype = None
     for name in ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_adjoint_grad",
-                 "fdfd_query", "fdfd_get_table"]:
+                 "fdfd_query", "fdfd_get_table", "fdfd_kernel_stats"]:
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -114,12 +121,13 @@ class Plan:
     """Cached analysis + factors of one grid (all systems share the pattern)."""
 
     def __init__(self, nx, ny, npml_x, npml_y=None, nsys=1, max_rhs=1, prec="c128",
-                 device=-1, leaf=0, host_only=False, mem_cap_bytes=0):
+                 device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False):
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         d = Desc(nx=nx, ny=ny, npml_x=npml_x, npml_y=npml_x if npml_y is None else npml_y,
                  nsys=nsys, max_rhs=max_rhs, prec=FDFD_C64_IR if prec in ("c64", FDFD_C64_IR) else FDFD_C128,
-                 device=device, leaf=leaf, flags=FDFD_ANALYZE_HOST_ONLY if host_only else 0,
+                 device=device, leaf=leaf,
+                 flags=(FDFD_ANALYZE_HOST_ONLY if host_only else 0) | (FDFD_PROFILE if profile else 0),
                  mem_cap_bytes=mem_cap_bytes)
         if prec not in ("c64", "c128", FDFD_C64_IR, FDFD_C128):
             raise ValueError(f"unknown precision {prec!r}")
@@ -192,6 +200,15 @@ class Plan:
         if st not in (FDFD_OK, FDFD_WARN_PIVOT):
             out["error"] = self._lib.fdfd_last_error(self._h).decode()
         return out
+
+    def kernel_stats(self):
+        """Per-kernel event totals since the last call (plans made with profile=True)."""
+        buf = (KernelStat * 32)()
+        n = ctypes.c_int32()
+        self._check(self._lib.fdfd_kernel_stats(self._h, buf, 32, ctypes.byref(n)))
+        return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                                       "alg_bytes": buf[i].alg_bytes, "alg_flops": buf[i].alg_flops}
+                for i in range(n.value)}
 
     def table(self, which):
         info = self.query() if self.host_only else None

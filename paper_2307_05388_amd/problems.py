@@ -88,40 +88,39 @@ def _centred_rows(ny: int, width: int) -> tuple:
 def make_problem(name: str) -> Problem:
     """The five synthetic workloads (small case, plain method, differentiation,
     batched multiplexer, large footprint)."""
-    name = name.upper()
-    if name == "C1":
+    if name == "small60":
         # 60x60 with 10-cell PML, dx = 50 nm, lambda = 1.55 um; 10-cell strip,
         # 20x20 design block, unit line source at x = 15.
-        return Problem("C1", 60, 60, 10, 50.0, (1.55,),
+        return Problem("small60", 60, 60, 10, 50.0, (1.55,),
                        strips=((0, 60, 25, 35),), design=(20, 40, 20, 40),
                        src_col=15, src_profiles=("line",), obj_col=45,
                        width_cells=5.0, iterations=1,
                        description="60x60, 10-cell PML, dx=50nm, lambda=1.55um, complex128")
-    if name == "C2":
+    if name == "plain300":
         r = _centred_rows(300, 12)
-        return Problem("C2", 300, 300, 20, 40.0, (1.55,),
+        return Problem("plain300", 300, 300, 20, 40.0, (1.55,),
                        strips=((0, 300) + r,), design=(100, 200, 100, 200),
                        src_col=25, src_profiles=("line",), obj_col=275,
                        width_cells=6.0, iterations=20,
                        description="300x300 (N=90,000), 20-cell PML, dx=40nm, 100x100 design re-drawn each step")
-    if name == "C3":
+    if name == "diff500":
         r = _centred_rows(500, 12)
-        return Problem("C3", 500, 500, 20, 40.0, (1.55,),
+        return Problem("diff500", 500, 500, 20, 40.0, (1.55,),
                        strips=((0, 175) + r, (325, 500) + r), design=(175, 325, 175, 325),
                        src_col=25, src_profiles=("gauss",), obj_col=475,
                        width_cells=6.0, iterations=1,
                        description="500x500 (N=250,000), 150x150 design, in/out strip guides")
-    if name == "C4":
+    if name == "mux400":
         r = _centred_rows(400, 12)
         lams = tuple(float(v) for v in np.linspace(1.50, 1.60, 8))
-        return Problem("C4", 400, 400, 20, 40.0, lams,
+        return Problem("mux400", 400, 400, 20, 40.0, lams,
                        strips=((0, 140) + r, (260, 400) + r), design=(140, 260, 140, 260),
                        src_col=25, src_profiles=("gauss", "alt_gauss"), obj_col=375,
                        width_cells=6.0, iterations=1,
                        description="400x400, 8 wavelengths 1.50-1.60um x 2 source profiles")
-    if name == "C5":
+    if name == "large2000":
         r = _centred_rows(2000, 12)
-        return Problem("C5", 2000, 2000, 40, 40.0, (1.55,),
+        return Problem("large2000", 2000, 2000, 40, 40.0, (1.55,),
                        strips=((0, 2000) + r,), design=(200, 1800, 200, 1800),
                        src_col=45, src_profiles=("line",), obj_col=1955,
                        width_cells=6.0, iterations=10,
@@ -132,7 +131,7 @@ def make_problem(name: str) -> Problem:
 def custom_problem(nx: int, ny: int, npml: int, dx_nm: float = 50.0,
                    wavelengths_um=(1.55,), design=None, src_profiles=("line",),
                    name: str = "custom") -> Problem:
-    """A small problem of the same structure as C1, for tests at arbitrary sizes."""
+    """A small problem of the same structure as the 60x60 case, for tests at any size."""
     if design is None:
         di = max(1, nx // 3)
         dj = max(1, ny // 3)

@@ -51,16 +51,16 @@ def test_c128_forward_adjoint_gradient(oracle, nx, ny, npml, leaf, small_lds):
     plan.close()
 
 
-def test_c1_full_iteration_c128(oracle):
-    """C1 (60x60, N = 3600): one factorisation + forward + adjoint in complex128."""
-    p = P.make_problem("C1")
+def test_small60_full_iteration_c128(oracle):
+    """60x60 grid (N = 3600): one factorisation + forward + adjoint in complex128."""
+    p = P.make_problem("small60")
     eps = P.design_eps(p)
     b = P.sources(p)
     c = P.objective_vector(p)
     plan = make_plan(p, "c128")
     out = gpu_iteration(plan, p, eps, b, c=c, max_ir=1, tol=1e-14)
     ref = _oracle(oracle, p, eps, b, c=c)
-    say("C1 rel x", rel(out["x"], ref["x"]), "grad", rel(out["grad"], ref["grad"]), out["info"])
+    say("60x60 rel x", rel(out["x"], ref["x"]), "grad", rel(out["grad"], ref["grad"]), out["info"])
     assert rel(out["x"], ref["x"]) < 1e-10
     assert rel(out["grad"], ref["grad"]) < 1e-9
     assert out["info"]["rel_residual_solve"] < 1e-10

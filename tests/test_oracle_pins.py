@@ -137,7 +137,7 @@ def test_pml_absorbs_better_when_thicker(oracle):
 
 def test_reciprocity_algebraic(oracle):
     """g^T A^-1 b = (A^-T g)^T b: the transposed solve of Eq. (6) is consistent."""
-    p = P.make_problem("C1")
+    p = P.make_problem("small60")
     coef = _coef(oracle, p)
     lu = oracle.BandLU(oracle.band_matrix(coef))
     ba, bb = P.random_complex((2, p.N), seed=5)
@@ -150,7 +150,7 @@ def test_reciprocity_point_sources(oracle):
     """Lorentz reciprocity: outside the PML, the field at b from a unit point
     source at a equals the field at a from a unit source at b.  With a point in
     the PML the S-weighted form x_a[b]/S_a = x_b[a]/S_b holds instead."""
-    p = P.make_problem("C1")
+    p = P.make_problem("small60")
     om = P.omegas(p)[0]
     coef = _coef(oracle, p)
     lu = oracle.BandLU(oracle.band_matrix(coef))
@@ -199,8 +199,8 @@ def test_gradient_matches_finite_differences_small(oracle):
     assert np.abs(g_ad - g_fd).max() <= 1e-5 * np.abs(g_fd).max()
 
 
-def test_gradient_matches_finite_differences_c1(oracle):
-    p = P.make_problem("C1")
+def test_gradient_matches_finite_differences_small60(oracle):
+    p = P.make_problem("small60")
     pixels = P.fd_pixels(p, 32)
     g_ad, g_fd = _fd_check(oracle, p, pixels)
     assert np.linalg.norm(g_ad - g_fd) / np.linalg.norm(g_fd) < 1e-6
