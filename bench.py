@@ -99,7 +99,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
-                                   "note only (see DESIGN.md), so --gpus must be 1"}))
+                                   "note only, so --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2307_05388_amd import problems as P

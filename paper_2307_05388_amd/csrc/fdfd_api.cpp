@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -15,9 +16,8 @@
 
 namespace fdfd {
 
-const char* const kKernelClassNames[KC_COUNT] = {"setup",       "front_small", "assemble_large", "diag_large",
-                                                 "trsm_large",  "update_large", "fwd_sweep",     "bwd_sweep",
-                                                 "residual",    "gradient"};
+const char* const kKernelClassNames[KC_COUNT] = {"setup",     "front_small", "large_tiles", "fwd_sweep",
+                                                 "bwd_sweep", "residual",    "gradient"};
 
 hipEvent_t profile_event(Plan& P) {
   if (!P.event_pool.empty()) {
@@ -127,15 +127,16 @@ void free_all(Plan& P) {
   P.status_host = nullptr;
 }
 
-// Level schedule: fused small-front kernel where the panel fits the LDS budget,
-// else the blocked multi-workgroup path with precomputed task lists.
-void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std::vector<int32_t>& mslot) {
+// Level schedule: the bottom levels whose panels fit the LDS budget run in the
+// one-workgroup-per-front kernel; every level above them runs in the tile task
+// graph, whose task list (topological: level, assembly, then block steps) is
+// built here.
+void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std::vector<int32_t>& tile_base,
+                    std::vector<int32_t>& is_tiled) {
   const fdfd::Analysis& A = P.an;
-  const int NB = P.nb_large;
   const size_t cs = P.csize;
-  mslot.assign(A.nfronts, 0);
+  const int T = 64;
   P.levels.clear();
-  P.nmslot = 0;
   for (int l = 0; l < A.nlevels; ++l) {
     fdfd::LevelPlan L;
     L.first = A.level_ptr[l];
@@ -147,79 +148,12 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       L.max_m = std::max(L.max_m, A.m(f));
       L.max_p = std::max(L.max_p, A.npiv[f]);
       L.max_u = std::max(L.max_u, A.nupd[f]);
-      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f]) * cs);
-    }
-    L.small = need <= small_cap;
-    L.small_lds = need;
-    for (int k = L.first; k < L.first + L.count; ++k) {
-      const int f = A.level_fronts[k];
+      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f] + 256) * cs);
       L.lbytes += P.front_lbytes[f];
-      L.asm_bytes += 0.5 * (double)A.m(f) * (A.m(f) + 1) * cs;
     }
-    L.asm_off = 0;
-    L.nasm = 0;
-    if (!L.small) {
-      L.asm_off = (int64_t)tasks.size();
-      for (int k = L.first; k < L.first + L.count; ++k) {
-        const int f = A.level_fronts[k];
-        const int m = A.m(f);
-        const int cw = std::max(1, 4096 / m);
-        for (int c0 = 0; c0 < m; c0 += cw) {
-          tasks.push_back(f);
-          tasks.push_back(c0);
-          tasks.push_back(std::min(m, c0 + cw));
-          ++L.nasm;
-        }
-        mslot[f] = P.nmslot++;
-      }
-      for (int kb = 0; kb < L.max_p; kb += NB) {
-        fdfd::BlockStep S;
-        S.kb = kb;
-        S.nb = NB;
-        S.diag_off = (int64_t)tasks.size();
-        S.ndiag = 0;
-        for (int k = L.first; k < L.first + L.count; ++k) {
-          const int f = A.level_fronts[k];
-          if (A.npiv[f] > kb) {
-            tasks.push_back(f);
-            ++S.ndiag;
-            const double nbk = std::min(NB, A.npiv[f] - kb);
-            const double t = A.m(f) - kb - nbk;
-            S.diag_flops += 8.0 * nbk * nbk * nbk / 6.0;
-            S.trsm_flops += 8.0 * t * nbk * nbk / 2.0;
-            S.upd_flops += 8.0 * nbk * t * (t + 1) / 2.0;
-          }
-        }
-        S.trsm_off = (int64_t)tasks.size();
-        S.ntrsm = 0;
-        for (int k = L.first; k < L.first + L.count; ++k) {
-          const int f = A.level_fronts[k];
-          if (A.npiv[f] <= kb) continue;
-          const int nbk = std::min(NB, A.npiv[f] - kb);
-          for (int r0 = kb + nbk; r0 < A.m(f); r0 += 64) {
-            tasks.push_back(f);
-            tasks.push_back(r0);
-            ++S.ntrsm;
-          }
-        }
-        S.upd_off = (int64_t)tasks.size();
-        S.nupd = 0;
-        for (int k = L.first; k < L.first + L.count; ++k) {
-          const int f = A.level_fronts[k];
-          if (A.npiv[f] <= kb) continue;
-          const int nbk = std::min(NB, A.npiv[f] - kb);
-          const int t0 = kb + nbk, m = A.m(f);
-          for (int c0 = t0; c0 < m; c0 += 64)
-            for (int r0 = c0; r0 < m; r0 += 64) {
-              tasks.push_back(f);
-              tasks.push_back(r0);
-              tasks.push_back(c0);
-              ++S.nupd;
-            }
-        }
-        L.steps.push_back(S);
-      }
-    }
+    // the one-workgroup kernel keeps at most 64 pivot columns (16 per wave)
+    L.small = need <= small_cap && L.max_p <= 64;
+    L.small_lds = need;
     P.levels.push_back(L);
   }
   P.small_prefix = 0;
@@ -228,6 +162,53 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     P.small_lds_prefix = std::max(P.small_lds_prefix, P.levels[P.small_prefix].small_lds);
     ++P.small_prefix;
   }
+  tasks.clear();
+  tile_base.assign(A.nfronts, 0);
+  is_tiled.assign(A.nfronts, 0);
+  P.ntiles = 0;
+  P.tiled_flops = 0;
+  auto push = [&](int type, int f, int k, int I, int J) {
+    tasks.push_back(type);
+    tasks.push_back(f);
+    tasks.push_back(k);
+    tasks.push_back(I);
+    tasks.push_back(J);
+  };
+  for (int l = P.small_prefix; l < (int)P.levels.size(); ++l) {
+    const fdfd::LevelPlan& L = P.levels[l];
+    int kmax = 0;
+    for (int q = L.first; q < L.first + L.count; ++q) {
+      const int f = A.level_fronts[q];
+      const int nbk = (A.npiv[f] + T - 1) / T, nut = (A.nupd[f] + T - 1) / T, R = nbk + nut;
+      is_tiled[f] = 1;
+      tile_base[f] = P.ntiles;
+      P.ntiles += R * (R + 1) / 2;
+      P.tiled_flops += P.front_flops[f];
+      kmax = std::max(kmax, nbk);
+      for (int I = 0; I < R; ++I)
+        for (int J = 0; J <= I; ++J) push(0, f, 0, I, J);
+    }
+    for (int k = 0; k < kmax; ++k) {
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int f = A.level_fronts[q];
+        if ((A.npiv[f] + T - 1) / T > k) push(1, f, k, k, k);
+      }
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int f = A.level_fronts[q];
+        const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
+        if (nbk <= k) continue;
+        for (int I = k + 1; I < R; ++I) push(2, f, k, I, k);
+      }
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int f = A.level_fronts[q];
+        const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
+        if (nbk <= k) continue;
+        for (int J = k + 1; J < R; ++J)
+          for (int I = J; I < R; ++I) push(3, f, k, I, J);
+      }
+    }
+  }
+  P.ntile_tasks = (int32_t)(tasks.size() / 5);
 }
 
 fdfd_status check_desc(const fdfd_desc* d) {
@@ -318,10 +299,11 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.n_cu = ncu > 0 ? ncu : 256;
   P.lds_limit = (size_t)lds_limit;
   const size_t cs = P.csize;
-  P.nb_large = 64;
-  while (P.nb_large > 16 && ((size_t)(2 * P.nb_large * P.nb_large + 65 * P.nb_large) * cs > (size_t)lds_limit - 512 ||
-                             (size_t)(2 * P.nb_large * 64) * cs > (size_t)lds_limit - 512))
-    P.nb_large /= 2;
+  // the tile kernels need the diagonal task's 64 x 64 block in LDS
+  if ((size_t)(64 * 64 + 2 * 64 + 256) * cs > (size_t)lds_limit - 512) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_HIP, "device LDS too small for 64-wide front blocks");
+  }
   size_t small_cap = (size_t)env_int("FDFD_SMALL_LDS", 65536);
   // a few hundred bytes stay free for the kernels' static LDS
   const size_t lds_dyn = (size_t)lds_limit - 512;
@@ -329,8 +311,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
 
   P.sweep_levels = env_int("FDFD_SWEEP_LEVELS", 0) != 0;
   P.small_levels = env_int("FDFD_SMALL_LEVELS", 0) != 0;
-  std::vector<int32_t> tasks, mslot;
-  build_schedule(P, small_cap, tasks, mslot);
+  std::vector<int32_t> tasks, tile_base, is_tiled;
+  build_schedule(P, small_cap, tasks, tile_base, is_tiled);
   if (P.small_levels) P.small_prefix = 0;
   const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
   if (max_solve_lds > lds_dyn) {
@@ -342,9 +324,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   const int64_t N = P.an.N, nsys = desc->nsys, R = desc->max_rhs;
   const int64_t sum_u = P.an.upd_ptr.back();
   P.res_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
-  const int64_t NB = P.nb_large;
   const int64_t need = nsys * P.an.fac_total * (int64_t)cs + nsys * P.an.upd_total * (int64_t)cs +
-                       nsys * std::max<int64_t>(1, P.nmslot) * NB * NB * (int64_t)cs +
+                       nsys * (int64_t)P.ntiles * 4 + nsys * (int64_t)P.an.nfronts * 4 +
                        nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16 + nsys * 8 + nsys * N * 8 +
                        nsys * R * N * (int64_t)cs + nsys * R * sum_u * (int64_t)cs + 2 * nsys * R * N * 16 +
                        nsys * R * P.res_blocks * 16 + (int64_t)sizeof(fdfd::DevStatus);
@@ -374,15 +355,18 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(upload(P, &P.t.perm, A.perm));
     TRY(upload(P, &P.t.iperm, A.iperm));
     TRY(upload(P, &P.t.level_fronts, A.level_fronts));
-    TRY(upload(P, &P.t.mslot, mslot));
+    TRY(upload(P, &P.t.tile_tasks, tasks));
+    P.tile_tasks_host = tasks;
+    TRY(upload(P, &P.t.tile_base, tile_base));
+    TRY(upload(P, &P.t.is_tiled, is_tiled));
     TRY(upload(P, &P.t.parent, A.parent));
     TRY(upload(P, &P.t.fac_off, A.fac_off));
     TRY(upload(P, &P.t.upd_off, A.upd_off));
     TRY(upload(P, &P.t.gmap_ptr, A.gmap_ptr));
-    TRY(upload(P, &P.t.tasks, tasks));
     TRY(alloc(P, &P.fac, nsys * A.fac_total * cs));
     TRY(alloc(P, &P.upd, nsys * A.upd_total * cs));
-    TRY(alloc(P, &P.mscr, nsys * std::max<int64_t>(1, P.nmslot) * NB * NB * cs));
+    TRY(alloc(P, (void**)&P.tile_state, nsys * (int64_t)std::max(1, P.ntiles) * 4));
+    TRY(alloc(P, (void**)&P.tile_done, nsys * (int64_t)A.nfronts * 4));
     TRY(alloc(P, (void**)&P.pml, nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16));
     TRY(alloc(P, (void**)&P.omega, nsys * 8));
     TRY(alloc(P, (void**)&P.eps, nsys * N * 8));
@@ -400,6 +384,17 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     if (e != hipSuccess) {
       st = hip_fail(&P, e, "hipMemset");
       goto bad;
+    }
+    if (const char* tp = std::getenv("FDFD_TRACE")) {
+      // task traces for performance analysis: written to this file by fdfd_query
+      P.trace_path = tp;
+      const int nsm = (P.small_prefix > 0 ? P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count
+                                          : 0) * (int)nsys;
+      const int caps[4] = {nsm, P.ntile_tasks * (int)nsys, A.nfronts * (int)nsys, A.nfronts * (int)nsys};
+      for (int k = 0; k < 4; ++k) {
+        P.trace_cap[k] = caps[k];
+        if (caps[k] > 0) TRY(alloc(P, (void**)&P.trace_buf[k], (size_t)caps[k] * 4 * sizeof(long long)));
+      }
     }
     e = hipHostMalloc((void**)&P.status_host, sizeof(fdfd::DevStatus), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -526,6 +521,31 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   info->rel_residual_adjoint = S.rel_adj;
   info->device_flags = (S.nonfinite ? 1 : 0) | (S.ir_failed_solve ? 2 : 0) | (S.ir_failed_adj ? 4 : 0) |
                        (S.spin_timeout ? 8 : 0);
+  if (!P.trace_path.empty()) {
+    FILE* fp = std::fopen(P.trace_path.c_str(), "w");
+    if (fp) {
+      for (int k = 0; k < 4; ++k) {
+        if (!P.trace_buf[k] || P.trace_n[k] == 0) continue;
+        std::vector<long long> tr((size_t)P.trace_n[k] * 4);
+        if (hipMemcpy(tr.data(), P.trace_buf[k], tr.size() * sizeof(long long), hipMemcpyDeviceToHost) != hipSuccess)
+          continue;
+        const int ns = P.desc.nsys;
+        for (int t = 0; t < P.trace_n[k]; ++t) {
+          // item: tile task record (type front k I J) for the tile graph, else the front
+          int it[5] = {-1, -1, -1, -1, -1};
+          if (k == 1) {
+            for (int q = 0; q < 5; ++q) it[q] = P.tile_tasks_host[5 * (t / ns) + q];
+          } else {
+            const int pos = t / ns;
+            it[1] = A.level_fronts[k == 3 ? A.nfronts - 1 - pos : pos];
+          }
+          std::fprintf(fp, "%d %d %lld %lld %lld %lld %d %d %d %d %d\n", k, t, tr[4 * t], tr[4 * t + 1],
+                       tr[4 * t + 2], tr[4 * t + 3], it[0], it[1], it[2], it[3], it[4]);
+        }
+      }
+      std::fclose(fp);
+    }
+  }
   if (S.nonfinite) return fail(&P, FDFD_ERR_NUMERIC, "non-finite value in the factor or residual");
   if (S.spin_timeout) return fail(&P, FDFD_ERR_NUMERIC, "a device dependency wait timed out");
   if (S.ir_failed_solve || S.ir_failed_adj)

@@ -15,6 +15,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxSys = 64;
+constexpr int kBW = 64;  // diagonal-block width shared by the factor layout and the sweeps
 
 template <typename R> struct Cx;
 template <> struct Cx<float> { typedef float2 T; };
@@ -64,7 +65,7 @@ __device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_doub
 // Everything a kernel needs about the plan, passed by value.
 struct KArgs {
   const int32_t *pbeg, *npiv, *nupd, *child_ptr, *child_list, *upd_ptr, *upd_idx;
-  const int32_t *gmap, *nbr_row, *perm, *iperm, *mslot, *parent;
+  const int32_t *gmap, *nbr_row, *perm, *iperm, *parent;
   const int64_t *fac_off, *upd_off, *gmap_ptr;
   int32_t nx, ny, N, nsys;
   int64_t fac_total, upd_total, sum_u;
@@ -73,10 +74,9 @@ struct KArgs {
   const double* omega;
   void* fac;
   void* upd;
-  void* mscr;
   DevStatus* st;
   double tau;
-  int32_t nb, nmslot, nfronts;
+  int32_t nfronts;
 };
 
 // ---------------------------------------------------------------------------
@@ -266,14 +266,22 @@ struct Queue {
   int32_t* counter;  // [0] next item, [1] workgroups that have left
   int32_t* done;     // [nsys][nfronts] epoch of the last completion
   DevStatus* st;
+  long long* trace;  // optional: per item claim / ready / finish times and workgroup
   int32_t epoch, ntasks, wait;
 };
+
+__device__ __forceinline__ void trace_mark(const Queue& q, int t, int slot) {
+  if (q.trace && threadIdx.x == 0 && t < q.ntasks) q.trace[4 * (int64_t)t + slot] = (long long)wall_clock64();
+}
 
 __device__ __forceinline__ int claim(const Queue& q, int* sh) {
   __syncthreads();
   if (threadIdx.x == 0) *sh = atomicAdd(&q.counter[0], 1);
   __syncthreads();
-  return *sh;
+  const int t = *sh;
+  trace_mark(q, t, 0);
+  if (q.trace && threadIdx.x == 0 && t < q.ntasks) q.trace[4 * (int64_t)t + 3] = blockIdx.x;
+  return t;
 }
 
 __device__ __forceinline__ void leave(const Queue& q) {
@@ -324,9 +332,193 @@ __device__ __forceinline__ void publish(const Queue& q, int64_t idx) {
 }
 
 // ---------------------------------------------------------------------------
+// Dense building blocks on LDS-resident, column-major panels (leading
+// dimension ld).  Wave w takes columns w, w+4, ...; lane l takes rows l, l+64,
+// ... so no index arithmetic needs a division.
+// ---------------------------------------------------------------------------
+
+template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
+  v.x = __shfl(v.x, lane);
+  v.y = __shfl(v.y, lane);
+  return v;
+}
+
+// LDL^T of the b x b (b <= 16) diagonal sub-block at (o, o), by wave 0 alone:
+// lane l holds row l in registers and the pivot column travels by shuffles,
+// so no barrier is needed.  Leaves the unit-lower L (scaled) in place and
+// d, 1/d in dd / invd; lane 0 keeps the pivot statistics.
+template <typename C>
+__device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, double thr, double anorm, int& npert,
+                          double& minr, int& nonfin) {
+  const int l = threadIdx.x;
+  C row[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) row[q] = (l < b && q < b && q <= l) ? F[(o + q) * ld + o + l] : czero<C>();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < b) {
+      int np = 0, nf = 0;
+      double mr = INFINITY;
+      const C d = fix_pivot(shfl_c(row[k], k), thr, anorm, np, mr, nf);
+      const C inv = cinv(d);
+      if (l == 0) {
+        npert += np;
+        minr = fmin(minr, mr);
+        nonfin |= nf;
+        dd[o + k] = d;
+        invd[o + k] = inv;
+      }
+      const C lk = cmul(row[k], inv);
+#pragma unroll
+      for (int j = k + 1; j < 16; ++j) {
+        const C fjk = shfl_c(row[k], j);
+        if (j < b && l >= j) row[j] = cfms(row[j], lk, fjk);
+      }
+      if (l > k) row[k] = lk;
+    }
+  }
+  if (l < b) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < l) F[(o + q) * ld + o + l] = row[q];
+  }
+}
+
+// Rows r in [r0, m) of the sub-block's columns: L_r = F_r L_ss^-T D^-1 by
+// forward substitution, one row per thread.
+template <typename C>
+__device__ void trsm_rows16(C* F, int ld, int o, int b, int r0, int m, const C* invd) {
+  for (int r = r0 + (int)threadIdx.x; r < m; r += kThreads) {
+    C y[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j < b) {
+        C v = F[(o + j) * ld + r];
+#pragma unroll
+        for (int q = 0; q < j; ++q) v = cfms(v, y[q], F[(o + q) * ld + o + j]);
+        y[j] = v;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < b) F[(o + j) * ld + r] = cmul(y[j], invd[o + j]);
+  }
+}
+
+// Trailing update of the panel columns c in [c0, p), rows r >= c:
+// F[r][c] -= sum_q L[r][o+q] d_q L[c][o+q].  Wave w takes columns c0+w, c0+w+4, ...
+template <typename C>
+__device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const C* dd) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = c0 + wave; c < p; c += 4) {
+    C lc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lc[q] = q < b ? cmul(F[(o + q) * ld + c], dd[o + q]) : czero<C>();
+    for (int r = c + lane; r < m; r += 64) {
+      C acc = F[c * ld + r];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q < b) acc = cfms(acc, F[(o + q) * ld + r], lc[q]);
+      F[c * ld + r] = acc;
+    }
+  }
+}
+
+// Blocked right-looking LDL^T of the first p (<= 64) columns of an m-row LDS
+// panel: per 16-column sub-block, wave 0 factors the diagonal sub-block, all
+// threads solve the rows below it and update the remaining panel columns.
+// Leaves the unit-lower L in place and d, 1/d in dd / invd.
+template <typename C>
+__device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, double thr, double anorm, int& npert,
+                            double& minr, int& nonfin) {
+  for (int o = 0; o < p; o += 16) {
+    const int b = min(16, p - o);
+    if (threadIdx.x < 64) ldl_sub16(F, ld, o, b, dd, invd, thr, anorm, npert, minr, nonfin);
+    __syncthreads();
+    trsm_rows16(F, ld, o, b, o + b, m, invd);
+    __syncthreads();
+    if (o + b < p) {
+      trail16(F, ld, o, b, o + b, p, m, dd);
+      __syncthreads();
+    }
+  }
+}
+
+// In-place inverse of the unit-lower nb x nb (nb <= 64) block at F: each wave
+// inverts one 16 x 16 diagonal sub-block (lane j builds column j), then the
+// off-diagonal sub-blocks follow in ascending block columns and rows,
+// X_ij = -X_ii sum_{j<=k<i} L_ik X_kj, through the 16 x 16 scratch T.
+template <typename C>
+__device__ void invert_blocked(C* F, int ld, int nb, C* T) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nsb = (nb + 15) / 16;
+  if (wave < nsb) {
+    const int o = 16 * wave, b = min(16, nb - o), j = lane;
+    C x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      C v = czero<C>();
+      if (i == j) {
+        v.x = 1;
+      } else if (i > j && i < b) {
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+          if (k >= j) v = cfms(v, F[(o + k) * ld + o + i], x[k]);
+      }
+      x[i] = v;
+    }
+    if (j < b) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i > j && i < b) F[(o + j) * ld + o + i] = x[i];
+    }
+  }
+  __syncthreads();
+  const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+  for (int jb = 0; jb + 1 < nsb; ++jb) {
+    for (int ib = jb + 1; ib < nsb; ++ib) {
+      const int ri = 16 * ib, cj = 16 * jb, bi = min(16, nb - ri), bj = min(16, nb - cj);
+      if (r < bi && c < bj) {
+        C acc = czero<C>();
+        for (int kb = jb; kb < ib; ++kb) {
+          const int rk = 16 * kb, bk = min(16, nb - rk);
+          for (int q = 0; q < bk; ++q) {
+            C xv;
+            if (kb == jb) {
+              if (q < c) continue;
+              if (q == c) {
+                xv = czero<C>();
+                xv.x = 1;
+              } else {
+                xv = F[(cj + c) * ld + rk + q];
+              }
+            } else {
+              xv = F[(cj + c) * ld + rk + q];
+            }
+            acc = cadd(acc, cmul(F[(rk + q) * ld + ri + r], xv));
+          }
+        }
+        T[r * 16 + c] = acc;
+      }
+      __syncthreads();
+      if (r < bi && c < bj) {
+        C v = T[r * 16 + c];
+        for (int q = 0; q < r; ++q) v = cadd(v, cmul(F[(ri + q) * ld + ri + r], T[q * 16 + c]));
+        v.x = -v.x;
+        v.y = -v.y;
+        F[(cj + c) * ld + ri + r] = v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small fronts: one workgroup per (front, system), whole panel in LDS.
 // Assembly, partial LDL^T of the pivot columns, Schur update of the u x u
-// block straight into the front's update slot, panel write-back.
+// block (4 x 4 register tiles) straight into the front's update slot, then the
+// panel with inverted 64-wide diagonal blocks, L below them and D on the
+// diagonal.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_raw) {
@@ -334,54 +526,70 @@ __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_ra
   C* F = reinterpret_cast<C*>(smem_raw);
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
   C* dd = F + (int64_t)m * p;
-  C* invd = dd + p;
+  C* invd = dd + p;  // followed by a 16 x 16 scratch for the inverse
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  for (int idx = threadIdx.x; idx < m * p; idx += kThreads) {
-    const int c = idx / m, r = idx - c * m;
-    F[idx] = (r >= c) ? front_entry<C>(a, s, f, p, m, r, c) : czero<C>();
-  }
+  for (int c = wave; c < p; c += 4)
+    for (int r = lane; r < m; r += 64) F[c * m + r] = (r >= c) ? front_entry<C>(a, s, f, p, m, r, c) : czero<C>();
   __syncthreads();
 
   const double anorm = anorm_of(a, s);
   const double thr = a.tau * anorm;
   int npert = 0, nonfin = 0;
   double minr = INFINITY;
-  for (int k = 0; k < p; ++k) {
-    // every thread derives the same (possibly perturbed) pivot
-    const C d = fix_pivot(F[k * m + k], thr, anorm, npert, minr, nonfin);
-    const C inv = cinv(d);
-    if (threadIdx.x == 0) {
-      dd[k] = d;
-      invd[k] = inv;
-    }
-    const int Rn = m - k - 1, Cn = p - k - 1;
-    const C* colk = F + k * m;
-    for (int idx = threadIdx.x; idx < Rn * Cn; idx += kThreads) {
-      const int jc = idx / Rn, ir = idx - jc * Rn;
-      const int i = k + 1 + ir, j = k + 1 + jc;
-      if (i >= j) F[j * m + i] = cfms(F[j * m + i], colk[i], cmul(colk[j], inv));
-    }
-    __syncthreads();
-  }
+  ldl_blocked(F, m, m, p, dd, invd, thr, anorm, npert, minr, nonfin);
 
-  // Schur complement: U = F22 - W D^-1 W^T with W the unscaled columns.
+  // Schur complement: U = F22 - L_u D L_u^T over the update rows.
   C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
-  for (int idx = threadIdx.x; idx < u * u; idx += kThreads) {
-    const int jj = idx / u, ii = idx - jj * u;
-    if (ii < jj) continue;
-    C acc = front_entry<C>(a, s, f, p, m, p + ii, p + jj);
-    for (int k = 0; k < p; ++k) acc = cfms(acc, F[k * m + p + ii], cmul(F[k * m + p + jj], invd[k]));
-    U[(int64_t)jj * u + ii] = acc;
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  for (int ti = 0; ti < u; ti += 64) {
+    for (int tj = 0; tj <= ti; tj += 64) {
+      C acc[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
+      for (int k = 0; k < p; ++k) {
+        const C* col = F + k * m + p;
+        const C dk = dd[k];
+        C av[4], bv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int r = ti + tr + 16 * x;
+          av[x] = r < u ? col[r] : czero<C>();
+        }
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int c = tj + tc + 16 * y;
+          bv[y] = c < u ? cmul(col[c], dk) : czero<C>();
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int c = tj + tc + 16 * y;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int r = ti + tr + 16 * x;
+          if (r < u && c < u && r >= c)
+            U[(int64_t)c * u + r] = csub(front_entry<C>(a, s, f, p, m, p + r, p + c), acc[x][y]);
+        }
+      }
+    }
   }
-  // Panel: unit-lower L with D on the diagonal.
+  __syncthreads();
+  invert_blocked(F, m, p, invd + p);
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  for (int idx = threadIdx.x; idx < m * p; idx += kThreads) {
-    const int c = idx / m, r = idx - c * m;
-    C v = czero<C>();
-    if (r > c) v = cmul(F[idx], invd[c]);
-    else if (r == c) v = dd[c];
-    L[idx] = v;
-  }
+  for (int c = wave; c < p; c += 4)
+    for (int r = lane; r < m; r += 64) {
+      C v = czero<C>();
+      if (r > c) v = F[c * m + r];
+      else if (r == c) v = dd[c];
+      L[(int64_t)c * m + r] = v;
+    }
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin);
 }
 
@@ -396,195 +604,309 @@ __global__ __launch_bounds__(kThreads) void k_front_small(KArgs a, Queue q, cons
     if (t >= q.ntasks) break;
     const int f = order[t / a.nsys], s = t % a.nsys;
     if (q.wait) wait_children(q, a, s, f);
+    trace_mark(q, t, 1);
     small_front<R>(a, s, f, smem_raw);
     publish(q, s * a.nfronts + f);
+    trace_mark(q, t, 2);
   }
   leave(q);
 }
 
 // ---------------------------------------------------------------------------
-// Large fronts: assembly into the panel / update slot, then per block column
-// of width nb: diagonal-block factorisation (+ inverse of its unit-lower L11),
-// panel solve as a product with that inverse, trailing update of every later
-// column (pivot columns and the update block) with K = nb.
+// Large fronts: one persistent launch runs a task graph over 64 x 64 tiles.
+// The rows (and columns) of a front are cut into chunks: pivot blocks of kBW
+// from row 0 up to p, then update chunks of kBW from row p up to m.  Tasks:
+//   ASM(I,J)     assemble tile (I,J): original entries + children's blocks
+//   DIAG(k)      LDL^T of pivot block k, inverse of its unit-lower part
+//   TRSM(k,I)    tile (I,k) <- F_Ik Xinv_k^T D_k^-1
+//   UPD(k,I,J)   tile (I,J) -= L_Ik D_k L_Jk^T       (k < J <= I)
+// Each tile carries a version (1 after ASM, +1 per modification); a task
+// waits for the exact versions it reads and writes, and publishes the next.
+// A front's update tiles count their final versions in done[], which the
+// parent's ASM tasks wait for.  Tasks are listed in topological order
+// (level, then block step), so every wait ends (see the queue notes above).
 // ---------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_assemble_large(KArgs a, const int32_t* tasks) {
-  typedef typename Cx<R>::T C;
-  const int s = blockIdx.y;
-  const int32_t* t = tasks + 3 * blockIdx.x;
-  const int f = t[0], c0 = t[1], c1 = t[2];
-  const int p = a.npiv[f], u = a.nupd[f], m = p + u;
-  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
-  for (int c = c0; c < c1; ++c) {
-    if (c < p) {
-      for (int r = threadIdx.x; r < m; r += kThreads)
-        L[(int64_t)c * m + r] = (r >= c) ? front_entry<C>(a, s, f, p, m, r, c) : czero<C>();
-    } else {
-      for (int r = c + threadIdx.x; r < m; r += kThreads)
-        U[(int64_t)(c - p) * u + (r - p)] = front_entry<C>(a, s, f, p, m, r, c);
+struct TileArgs {
+  const int32_t* tasks;      // 5 ints per task: type, front, k, I, J
+  int32_t* state;            // [nsys][ntiles] tile versions
+  int32_t* done;             // [nsys][nfronts] final update tiles per front
+  const int32_t* tile_base;  // [nfronts] first packed tile of a front
+  const int32_t* is_tiled;   // [nfronts] 1 if the front is factored by this launch
+  int32_t ntiles;
+};
+
+enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3 };
+
+struct Chunks {
+  int p, u, m, nbk, nut;
+  __device__ Chunks(int p_, int u_) : p(p_), u(u_), m(p_ + u_), nbk((p_ + kBW - 1) / kBW), nut((u_ + kBW - 1) / kBW) {}
+  __device__ int lo(int I) const { return I < nbk ? I * kBW : p + (I - nbk) * kBW; }
+  __device__ int hi(int I) const { return I < nbk ? min(p, (I + 1) * kBW) : min(m, p + (I - nbk + 1) * kBW); }
+};
+
+__device__ __forceinline__ int tile_id(int I, int J) { return I * (I + 1) / 2 + J; }
+
+__device__ __forceinline__ void wait_value(const int32_t* p, int v, DevStatus* st) {
+  int it = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != v) {
+    if (++it > kSpinLimit) {
+      atomicExch(&st->spin_timeout, 1);
+      break;
     }
+    __builtin_amdgcn_s_sleep(2);
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_diag_large(KArgs a, const int32_t* fronts, int kb) {
-  typedef typename Cx<R>::T C;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int NB = a.nb;
-  C* B = reinterpret_cast<C*>(smem_raw);  // NB x NB, column major
-  C* dd = B + NB * NB;
-  C* invd = dd + NB;
-  const int s = blockIdx.y;
-  const int f = fronts[blockIdx.x];
-  const int p = a.npiv[f], m = p + a.nupd[f];
-  const int nb = min(NB, p - kb);
-  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)kb * m + kb;
-  for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
-    const int c = idx / nb, r = idx - c * nb;
-    B[c * NB + r] = (r >= c) ? L[(int64_t)c * m + r] : czero<C>();
+__device__ __forceinline__ void wait_at_least(const int32_t* p, int v, DevStatus* st) {
+  int it = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+    if (++it > kSpinLimit) {
+      atomicExch(&st->spin_timeout, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
   }
+}
+
+// C[r][c] (64 x 64 register tile, 4 x 4 per thread) += sum_q A[r][q] B[c][q]
+// over q < K in chunks of 16 staged in LDS (k-major).  The next chunk is
+// loaded into registers while the current one is multiplied.  loadA/loadB
+// return the operands for (row, q).
+template <typename C, typename FA, typename FB>
+__device__ __forceinline__ void tile_abt(int na, int nb_, int K, FA loadA, FB loadB, C* As, C* Bs, C acc[4][4]) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  C pa[4], pb[4];
+  for (int q0 = 0; q0 < K; q0 += 16) {
+    if (q0 == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + e * kThreads;
+        const int qq = idx >> 6, r = idx & 63;
+        const bool in = qq < min(16, K);
+        pa[e] = (in && r < na) ? loadA(r, qq) : czero<C>();
+        pb[e] = (in && r < nb_) ? loadB(r, qq) : czero<C>();
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      As[threadIdx.x + e * kThreads] = pa[e];
+      Bs[threadIdx.x + e * kThreads] = pb[e];
+    }
+    __syncthreads();
+    if (q0 + 16 < K) {
+      const int q1 = q0 + 16, kq = min(16, K - q1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + e * kThreads;
+        const int qq = idx >> 6, r = idx & 63;
+        pa[e] = (qq < kq && r < na) ? loadA(r, q1 + qq) : czero<C>();
+        pb[e] = (qq < kq && r < nb_) ? loadB(r, q1 + qq) : czero<C>();
+      }
+    }
+#pragma unroll 1
+    for (int qq = 0; qq < 16; ++qq) {
+      C av[4], bv[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) av[x] = As[qq * kBW + tr + 16 * x];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) bv[y] = Bs[qq * kBW + tc + 16 * y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
+    }
+    __syncthreads();
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, int u, int m, int r, int c) {
+  if (c < p) return (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)c * m + r;
+  return (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f] + (int64_t)(c - p) * u + (r - p);
+}
+
+template <typename R>
+__device__ void task_asm(const KArgs& a, int s, int f, int I, int J) {
+  typedef typename Cx<R>::T C;
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int r0 = ch.lo(I), r1 = ch.hi(I), c0 = ch.lo(J), c1 = ch.hi(J);
+  const int nr = r1 - r0, nc = c1 - c0;
+  for (int idx = threadIdx.x; idx < nr * nc; idx += kThreads) {
+    const int c = c0 + idx / nr, r = r0 + idx % nr;
+    if (r >= c) *front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c) = front_entry<C>(a, s, f, ch.p, ch.m, r, c);
+    else if (c < ch.p) *front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c) = czero<C>();
+  }
+}
+
+// DIAG(k): LDL^T of the nb x nb pivot block and the in-place inverse of its
+// unit-lower factor, both blocked by 16 (see ldl_blocked / invert_blocked).
+template <typename R>
+__device__ void task_diag(const KArgs& a, int s, int f, int k, unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  C* B = reinterpret_cast<C*>(smem);  // kBW x kBW, column major
+  C* dd = B + kBW * kBW;
+  C* invd = dd + kBW;
+  C* T = invd + kBW;  // 16 x 16
+  const int p = a.npiv[f], m = p + a.nupd[f];
+  const int k0 = k * kBW, nb = min(kBW, p - k0);
+  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m + k0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < nb; c += 4)
+    for (int r = lane; r < nb; r += 64) B[c * kBW + r] = (r >= c) ? L[(int64_t)c * m + r] : czero<C>();
   __syncthreads();
   const double anorm = anorm_of(a, s);
   const double thr = a.tau * anorm;
   int npert = 0, nonfin = 0;
   double minr = INFINITY;
-  for (int k = 0; k < nb; ++k) {
-    const C d = fix_pivot(B[k * NB + k], thr, anorm, npert, minr, nonfin);
-    const C inv = cinv(d);
-    if (threadIdx.x == 0) {
-      dd[k] = d;
-      invd[k] = inv;
-    }
-    const int Rn = nb - k - 1;
-    for (int idx = threadIdx.x; idx < Rn * Rn; idx += kThreads) {
-      const int jc = idx / Rn, ir = idx - jc * Rn;
-      const int i = k + 1 + ir, j = k + 1 + jc;
-      if (i >= j) B[j * NB + i] = cfms(B[j * NB + i], B[k * NB + i], cmul(B[k * NB + j], inv));
-    }
-    __syncthreads();
-  }
-  // scale to unit-lower L11 and write back with D on the diagonal
-  for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
-    const int c = idx / nb, r = idx - c * nb;
-    if (r > c) B[c * NB + r] = cmul(B[c * NB + r], invd[c]);
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
-    const int c = idx / nb, r = idx - c * nb;
-    if (r > c) L[(int64_t)c * m + r] = B[c * NB + r];
-    else if (r == c) L[(int64_t)c * m + r] = dd[c];
-  }
-  // X = L11^-1 (unit lower) in LDS by row elimination: X = I, then for every k
-  // rows i > k take X[i][:] -= L[i][k] X[k][:] (only columns <= k are nonzero).
-  C* Xl = invd + NB;  // NB x NB, column major
-  for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
-    const int c = idx / nb, r = idx - c * nb;
-    C v = czero<C>();
-    if (r == c) v.x = 1;
-    Xl[c * NB + r] = v;
-  }
-  __syncthreads();
-  for (int k = 0; k < nb - 1; ++k) {
-    const int Rn = nb - k - 1, Cn = k + 1;
-    for (int idx = threadIdx.x; idx < Rn * Cn; idx += kThreads) {
-      const int j = idx / Rn, i = k + 1 + (idx - j * Rn);
-      Xl[j * NB + i] = cfms(Xl[j * NB + i], B[k * NB + i], Xl[j * NB + k]);
-    }
-    __syncthreads();
-  }
-  C* X = (C*)a.mscr + ((int64_t)s * a.nmslot + a.mslot[f]) * NB * NB;
-  for (int idx = threadIdx.x; idx < nb * NB; idx += kThreads) X[idx] = Xl[idx];
+  ldl_blocked(B, kBW, nb, nb, dd, invd, thr, anorm, npert, minr, nonfin);
+  invert_blocked(B, kBW, nb, T);
+  for (int c = wave; c < nb; c += 4)
+    for (int r = c + lane; r < nb; r += 64) L[(int64_t)c * m + r] = (r > c) ? B[c * kBW + r] : dd[c];
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin);
 }
 
-// Rows [r0, r0+64) below the diagonal block: L21 = F21 L11^-T D^-1.
+// tile (I,k) <- F_Ik Xinv^T D^-1: out[r][j] = sum_{q<=j} F[r][q] Xinv[j][q] / d_j
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_trsm_large(KArgs a, const int32_t* tasks, int kb) {
+__device__ void task_trsm(const KArgs& a, int s, int f, int k, int I, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int TR = 64;
-  const int NB = a.nb;
-  C* Xs = reinterpret_cast<C*>(smem_raw);  // NB x NB, Xs[j*NB + k] = (L11^-1)[k][j]... see below
-  C* Ft = Xs + NB * NB;                   // TR x NB, row major
-  C* invd = Ft + TR * NB;
-  const int s = blockIdx.y;
-  const int f = tasks[2 * blockIdx.x], r0 = tasks[2 * blockIdx.x + 1];
-  const int p = a.npiv[f], m = p + a.nupd[f];
-  const int nb = min(NB, p - kb);
-  const int nr = min(TR, m - r0);
+  C* As = reinterpret_cast<C*>(smem);
+  C* Bs = As + 16 * kBW;
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
+  const int r0 = ch.lo(I), nr = ch.hi(I) - r0;
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  const C* X = (const C*)a.mscr + ((int64_t)s * a.nmslot + a.mslot[f]) * NB * NB;
-  for (int idx = threadIdx.x; idx < nb * NB; idx += kThreads) Xs[idx] = X[idx];
-  for (int idx = threadIdx.x; idx < nr * nb; idx += kThreads) {
-    const int k = idx / nr, r = idx - k * nr;
-    Ft[r * NB + k] = L[(int64_t)(kb + k) * m + r0 + r];
-  }
-  for (int k = threadIdx.x; k < nb; k += kThreads)
-    invd[k] = cinv(L[(int64_t)(kb + k) * m + kb + k]);
-  __syncthreads();
-  // out[r][j] = (sum_{k<=j} F[r][k] (L11^-1)[j][k]) / d_j ; (L11^-1)[j][k] = X[k*NB + j]
-  for (int idx = threadIdx.x; idx < nr * nb; idx += kThreads) {
-    const int j = idx / nr, r = idx - j * nr;
-    C acc = czero<C>();
-    for (int k = 0; k <= j; ++k) acc = cadd(acc, cmul(Ft[r * NB + k], Xs[k * NB + j]));
-    L[(int64_t)(kb + j) * m + r0 + r] = cmul(acc, invd[j]);
-  }
-}
-
-// Trailing update of a 64 x 64 lower tile: C[r][c] -= sum_k L[r][kb+k] d_k L[c][kb+k].
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_update_large(KArgs a, const int32_t* tasks, int kb) {
-  typedef typename Cx<R>::T C;
-  constexpr int TS = 64;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int NB = a.nb;
-  C* As = reinterpret_cast<C*>(smem_raw);  // NB x TS (k major): As[k*TS + r]
-  C* Bs = As + NB * TS;                   // NB x TS, premultiplied by d_k
-  const int s = blockIdx.y;
-  const int32_t* t = tasks + 3 * blockIdx.x;
-  const int f = t[0], r0 = t[1], c0 = t[2];
-  const int p = a.npiv[f], u = a.nupd[f], m = p + u;
-  const int nb = min(NB, p - kb);
-  const int nr = min(TS, m - r0), nc = min(TS, m - c0);
-  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
-  for (int idx = threadIdx.x; idx < nb * TS; idx += kThreads) {
-    const int k = idx / TS, r = idx - k * TS;
-    const C* col = L + (int64_t)(kb + k) * m;
-    As[idx] = r < nr ? col[r0 + r] : czero<C>();
-    Bs[idx] = r < nc ? cmul(col[c0 + r], col[kb + k]) : czero<C>();
-  }
-  __syncthreads();
-  // 4 x 4 outputs per thread: rows tr*4.., cols tc*4.. with a 16 x 16 thread grid
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   C acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
-  for (int k = 0; k < nb; ++k) {
-    C av[4], bv[4];
+  tile_abt<C>(nr, nb, nb, [&](int r, int q) { return L[(int64_t)(k0 + q) * m + r0 + r]; },
+              [&](int j, int q) {
+                C v = czero<C>();
+                if (q < j) v = L[(int64_t)(k0 + q) * m + k0 + j];
+                else if (q == j) v.x = 1;
+                return v;
+              },
+              As, Bs, acc);
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) av[x] = As[k * TS + tr + 16 * x];
+  for (int y = 0; y < 4; ++y) {
+    const int j = tc + 16 * y;
+    if (j >= nb) continue;
+    const C invj = cinv(L[(int64_t)(k0 + j) * m + k0 + j]);
 #pragma unroll
-    for (int y = 0; y < 4; ++y) bv[y] = Bs[k * TS + tc + 16 * y];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
+    for (int x = 0; x < 4; ++x) {
+      const int r = tr + 16 * x;
+      if (r < nr) L[(int64_t)(k0 + j) * m + r0 + r] = cmul(acc[x][y], invj);
+    }
   }
+}
+
+// tile (I,J) -= L_Ik D_k L_Jk^T
+template <typename R>
+__device__ void task_upd(const KArgs& a, int s, int f, int k, int I, int J, unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  C* As = reinterpret_cast<C*>(smem);
+  C* Bs = As + 16 * kBW;
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
+  const int r0 = ch.lo(I), nr = ch.hi(I) - r0, c0 = ch.lo(J), nc = ch.hi(J) - c0;
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  C acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
+  tile_abt<C>(nr, nc, nb, [&](int r, int q) { return L[(int64_t)(k0 + q) * m + r0 + r]; },
+              [&](int c, int q) {
+                const C* col = L + (int64_t)(k0 + q) * m;
+                return cmul(col[c0 + c], col[k0 + q]);
+              },
+              As, Bs, acc);
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int r = r0 + tr + 16 * x;
+    if (r >= r0 + nr) continue;
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int c = c0 + tc + 16 * y;
-      if (r >= m || c >= m || r < c) continue;
-      C* dst = (c < p) ? (L + (int64_t)c * m + r) : (U + (int64_t)(c - p) * u + (r - p));
+      if (c >= c0 + nc || r < c) continue;
+      C* dst = front_elem<C>(a, s, f, ch.p, ch.u, m, r, c);
       *dst = csub(*dst, acc[x][y]);
     }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, Queue q) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
+  for (;;) {
+    const int t = claim(q, &sh);
+    if (t >= q.ntasks) break;
+    const int32_t* tk = ta.tasks + 5 * (t / a.nsys);
+    const int s = t % a.nsys;
+    const int type = tk[0], f = tk[1], k = tk[2], I = tk[3], J = tk[4];
+    const Chunks ch(a.npiv[f], a.nupd[f]);
+    int32_t* st = ta.state + (int64_t)s * ta.ntiles + ta.tile_base[f];
+    if (threadIdx.x == 0) {
+      if (type == T_ASM) {
+        for (int c = a.child_ptr[f]; c < a.child_ptr[f + 1]; ++c) {
+          const int cf = a.child_list[c];
+          if (!ta.is_tiled[cf]) continue;
+          const int nut = (a.nupd[cf] + kBW - 1) / kBW;
+          wait_at_least(ta.done + (int64_t)s * a.nfronts + cf, nut * (nut + 1) / 2, a.st);
+        }
+      } else if (type == T_DIAG) {
+        wait_value(st + tile_id(k, k), k + 1, a.st);
+      } else if (type == T_TRSM) {
+        wait_value(st + tile_id(k, k), k + 2, a.st);
+        wait_value(st + tile_id(I, k), k + 1, a.st);
+      } else {
+        wait_value(st + tile_id(I, k), k + 2, a.st);
+        wait_value(st + tile_id(J, k), k + 2, a.st);
+        wait_value(st + tile_id(I, J), k + 1, a.st);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    trace_mark(q, t, 1);
+    int tile = 0, ver = 0;
+    if (type == T_ASM) {
+      task_asm<R>(a, s, f, I, J);
+      tile = tile_id(I, J);
+      ver = 1;
+    } else if (type == T_DIAG) {
+      task_diag<R>(a, s, f, k, smem_raw);
+      tile = tile_id(k, k);
+      ver = k + 2;
+    } else if (type == T_TRSM) {
+      task_trsm<R>(a, s, f, k, I, smem_raw);
+      tile = tile_id(I, k);
+      ver = k + 2;
+    } else {
+      task_upd<R>(a, s, f, k, I, J, smem_raw);
+      tile = tile_id(I, J);
+      ver = k + 2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(st + tile, ver, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (type == T_UPD && J >= ch.nbk && k == ch.nbk - 1)
+        __hip_atomic_fetch_add(ta.done + (int64_t)s * a.nfronts + f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    trace_mark(q, t, 2);
+  }
+  leave(q);
+}
+
+// Clears tile versions and completion counts before the task-graph launch.
+__global__ void k_tiles_reset(int32_t* state, int64_t nstate, int32_t* done, int64_t ndone) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nstate + ndone;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nstate) state[i] = 0;
+    else done[i - nstate] = 0;
   }
 }
 
@@ -598,12 +920,6 @@ __global__ __launch_bounds__(kThreads) void k_update_large(KArgs a, const int32_
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool done(const int* flag) { return flag && *(volatile const int*)flag; }
 
-template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
-  v.x = __shfl(v.x, lane);
-  v.y = __shfl(v.y, lane);
-  return v;
-}
-
 struct SweepArgs {
   const double2* src;  // forward: right-hand sides, grid order
   double2* out;        // backward: solution, grid order
@@ -613,17 +929,18 @@ struct SweepArgs {
   int32_t nrhs, scale_src, accumulate;
 };
 
-// One front of the forward sweep: V = [rhs_p; 0] + children's update vectors,
-// V <- L^-1 V over the pivot columns in BW-wide blocks (one wave solves the
-// block triangle staged in LDS, all threads apply the rows below it), then
-// y_p = D^-1 V_p and the front's update vector is V_u.
-template <typename R, int BW>
+// One front of the forward sweep.  V = [rhs_p; 0] + the children's update
+// vectors; then for each kBW-wide pivot block: V_blk <- Xinv V_blk with the
+// inverted unit-lower diagonal block stored in the panel (four waves split the
+// columns, partial sums meet in LDS), and V_below -= L_below,blk V_blk (one
+// row per thread).  Finally y_p = D^-1 V_p and the update vector is V_u.
+template <typename R>
 __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
-  C* T = reinterpret_cast<C*>(smem);  // BW x (BW+1)
-  C* V = T + BW * (BW + 1);          // nrhs x m
+  C* red = reinterpret_cast<C*>(smem);  // 4 x kBW partial sums
+  C* V = red + 4 * kBW;                 // nrhs x m
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
@@ -646,29 +963,39 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     V[col * m + r] = v;
   }
   __syncthreads();
-  for (int k0 = 0; k0 < p; k0 += BW) {
-    const int kn = min(BW, p - k0), k1 = k0 + kn;
-    for (int idx = threadIdx.x; idx < kn * kn; idx += kThreads) {
-      const int k = idx / kn, l = idx - k * kn;
-      T[k * (BW + 1) + l] = L[(int64_t)(k0 + k) * m + k0 + l];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int lane = threadIdx.x;
-      for (int col = 0; col < nrhs; ++col) {
-        C v = lane < kn ? V[col * m + k0 + lane] : czero<C>();
-        for (int k = 0; k < kn; ++k) {
-          const C vk = shfl_c(v, k);
-          if (lane > k && lane < kn) v = cfms(v, T[k * (BW + 1) + lane], vk);
-        }
-        if (lane < kn) V[col * m + k0 + lane] = v;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < p; k0 += kBW) {
+    const int kn = min(kBW, p - k0), k1 = k0 + kn;
+    const C* Xb = L + (int64_t)k0 * m + k0;
+    for (int col = 0; col < nrhs; ++col) {
+      const C* Vb = V + col * m + k0;
+      C acc = czero<C>();
+      if (lane < kn) {
+#pragma unroll 4
+        for (int j = wave; j < lane; j += 4) acc = cadd(acc, cmul(Xb[(int64_t)j * m + lane], Vb[j]));
       }
+      red[wave * kBW + lane] = acc;
+      __syncthreads();
+      if (wave == 0 && lane < kn) {
+        C t = Vb[lane];
+        t = cadd(t, cadd(cadd(red[lane], red[kBW + lane]), cadd(red[2 * kBW + lane], red[3 * kBW + lane])));
+        V[col * m + k0 + lane] = t;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int i = k1 + threadIdx.x; i < m; i += kThreads) {
       for (int col = 0; col < nrhs; ++col) {
+        const C* Vb = V + col * m + k0;
         C acc = V[col * m + i];
-        for (int k = k0; k < k1; ++k) acc = cfms(acc, L[(int64_t)k * m + i], V[col * m + k]);
+        int j = 0;
+        for (; j + 16 <= kn; j += 16) {
+          C l[16];
+#pragma unroll
+          for (int t = 0; t < 16; ++t) l[t] = L[(int64_t)(k0 + j + t) * m + i];
+#pragma unroll
+          for (int t = 0; t < 16; ++t) acc = cfms(acc, l[t], Vb[j + t]);
+        }
+        for (; j < kn; ++j) acc = cfms(acc, L[(int64_t)(k0 + j) * m + i], Vb[j]);
         V[col * m + i] = acc;
       }
     }
@@ -681,17 +1008,26 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   }
 }
 
-// One front of the backward sweep: X = [z_p; x(update rows)], then for BW-wide
-// blocks from the last: X_blk -= L(rows below, blk)^T X(below) (one wave per
-// column, lanes over rows) and one wave solves the transposed block triangle
-// staged in LDS.  x_p goes to y and to the grid-order output.
-template <typename R, int BW>
+template <typename C> __device__ __forceinline__ C wave_sum(C v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+
+// One front of the backward sweep.  X = [z_p; x(update rows)]; for kBW-wide
+// blocks from the last: X_blk -= L_below,blk^T X_below, then
+// X_blk <- Xinv^T X_blk.  Both are column dot products: one wave per column,
+// lanes over rows, coalesced.  x_p goes to y and to the grid-order output.
+template <typename R>
 __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
-  C* T = reinterpret_cast<C*>(smem);
-  C* X = T + BW * (BW + 1);
+  C* tmp = reinterpret_cast<C*>(smem);  // nrhs x kBW
+  C* red = tmp + nrhs * kBW;             // nrhs x 4 x kBW partial sums
+  C* X = red + 4 * nrhs * kBW;
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
@@ -701,36 +1037,64 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int NW = kThreads / 64;
   int k1 = p;
   while (k1 > 0) {
-    const int k0 = ((k1 - 1) / BW) * BW;
+    const int k0 = ((k1 - 1) / kBW) * kBW;
     const int kn = k1 - k0;
-    for (int k = k0 + wave; k < k1; k += NW) {
+    // (a) X_blk[j] -= sum_{i >= k1} L[i][k0+j] X[i]: lane = column j, the four
+    // waves split the rows; every lane walks down its own (contiguous) column.
+    {
+      const int rows = m - k1, per = (rows + 3) / 4;
+      const int r0 = k1 + wave * per, r1 = min(m, r0 + per);
+      const C* Lc = L + (int64_t)(k0 + lane) * m;
       for (int col = 0; col < nrhs; ++col) {
+        const C* Xc = X + col * m;
         C acc = czero<C>();
-        for (int i = k1 + lane; i < m; i += 64) acc = cadd(acc, cmul(L[(int64_t)k * m + i], X[col * m + i]));
-        for (int o = 32; o > 0; o >>= 1) {
-          acc.x += __shfl_xor(acc.x, o);
-          acc.y += __shfl_xor(acc.y, o);
+        if (lane < kn) {
+          int i = r0;
+          for (; i + 8 <= r1; i += 8) {
+            C l[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) l[t] = Lc[i + t];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc = cadd(acc, cmul(l[t], Xc[i + t]));
+          }
+          for (; i < r1; ++i) acc = cadd(acc, cmul(Lc[i], Xc[i]));
         }
-        if (lane == 0) X[col * m + k] = csub(X[col * m + k], acc);
+        red[(col * 4 + wave) * kBW + lane] = acc;
       }
-    }
-    for (int idx = threadIdx.x; idx < kn * kn; idx += kThreads) {
-      const int l = idx / kn, k = idx - l * kn;
-      T[l * (BW + 1) + k] = L[(int64_t)(k0 + l) * m + k0 + k];
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
+      const int col = idx / kn, j = idx - col * kn;
+      const C* rr = red + col * 4 * kBW + j;
+      X[col * m + k0 + j] = csub(X[col * m + k0 + j], cadd(cadd(rr[0], rr[kBW]), cadd(rr[2 * kBW], rr[3 * kBW])));
+    }
+    __syncthreads();
+    // (b) x_blk[j] = X_blk[j] + sum_{j < i < kn} Xinv[i][j] X_blk[i], same layout
+    {
+      const int per = (kn + 3) / 4;
+      const int r0 = wave * per, r1 = min(kn, r0 + per);
+      const C* Xcol = L + (int64_t)(k0 + lane) * m + k0;
       for (int col = 0; col < nrhs; ++col) {
-        C v = lane < kn ? X[col * m + k0 + lane] : czero<C>();
-        for (int k = kn - 1; k > 0; --k) {
-          const C xk = shfl_c(v, k);
-          if (lane < k) v = cfms(v, T[lane * (BW + 1) + k], xk);
+        const C* Xb = X + col * m + k0;
+        C acc = czero<C>();
+        if (lane < kn) {
+          for (int i = max(r0, lane + 1); i < r1; ++i) acc = cadd(acc, cmul(Xcol[i], Xb[i]));
         }
-        if (lane < kn) X[col * m + k0 + lane] = v;
+        red[(col * 4 + wave) * kBW + lane] = acc;
       }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
+      const int col = idx / kn, j = idx - col * kn;
+      const C* rr = red + col * 4 * kBW + j;
+      tmp[col * kBW + j] = cadd(X[col * m + k0 + j], cadd(cadd(rr[0], rr[kBW]), cadd(rr[2 * kBW], rr[3 * kBW])));
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
+      const int col = idx / kn, j = idx - col * kn;
+      X[col * m + k0 + j] = tmp[col * kBW + j];
     }
     __syncthreads();
     k1 = k0;
@@ -747,7 +1111,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
 }
 
 // Forward sweep: items in level order (leaves first), each waits for its children.
-template <typename R, int BW>
+template <typename R>
 __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -757,14 +1121,16 @@ __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Qu
     if (t >= q.ntasks) break;
     const int f = order[t / a.nsys], s = t % a.nsys;
     if (q.wait) wait_children(q, a, s, f);
-    fwd_front<R, BW>(a, w, s, f, smem_raw);
+    trace_mark(q, t, 1);
+    fwd_front<R>(a, w, s, f, smem_raw);
     publish(q, (int64_t)s * a.nfronts + f);
+    trace_mark(q, t, 2);
   }
   leave(q);
 }
 
 // Backward sweep: items in reverse level order (root first), each waits for its parent.
-template <typename R, int BW>
+template <typename R>
 __global__ __launch_bounds__(kThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -775,8 +1141,10 @@ __global__ __launch_bounds__(kThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Qu
     if (t >= q.ntasks) break;
     const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
     if (q.wait) wait_parent(q, a, s, f);
-    bwd_front<R, BW>(a, w, s, f, smem_raw);
+    trace_mark(q, t, 1);
+    bwd_front<R>(a, w, s, f, smem_raw);
     publish(q, (int64_t)s * F + f);
+    trace_mark(q, t, 2);
   }
   leave(q);
 }
@@ -975,7 +1343,6 @@ KArgs make_args(Plan& P) {
   a.nbr_row = P.t.nbr_row;
   a.perm = P.t.perm;
   a.iperm = P.t.iperm;
-  a.mslot = P.t.mslot;
   a.parent = P.t.parent;
   a.fac_off = P.t.fac_off;
   a.upd_off = P.t.upd_off;
@@ -992,12 +1359,9 @@ KArgs make_args(Plan& P) {
   a.omega = P.omega;
   a.fac = P.fac;
   a.upd = P.upd;
-  a.mscr = P.mscr;
   a.st = P.status;
   // pivot threshold tau * ||SA||_max with tau = sqrt(unit roundoff)
   a.tau = P.is_c64 ? 2.44140625e-4 : 1.0536712127723509e-8;
-  a.nb = P.nb_large;
-  a.nmslot = P.nmslot;
   a.nfronts = P.an.nfronts;
   return a;
 }
@@ -1009,11 +1373,16 @@ inline unsigned grid1d(int64_t n, int64_t cap = 2048) {
   return (unsigned)b;
 }
 
-Queue make_queue(Plan& P, int ntasks, int wait) {
+Queue make_queue(Plan& P, int ntasks, int wait, int trace_kind = -1) {
   Queue q;
   q.counter = P.counters;
   q.done = P.done;
   q.st = P.status;
+  q.trace = nullptr;
+  if (trace_kind >= 0 && P.trace_buf[trace_kind] && ntasks <= P.trace_cap[trace_kind]) {
+    q.trace = P.trace_buf[trace_kind];
+    P.trace_n[trace_kind] = ntasks;
+  }
   q.epoch = ++P.epoch;
   q.ntasks = ntasks;
   q.wait = wait;
@@ -1051,12 +1420,18 @@ unsigned persistent_grid(const Plan& P, size_t lds, int ntasks) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// LDS of the task-graph kernel: the diagonal task's block and pivots, or the
+// two 16-deep operand panels of the tile products, whichever is larger.
+size_t tile_lds(const Plan& P) {
+  const size_t diag = (size_t)(kBW * kBW + 2 * kBW + 256);
+  const size_t gemm = (size_t)(2 * 16 * kBW);
+  return (diag > gemm ? diag : gemm) * P.csize;
+}
+
 template <typename R>
 hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st) {
   const KArgs a = make_args(P);
   const int nsys = P.desc.nsys;
-  const size_t cs = P.csize;
-  const int NB = P.nb_large;
   Omegas om;
   for (int s = 0; s < kMaxSys; ++s) om.w[s] = s < nsys ? P.omega_host[s] : 0.0;
   {
@@ -1068,70 +1443,48 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
     hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
   }
   const int32_t* lf = P.t.level_fronts;
-  const int32_t* tk = P.t.tasks;
-  const size_t nl = P.levels.size();
-  size_t l = 0;
   // the small levels at the bottom of the tree: one persistent launch
   if (P.small_prefix > 0) {
     const int nf = P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count;
-    const Queue q = make_queue(P, nf * nsys, 1);
+    const Queue q = make_queue(P, nf * nsys, 1, 0);
     double fl = 0.0;
     for (int k = 0; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
     Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
     hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, nf * nsys)),
                        dim3(kThreads), P.small_lds_prefix, st, a, q, lf);
-    l = P.small_prefix;
   }
-  for (; l < nl; ++l) {
-    const LevelPlan& L = P.levels[l];
-    if (L.small) {
-      const Queue q = make_queue(P, L.count * nsys, 0);
-      double fl = 0.0;
-      for (int k = L.first; k < L.first + L.count; ++k) fl += P.front_flops[P.an.level_fronts[k]];
-      Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
-      hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, L.small_lds, L.count * nsys)),
-                         dim3(kThreads), L.small_lds, st, a, q, lf + L.first);
-      continue;
-    }
-    {
-      Prof pr(P, st, KC_ASSEMBLE_LARGE, L.asm_bytes * nsys, 0.0);
-      hipLaunchKernelGGL(k_assemble_large<R>, dim3(L.nasm, nsys), dim3(kThreads), 0, st, a,
-                         tk + L.asm_off);
-    }
-    for (const BlockStep& S : L.steps) {
-      {
-        Prof pr(P, st, KC_DIAG_LARGE, 0.0, S.diag_flops * nsys);
-        hipLaunchKernelGGL(k_diag_large<R>, dim3(S.ndiag, nsys), dim3(kThreads),
-                           (size_t)(2 * NB * NB + 2 * NB) * cs, st, a, tk + S.diag_off, S.kb);
-      }
-      if (S.ntrsm) {
-        Prof pr(P, st, KC_TRSM_LARGE, 0.0, S.trsm_flops * nsys);
-        hipLaunchKernelGGL(k_trsm_large<R>, dim3(S.ntrsm, nsys), dim3(kThreads),
-                           (size_t)(NB * NB + 64 * NB + NB) * cs, st, a, tk + S.trsm_off, S.kb);
-      }
-      if (S.nupd) {
-        Prof pr(P, st, KC_UPDATE_LARGE, 0.0, S.upd_flops * nsys);
-        hipLaunchKernelGGL(k_update_large<R>, dim3(S.nupd, nsys), dim3(kThreads),
-                           (size_t)(2 * NB * 64) * cs, st, a, tk + S.upd_off, S.kb);
-      }
-    }
+  // every level above them: one persistent launch of the tile task graph
+  if (P.ntile_tasks > 0) {
+    const int64_t nstate = (int64_t)nsys * P.ntiles, ndone = (int64_t)nsys * P.an.nfronts;
+    hipLaunchKernelGGL(k_tiles_reset, dim3(grid1d(nstate + ndone, 256)), dim3(kThreads), 0, st, P.tile_state,
+                       nstate, P.tile_done, ndone);
+    TileArgs ta;
+    ta.tasks = P.t.tile_tasks;
+    ta.state = P.tile_state;
+    ta.done = P.tile_done;
+    ta.tile_base = P.t.tile_base;
+    ta.is_tiled = P.t.is_tiled;
+    ta.ntiles = P.ntiles;
+    const size_t lds = tile_lds(P);
+    const int nt = P.ntile_tasks * nsys;
+    Prof pr(P, st, KC_LARGE_TILES, 0.0, P.tiled_flops * nsys);
+    hipLaunchKernelGGL(k_large_tiles<R>, dim3(persistent_grid(P, lds, nt)), dim3(kThreads), lds, st, a, ta,
+                       make_queue(P, nt, 1, 1));
   }
   return hipGetLastError();
 }
 
-template <typename R> constexpr int sweep_bw() { return sizeof(R) == 8 ? 32 : 64; }
-
-size_t sweep_lds(const Plan& P, int nrhs, int bw) {
-  return ((size_t)bw * (bw + 1) + (size_t)P.an.max_front * nrhs) * P.csize;
+size_t sweep_lds(const Plan& P, int nrhs) {
+  // forward: 4 x kBW partials + V; backward: nrhs x kBW + 4 nrhs x kBW + X
+  return ((size_t)kBW * 5 * (nrhs > 1 ? nrhs : 1) + (size_t)P.an.max_front * nrhs) * P.csize;
 }
 
 // One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src.
 template <typename R>
 void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
            int accumulate, const int* flag, hipStream_t st) {
-  constexpr int BW = sweep_bw<R>();
   const int nt = P.an.nfronts * P.desc.nsys;
-  const size_t lds = sweep_lds(P, nrhs, BW);
+  const size_t lds = sweep_lds(P, nrhs);
   SweepArgs w;
   w.src = src;
   w.out = dst;
@@ -1151,14 +1504,14 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
     for (const LevelPlan& L : P.levels) {
       const int n = L.count * nsys;
       Prof pr(P, st, KC_FWD_SWEEP, L.lbytes * nsys + vec_bytes * L.count / P.an.nfronts, 0.0);
-      hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
+      hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
                          make_queue(P, n, 0), lf + L.first);
     }
     for (size_t l = P.levels.size(); l-- > 0;) {
       const LevelPlan& L = P.levels[l];
       const int n = L.count * nsys;
       Prof pr(P, st, KC_BWD_SWEEP, L.lbytes * nsys + vec_bytes * L.count / P.an.nfronts, 0.0);
-      hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
+      hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
                          make_queue(P, n, 0), lf + L.first);
     }
     return;
@@ -1167,11 +1520,11 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   const double fb = P.factor_lbytes * nsys + vec_bytes;
   {
     Prof pr(P, st, KC_FWD_SWEEP, fb, 0.0);
-    hipLaunchKernelGGL((k_fwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
+    hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1, 2), lf);
   }
   {
     Prof pr(P, st, KC_BWD_SWEEP, fb, 0.0);
-    hipLaunchKernelGGL((k_bwd_sweep<R, BW>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1), lf);
+    hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1, 3), lf);
   }
 }
 
@@ -1218,11 +1571,9 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
 
 template <typename R>
 hipError_t set_lds_limits(int limit) {
-  constexpr int BW = sweep_bw<R>();
   hipError_t e = hipSuccess;
-  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_diag_large<R>,
-                       (const void*)k_trsm_large<R>, (const void*)k_update_large<R>,
-                       (const void*)k_fwd_sweep<R, BW>, (const void*)k_bwd_sweep<R, BW>};
+  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_large_tiles<R>,
+                       (const void*)k_fwd_sweep<R>, (const void*)k_bwd_sweep<R>};
   for (const void* fn : fns) {
     hipFuncAttributes fa;
     hipError_t r = hipFuncGetAttributes(&fa, fn);
@@ -1239,9 +1590,7 @@ hipError_t configure_kernels(Plan& P, int lds_limit) {
   return P.is_c64 ? set_lds_limits<float>(lds_limit) : set_lds_limits<double>(lds_limit);
 }
 
-size_t solve_lds_bytes(const Plan& P, int nrhs) {
-  return sweep_lds(P, nrhs, P.is_c64 ? sweep_bw<float>() : sweep_bw<double>());
-}
+size_t solve_lds_bytes(const Plan& P, int nrhs) { return sweep_lds(P, nrhs); }
 
 hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st) {
   return P.is_c64 ? refactor_impl<float>(P, eps, eps_stride, st)

@@ -36,35 +36,23 @@ struct DevTables {
   int32_t *gmap = nullptr, *nbr_row = nullptr;
   int32_t *perm = nullptr, *iperm = nullptr;
   int32_t *level_fronts = nullptr;
-  int32_t *mslot = nullptr, *parent = nullptr;
+  int32_t *parent = nullptr;
+  int32_t *tile_tasks = nullptr, *tile_base = nullptr, *is_tiled = nullptr;
   int64_t *fac_off = nullptr, *upd_off = nullptr, *gmap_ptr = nullptr;
-  int32_t *tasks = nullptr;  // task lists of the large-front path
-};
-
-// One block step of the large-front path at one level.
-struct BlockStep {
-  int32_t kb, nb;
-  int64_t diag_off;  int32_t ndiag;    // fronts with p > kb (task buffer offsets)
-  int64_t trsm_off;  int32_t ntrsm;    // (front, first row) pairs
-  int64_t upd_off;   int32_t nupd;     // (front, tile row, tile col) triples
-  double diag_flops = 0, trsm_flops = 0, upd_flops = 0;  // algorithmic work per system
 };
 
 struct LevelPlan {
   int32_t first, count;        // slice of level_fronts
-  bool small;                  // fused one-workgroup-per-front kernel
-  size_t small_lds;            // dynamic LDS bytes of the fused kernel
-  int64_t asm_off; int32_t nasm;   // assembly tasks (front, c0, c1), large path
-  std::vector<BlockStep> steps;
+  bool small;                  // panel fits the one-workgroup LDS kernel
+  size_t small_lds;            // dynamic LDS bytes of that kernel
   int32_t max_m, max_p, max_u;
   double lbytes = 0;           // lower-trapezoid factor bytes of the level (one system)
-  double asm_bytes = 0;        // front entries written by the large-path assembly
 };
 
 // Kernel classes for FDFD_PROFILE timing.
 enum KernelClass {
-  KC_SETUP = 0, KC_FRONT_SMALL, KC_ASSEMBLE_LARGE, KC_DIAG_LARGE, KC_TRSM_LARGE, KC_UPDATE_LARGE,
-  KC_FWD_SWEEP, KC_BWD_SWEEP, KC_RESIDUAL, KC_GRADIENT, KC_COUNT
+  KC_SETUP = 0, KC_FRONT_SMALL, KC_LARGE_TILES, KC_FWD_SWEEP, KC_BWD_SWEEP, KC_RESIDUAL, KC_GRADIENT,
+  KC_COUNT
 };
 extern const char* const kKernelClassNames[KC_COUNT];
 
@@ -88,10 +76,9 @@ struct Plan {
   size_t csize = 16;           // bytes of one factor scalar (complex)
   DevTables t;
   std::vector<LevelPlan> levels;
-  int32_t nb_large = 64;       // block width of the large-front path
-  int32_t tile_trsm = 64;      // rows per trsm task
-  int32_t tile_upd = 64;       // update tile edge
-  int32_t nmslot = 0;
+  int32_t ntile_tasks = 0;     // tasks of the tile graph (one system)
+  int32_t ntiles = 0;          // packed tiles of the tiled fronts (one system)
+  double tiled_flops = 0;      // partial-LDL^T flops of the tiled fronts (one system)
   size_t solve_lds_max = 0;
   int32_t small_prefix = 0;    // leading levels run by one persistent small-front launch
   size_t small_lds_prefix = 0;
@@ -103,7 +90,6 @@ struct Plan {
   // arenas (device)
   void* fac = nullptr;         // nsys * fac_total scalars
   void* upd = nullptr;         // nsys * upd_total scalars
-  void* mscr = nullptr;        // nsys * nmslot * nb^2 scalars (trsm multipliers)
   double2* pml = nullptr;      // nsys * (2nx + 2ny + 2)
   double* omega = nullptr;     // nsys
   double* eps = nullptr;       // nsys * N (copy taken at refactor)
@@ -116,11 +102,19 @@ struct Plan {
   DevStatus* status = nullptr;
   int32_t* counters = nullptr;  // [0..1] persistent-queue counters, [2] residual blocks
   int32_t* done = nullptr;      // [nsys][nfronts] completion epochs
+  int32_t* tile_state = nullptr;  // [nsys][ntiles] tile versions
+  int32_t* tile_done = nullptr;   // [nsys][nfronts] finished update tiles
   int32_t epoch = 0;            // last epoch handed to a persistent launch
   DevStatus* status_host = nullptr;  // pinned
   int64_t device_bytes = 0;
   std::vector<void*> allocations;
 
+  // task traces (FDFD_TRACE=<file>): 0 small fronts, 1 tile graph, 2 fwd, 3 bwd sweep
+  long long* trace_buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t trace_cap[4] = {0, 0, 0, 0};
+  int32_t trace_n[4] = {0, 0, 0, 0};
+  std::string trace_path;
+  std::vector<int32_t> tile_tasks_host;
   // FDFD_PROFILE
   bool profile = false;
   std::vector<hipEvent_t> event_pool;

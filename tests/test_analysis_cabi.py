@@ -99,7 +99,7 @@ def test_analysis_matches_brute_force_elimination(lib, nx, ny, leaf):
 
 
 def test_analysis_statistics_match_estimator(lib):
-    """The 300 x 300 grid with 64-cell leaves reproduces the survey estimator:
+    """The 300 x 300 grid with 64-cell leaves reproduces the nested-dissection estimate:
     3373 fronts, 12 levels, nnz(L) = 5.78e6, 2.57e9 refactor flops."""
     P = F.Plan(300, 300, 20, host_only=True, leaf=64)
     info = P.query()
