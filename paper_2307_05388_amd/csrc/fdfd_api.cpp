@@ -148,7 +148,10 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       L.max_m = std::max(L.max_m, A.m(f));
       L.max_p = std::max(L.max_p, A.npiv[f]);
       L.max_u = std::max(L.max_u, A.nupd[f]);
-      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f] + 256) * cs);
+      // panel, d, 1/d, then the dense routines' scratch: 16 x 16 for the inverse
+      // blocks, 16 x (p - 16) for the d-scaled columns of the trailing update
+      const size_t scratch = std::max<size_t>(256, 16 * (size_t)std::max(0, A.npiv[f] - 16));
+      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f] + scratch) * cs);
       L.lbytes += P.front_lbytes[f];
     }
     // the one-workgroup kernel keeps at most 64 pivot columns (16 per wave)
@@ -300,7 +303,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.lds_limit = (size_t)lds_limit;
   const size_t cs = P.csize;
   // the tile kernels need the diagonal task's 64 x 64 block in LDS
-  if ((size_t)(64 * 64 + 2 * 64 + 256) * cs > (size_t)lds_limit - 512) {
+  if ((size_t)(64 * 64 + 2 * 64 + 1024) * cs > (size_t)lds_limit - 512) {
     delete h;
     return fail(nullptr, FDFD_ERR_HIP, "device LDS too small for 64-wide front blocks");
   }

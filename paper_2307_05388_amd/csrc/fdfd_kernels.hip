@@ -37,11 +37,11 @@ template <typename C> __device__ __forceinline__ C cfms(C acc, C a, C b) {
   return acc;
 }
 template <typename C> __device__ __forceinline__ C cinv(C d) {
-  const auto s = d.x * d.x + d.y * d.y;
-  C r;
-  r.x = d.x / s;
-  r.y = -d.y / s;
-  return r;
+  const auto r = 1 / (d.x * d.x + d.y * d.y);
+  C o;
+  o.x = d.x * r;
+  o.y = -d.y * r;
+  return o;
 }
 template <typename C> __device__ __forceinline__ C from_d2(double2 v) {
   C r;
@@ -145,20 +145,20 @@ __device__ __forceinline__ C front_entry(const KArgs& a, int s, int f, int p, in
 }
 
 // Static pivot perturbation: |d| < thr becomes d (1 + thr/|d|) (thr if d = 0).
+// The test uses |d|^2 against thr^2, so a square root is taken only when a
+// pivot is perturbed; min2 tracks the smallest |d|^2 seen.
 template <typename C>
-__device__ __forceinline__ C fix_pivot(C d, double thr, double anorm, int& npert, double& minr,
-                                       int& nonfin) {
-  const double ad = hypot((double)d.x, (double)d.y);
-  if (!(ad <= DBL_MAX)) nonfin = 1;
-  const double ratio = anorm > 0 ? ad / anorm : ad;
-  minr = fmin(minr, ratio);
-  if (ad < thr) {
+__device__ __forceinline__ C fix_pivot(C d, double thr, double anorm, int& npert, double& min2, int& nonfin) {
+  const double a2 = (double)d.x * d.x + (double)d.y * d.y;
+  if (!(a2 <= DBL_MAX)) nonfin = 1;
+  min2 = fmin(min2, a2);
+  if (a2 < thr * thr) {
     ++npert;
-    if (ad == 0.0) {
+    if (a2 == 0.0) {
       d.x = (decltype(d.x))thr;
       d.y = 0;
     } else {
-      const double g = 1.0 + thr / ad;
+      const double g = 1.0 + thr / sqrt(a2);
       d.x = (decltype(d.x))(d.x * g);
       d.y = (decltype(d.y))(d.y * g);
     }
@@ -166,11 +166,14 @@ __device__ __forceinline__ C fix_pivot(C d, double thr, double anorm, int& npert
   return d;
 }
 
-__device__ __forceinline__ void record_pivots(DevStatus* st, int npert, double minr, int nonfin) {
+// min2: smallest |d|^2 of the pivots examined by this thread (INFINITY if none).
+__device__ __forceinline__ void record_pivots(DevStatus* st, int npert, double min2, int nonfin, double anorm) {
   if (npert) atomicAdd(&st->n_perturbed, npert);
   if (nonfin) atomicExch(&st->nonfinite, 1);
-  if (minr < INFINITY)
-    atomicMin(&st->min_ratio_bits, (unsigned long long)__double_as_longlong(minr));
+  if (min2 < INFINITY) {
+    const double ratio = anorm > 0 ? sqrt(min2) / anorm : sqrt(min2);
+    atomicMin(&st->min_ratio_bits, (unsigned long long)__double_as_longlong(ratio));
+  }
 }
 
 __device__ __forceinline__ double anorm_of(const KArgs& a, int s) {
@@ -344,12 +347,13 @@ template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
 }
 
 // LDL^T of the b x b (b <= 16) diagonal sub-block at (o, o), by wave 0 alone:
-// lane l holds row l in registers and the pivot column travels by shuffles,
-// so no barrier is needed.  Leaves the unit-lower L (scaled) in place and
-// d, 1/d in dd / invd; lane 0 keeps the pivot statistics.
+// lane l holds row l in registers; each step the lanes publish their entry of
+// the pivot column to colbuf and read it back as broadcasts (one wave, so the
+// LDS accesses stay in order without a barrier).  Leaves the unit-lower L
+// (scaled) in place and d, 1/d in dd / invd; lane 0 keeps the statistics.
 template <typename C>
-__device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, double thr, double anorm, int& npert,
-                          double& minr, int& nonfin) {
+__device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, C* colbuf, double thr, double anorm,
+                          int& npert, double& minr, int& nonfin) {
   const int l = threadIdx.x;
   C row[16];
 #pragma unroll
@@ -357,9 +361,14 @@ __device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, double thr
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     if (k < b) {
+      if (l < 16) colbuf[l] = row[k];
+      __builtin_amdgcn_wave_barrier();
+      C cj[16];
+#pragma unroll
+      for (int j = k; j < 16; ++j) cj[j] = colbuf[j];
       int np = 0, nf = 0;
       double mr = INFINITY;
-      const C d = fix_pivot(shfl_c(row[k], k), thr, anorm, np, mr, nf);
+      const C d = fix_pivot(cj[k], thr, anorm, np, mr, nf);
       const C inv = cinv(d);
       if (l == 0) {
         npert += np;
@@ -370,11 +379,10 @@ __device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, double thr
       }
       const C lk = cmul(row[k], inv);
 #pragma unroll
-      for (int j = k + 1; j < 16; ++j) {
-        const C fjk = shfl_c(row[k], j);
-        if (j < b && l >= j) row[j] = cfms(row[j], lk, fjk);
-      }
+      for (int j = k + 1; j < 16; ++j)
+        if (j < b && l >= j) row[j] = cfms(row[j], lk, cj[j]);
       if (l > k) row[k] = lk;
+      __builtin_amdgcn_wave_barrier();
     }
   }
   if (l < b) {
@@ -406,19 +414,27 @@ __device__ void trsm_rows16(C* F, int ld, int o, int b, int r0, int m, const C* 
 }
 
 // Trailing update of the panel columns c in [c0, p), rows r >= c:
-// F[r][c] -= sum_q L[r][o+q] d_q L[c][o+q].  Wave w takes columns c0+w, c0+w+4, ...
+// F[r][c] -= sum_q L[r][o+q] d_q L[c][o+q].  The d-scaled columns go to Lsc
+// first; then lane = row (its 16 L values in registers), wave w takes the
+// columns c0+w, c0+w+4, ... and reads their scaled rows as broadcasts.
 template <typename C>
-__device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const C* dd) {
+__device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const C* dd, C* Lsc) {
+  for (int idx = threadIdx.x; idx < (p - c0) * 16; idx += kThreads) {
+    const int c = c0 + (idx >> 4), q = idx & 15;
+    Lsc[idx] = q < b ? cmul(F[(o + q) * ld + c], dd[o + q]) : czero<C>();
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = c0 + wave; c < p; c += 4) {
-    C lc[16];
+  for (int r = c0 + lane; r < m; r += 64) {
+    C lr[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lc[q] = q < b ? cmul(F[(o + q) * ld + c], dd[o + q]) : czero<C>();
-    for (int r = c + lane; r < m; r += 64) {
+    for (int q = 0; q < 16; ++q) lr[q] = q < b ? F[(o + q) * ld + r] : czero<C>();
+    const int cend = min(p, r + 1);
+    for (int c = c0 + wave; c < cend; c += 4) {
+      const C* sc = Lsc + (c - c0) * 16;
       C acc = F[c * ld + r];
 #pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q < b) acc = cfms(acc, F[(o + q) * ld + r], lc[q]);
+      for (int q = 0; q < 16; ++q) acc = cfms(acc, lr[q], sc[q]);
       F[c * ld + r] = acc;
     }
   }
@@ -428,17 +444,18 @@ __device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const 
 // panel: per 16-column sub-block, wave 0 factors the diagonal sub-block, all
 // threads solve the rows below it and update the remaining panel columns.
 // Leaves the unit-lower L in place and d, 1/d in dd / invd.
+// scratch: 16 x 64 entries of LDS (pivot column buffer, scaled columns).
 template <typename C>
-__device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, double thr, double anorm, int& npert,
-                            double& minr, int& nonfin) {
+__device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scratch, double thr, double anorm,
+                            int& npert, double& minr, int& nonfin) {
   for (int o = 0; o < p; o += 16) {
     const int b = min(16, p - o);
-    if (threadIdx.x < 64) ldl_sub16(F, ld, o, b, dd, invd, thr, anorm, npert, minr, nonfin);
+    if (threadIdx.x < 64) ldl_sub16(F, ld, o, b, dd, invd, scratch, thr, anorm, npert, minr, nonfin);
     __syncthreads();
     trsm_rows16(F, ld, o, b, o + b, m, invd);
     __syncthreads();
     if (o + b < p) {
-      trail16(F, ld, o, b, o + b, p, m, dd);
+      trail16(F, ld, o, b, o + b, p, m, dd, scratch);
       __syncthreads();
     }
   }
@@ -449,7 +466,7 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, double t
 // off-diagonal sub-blocks follow in ascending block columns and rows,
 // X_ij = -X_ii sum_{j<=k<i} L_ik X_kj, through the 16 x 16 scratch T.
 template <typename C>
-__device__ void invert_blocked(C* F, int ld, int nb, C* T) {
+__device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsb = (nb + 15) / 16;
   if (wave < nsb) {
@@ -478,32 +495,38 @@ __device__ void invert_blocked(C* F, int ld, int nb, C* T) {
   for (int jb = 0; jb + 1 < nsb; ++jb) {
     for (int ib = jb + 1; ib < nsb; ++ib) {
       const int ri = 16 * ib, cj = 16 * jb, bi = min(16, nb - ri), bj = min(16, nb - cj);
-      if (r < bi && c < bj) {
-        C acc = czero<C>();
-        for (int kb = jb; kb < ib; ++kb) {
-          const int rk = 16 * kb, bk = min(16, nb - rk);
-          for (int q = 0; q < bk; ++q) {
-            C xv;
-            if (kb == jb) {
-              if (q < c) continue;
-              if (q == c) {
-                xv = czero<C>();
-                xv.x = 1;
-              } else {
-                xv = F[(cj + c) * ld + rk + q];
-              }
-            } else {
-              xv = F[(cj + c) * ld + rk + q];
+      // every lane computes (clamped addresses); only r < bi, c < bj store
+      const int rr = min(r, bi - 1), cc = min(c, bj - 1);
+      C acc = czero<C>();
+      for (int kb = jb; kb < ib; ++kb) {
+        const int rk = 16 * kb, bk = min(16, nb - rk);
+        const bool diag = kb == jb;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          if (q < bk) {  // uniform across the workgroup
+            // X_{kb,jb}[q][c]: unit lower on the diagonal block
+            const C st = F[(cj + cc) * ld + rk + q];
+            C xv = st;
+            if (diag) {
+              xv.x = q > c ? st.x : (q == c ? 1 : 0);
+              xv.y = q > c ? st.y : 0;
             }
-            acc = cadd(acc, cmul(F[(rk + q) * ld + ri + r], xv));
+            acc = cadd(acc, cmul(F[(rk + q) * ld + ri + rr], xv));
           }
         }
-        T[r * 16 + c] = acc;
       }
+      if (r < bi && c < bj) T[r * 16 + c] = acc;
       __syncthreads();
       if (r < bi && c < bj) {
-        C v = T[r * 16 + c];
-        for (int q = 0; q < r; ++q) v = cadd(v, cmul(F[(ri + q) * ld + ri + r], T[q * 16 + c]));
+        C v = czero<C>();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const C xl = F[(ri + q) * ld + ri + r];
+          C xv;
+          xv.x = q < r ? xl.x : (q == r ? 1 : 0);
+          xv.y = q < r ? xl.y : 0;
+          if (q < bi) v = cadd(v, cmul(xv, T[q * 16 + c]));
+        }
         v.x = -v.x;
         v.y = -v.y;
         F[(cj + c) * ld + ri + r] = v;
@@ -526,7 +549,7 @@ __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_ra
   C* F = reinterpret_cast<C*>(smem_raw);
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
   C* dd = F + (int64_t)m * p;
-  C* invd = dd + p;  // followed by a 16 x 16 scratch for the inverse
+  C* invd = dd + p;  // followed by max(16 x 16, 16 x (p - 16)) entries of scratch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   for (int c = wave; c < p; c += 4)
@@ -537,7 +560,7 @@ __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_ra
   const double thr = a.tau * anorm;
   int npert = 0, nonfin = 0;
   double minr = INFINITY;
-  ldl_blocked(F, m, m, p, dd, invd, thr, anorm, npert, minr, nonfin);
+  ldl_blocked(F, m, m, p, dd, invd, invd + p, thr, anorm, npert, minr, nonfin);
 
   // Schur complement: U = F22 - L_u D L_u^T over the update rows.
   C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
@@ -590,7 +613,7 @@ __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_ra
       else if (r == c) v = dd[c];
       L[(int64_t)c * m + r] = v;
     }
-  if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin);
+  if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
 }
 
 // Persistent launch over fronts order[0 .. ntasks/nsys): with q.wait set, a
@@ -746,7 +769,7 @@ __device__ void task_diag(const KArgs& a, int s, int f, int k, unsigned char* sm
   C* B = reinterpret_cast<C*>(smem);  // kBW x kBW, column major
   C* dd = B + kBW * kBW;
   C* invd = dd + kBW;
-  C* T = invd + kBW;  // 16 x 16
+  C* T = invd + kBW;  // 16 x 64 scratch
   const int p = a.npiv[f], m = p + a.nupd[f];
   const int k0 = k * kBW, nb = min(kBW, p - k0);
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m + k0;
@@ -758,11 +781,11 @@ __device__ void task_diag(const KArgs& a, int s, int f, int k, unsigned char* sm
   const double thr = a.tau * anorm;
   int npert = 0, nonfin = 0;
   double minr = INFINITY;
-  ldl_blocked(B, kBW, nb, nb, dd, invd, thr, anorm, npert, minr, nonfin);
+  ldl_blocked(B, kBW, nb, nb, dd, invd, T, thr, anorm, npert, minr, nonfin);
   invert_blocked(B, kBW, nb, T);
   for (int c = wave; c < nb; c += 4)
     for (int r = c + lane; r < nb; r += 64) L[(int64_t)c * m + r] = (r > c) ? B[c * kBW + r] : dd[c];
-  if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin);
+  if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
 }
 
 // tile (I,k) <- F_Ik Xinv^T D^-1: out[r][j] = sum_{q<=j} F[r][q] Xinv[j][q] / d_j
@@ -1423,7 +1446,7 @@ unsigned persistent_grid(const Plan& P, size_t lds, int ntasks) {
 // LDS of the task-graph kernel: the diagonal task's block and pivots, or the
 // two 16-deep operand panels of the tile products, whichever is larger.
 size_t tile_lds(const Plan& P) {
-  const size_t diag = (size_t)(kBW * kBW + 2 * kBW + 256);
+  const size_t diag = (size_t)(kBW * kBW + 2 * kBW + 1024);
   const size_t gemm = (size_t)(2 * 16 * kBW);
   return (diag > gemm ? diag : gemm) * P.csize;
 }
