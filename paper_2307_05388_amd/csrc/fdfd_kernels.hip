@@ -117,31 +117,60 @@ __device__ __forceinline__ double2 sym_scale(const KArgs& a, int s, int n) {
 // Entry (r, c), r >= c, of front f before elimination: the original entry of
 // S*A (only in pivot columns) plus the children's update blocks (extend-add in
 // gather form: every entry reads its contributions, fixed child order).
+// Original (symmetrised) operator entries of the pivot columns [c0, c0 + nc)
+// of front f, one thread per column, staged for the assembly loops:
+// sv[5 t] = diagonal, sv[5 t + 1 + d] = coupling to neighbour d (x-1, x+1,
+// y-1, y+1), nb[4 t + d] = that neighbour's front row (-1 if not in the front).
 template <typename C>
-__device__ __forceinline__ C front_entry(const KArgs& a, int s, int f, int p, int m, int r, int c) {
-  C val = czero<C>();
-  if (c < p) {
-    const int q = a.pbeg[f] + c;
-    if (r == c) {
-      val = from_d2<C>(stencil_at(a, s, a.perm[q]).diag);
-    } else {
-      const int32_t* nr = a.nbr_row + 4 * (int64_t)q;
-      for (int d = 0; d < 4; ++d)
-        if (nr[d] == r) val = from_d2<C>(stencil_at(a, s, a.perm[q]).c[d]);
+__device__ void stage_columns(const KArgs& a, int s, int f, int c0, int nc, C* sv, int* nb) {
+  for (int t = threadIdx.x; t < nc; t += kThreads) {
+    const int q = a.pbeg[f] + c0 + t;
+    const Stencil S = stencil_at(a, s, a.perm[q]);
+    sv[5 * t] = from_d2<C>(S.diag);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      sv[5 * t + 1 + d] = from_d2<C>(S.c[d]);
+      nb[4 * t + d] = a.nbr_row[4 * (int64_t)q + d];
     }
   }
+}
+
+// Entry (r, c) of the original matrix from staged column t (= c - c0).
+template <typename C>
+__device__ __forceinline__ C staged_entry(const C* sv, const int* nb, int t, int r, int c) {
+  C v = czero<C>();
+  if (r == c) v = sv[5 * t];
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    if (nb[4 * t + d] == r) v = sv[5 * t + 1 + d];
+  return v;
+}
+
+// Extend-add, gather form: adds the children's update-matrix entries that map
+// to front entries (rr[e], cc[e]) (rr[e] >= cc[e]; rr[e] < 0 marks an unused
+// slot).  The loads of all NB entries are issued together, child by child.
+template <typename C, int NB>
+__device__ __forceinline__ void add_children(const KArgs& a, int s, int f, int m, const int (&rr)[NB],
+                                             const int (&cc)[NB], C (&val)[NB]) {
   const int cb = a.child_ptr[f], ce = a.child_ptr[f + 1];
   const int32_t* g = a.gmap + a.gmap_ptr[f];
   const C* U = (const C*)a.upd + (int64_t)s * a.upd_total;
   for (int k = cb; k < ce; ++k, g += m) {
-    const int gr = g[r];
-    if (gr < 0) continue;
-    const int gc = g[c];
-    if (gc < 0) continue;
     const int ch = a.child_list[k];
-    val = cadd(val, U[a.upd_off[ch] + (int64_t)gc * a.nupd[ch] + gr]);
+    const C* Uc = U + a.upd_off[ch];
+    const int nu = a.nupd[ch];
+    int gr[NB], gc[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      gr[e] = rr[e] >= 0 ? g[rr[e]] : -1;
+      gc[e] = rr[e] >= 0 ? g[cc[e]] : -1;
+    }
+    C v[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) v[e] = (gr[e] >= 0 && gc[e] >= 0) ? Uc[(int64_t)gc[e] * nu + gr[e]] : czero<C>();
+#pragma unroll
+    for (int e = 0; e < NB; ++e) val[e] = cadd(val[e], v[e]);
   }
-  return val;
 }
 
 // Static pivot perturbation: |d| < thr becomes d (1 + thr/|d|) (thr if d = 0).
@@ -329,7 +358,15 @@ __device__ __forceinline__ void wait_parent(const Queue& q, const KArgs& a, int 
   __syncthreads();
 }
 
+// Every wave waits until its global stores are acknowledged by L2 before the
+// barrier; the one agent-scope release by thread 0 then writes L2 back for all
+// of them (a workgroup barrier alone does not wait for other waves' stores).
+__device__ __forceinline__ void drain_stores() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained (gfx9 encoding)
+}
+
 __device__ __forceinline__ void publish(const Queue& q, int64_t idx) {
+  drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(q.done + idx, q.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -346,22 +383,25 @@ template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
   return v;
 }
 
-// LDL^T of the b x b (b <= 16) diagonal sub-block at (o, o), by wave 0 alone:
-// lane l holds row l in registers; each step the lanes publish their entry of
-// the pivot column to colbuf and read it back as broadcasts (one wave, so the
-// LDS accesses stay in order without a barrier).  Leaves the unit-lower L
-// (scaled) in place and d, 1/d in dd / invd; lane 0 keeps the statistics.
+// LDL^T of the b x b (b <= 16) diagonal sub-block at (o, o) together with the
+// rows below it up to row 63, by wave 0 alone: lane l holds row l of the
+// sub-block's columns in registers.  Each step the lanes of the sub-block
+// publish their entry of the pivot column to colbuf and every lane reads it
+// back as broadcasts (one wave, so the LDS accesses stay in order without a
+// barrier).  Leaves the unit-lower L (scaled) in place for rows < min(m, 64)
+// and d, 1/d in dd / invd; lane 0 keeps the statistics.
 template <typename C>
-__device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, C* colbuf, double thr, double anorm,
+__device__ void ldl_sub16(C* F, int ld, int o, int b, int m, C* dd, C* invd, C* colbuf, double thr, double anorm,
                           int& npert, double& minr, int& nonfin) {
   const int l = threadIdx.x;
+  const bool act = l >= o && l < m;
   C row[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) row[q] = (l < b && q < b && q <= l) ? F[(o + q) * ld + o + l] : czero<C>();
+  for (int q = 0; q < 16; ++q) row[q] = (act && q < b && o + q <= l) ? F[(o + q) * ld + l] : czero<C>();
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     if (k < b) {
-      if (l < 16) colbuf[l] = row[k];
+      if (l >= o && l < o + 16) colbuf[l - o] = row[k];
       __builtin_amdgcn_wave_barrier();
       C cj[16];
 #pragma unroll
@@ -380,15 +420,15 @@ __device__ void ldl_sub16(C* F, int ld, int o, int b, C* dd, C* invd, C* colbuf,
       const C lk = cmul(row[k], inv);
 #pragma unroll
       for (int j = k + 1; j < 16; ++j)
-        if (j < b && l >= j) row[j] = cfms(row[j], lk, cj[j]);
-      if (l > k) row[k] = lk;
+        if (j < b && l >= o + j) row[j] = cfms(row[j], lk, cj[j]);
+      if (l > o + k) row[k] = lk;
       __builtin_amdgcn_wave_barrier();
     }
   }
-  if (l < b) {
+  if (act) {
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-      if (q < l) F[(o + q) * ld + o + l] = row[q];
+      if (q < b && o + q < l) F[(o + q) * ld + l] = row[q];
   }
 }
 
@@ -450,10 +490,12 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scrat
                             int& npert, double& minr, int& nonfin) {
   for (int o = 0; o < p; o += 16) {
     const int b = min(16, p - o);
-    if (threadIdx.x < 64) ldl_sub16(F, ld, o, b, dd, invd, scratch, thr, anorm, npert, minr, nonfin);
+    if (threadIdx.x < 64) ldl_sub16(F, ld, o, b, m, dd, invd, scratch, thr, anorm, npert, minr, nonfin);
     __syncthreads();
-    trsm_rows16(F, ld, o, b, o + b, m, invd);
-    __syncthreads();
+    if (m > 64) {
+      trsm_rows16(F, ld, o, b, 64, m, invd);
+      __syncthreads();
+    }
     if (o + b < p) {
       trail16(F, ld, o, b, o + b, p, m, dd, scratch);
       __syncthreads();
@@ -544,7 +586,7 @@ __device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
 // diagonal.
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_raw) {
+__device__ void small_front(const KArgs& a, const Queue& q, int s, int f, unsigned char* smem_raw) {
   typedef typename Cx<R>::T C;
   C* F = reinterpret_cast<C*>(smem_raw);
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
@@ -552,9 +594,34 @@ __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_ra
   C* invd = dd + p;  // followed by max(16 x 16, 16 x (p - 16)) entries of scratch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  for (int c = wave; c < p; c += 4)
-    for (int r = lane; r < m; r += 64) F[c * m + r] = (r >= c) ? front_entry<C>(a, s, f, p, m, r, c) : czero<C>();
-  __syncthreads();
+  {
+    // the d / 1/d / scratch area is free until the factorisation starts
+    C* sv = dd;
+    int* nbv = reinterpret_cast<int*>(dd + 5 * p);
+    stage_columns(a, s, f, 0, p, sv, nbv);
+    __syncthreads();
+    // four columns per wave and batch (c, c+4, c+8, c+12), lane = row
+    for (int cb = wave; cb < p; cb += 16)
+      for (int r = lane; r < m; r += 64) {
+        int rr[4], cc[4];
+        C v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = cb + 4 * e;
+          const bool ok = c < p && r >= c;
+          rr[e] = ok ? r : -1;
+          cc[e] = c;
+          v[e] = ok ? staged_entry(sv, nbv, c, r, c) : czero<C>();
+        }
+        add_children<C, 4>(a, s, f, m, rr, cc, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = cb + 4 * e;
+          if (c < p) F[c * m + r] = v[e];
+        }
+      }
+    __syncthreads();
+  }
 
   const double anorm = anorm_of(a, s);
   const double thr = a.tau * anorm;
@@ -591,19 +658,30 @@ __device__ void small_front(const KArgs& a, int s, int f, unsigned char* smem_ra
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
       }
+      // children's contributions to the update block, eight entries per batch
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int c = tj + tc + 16 * y;
+      for (int yh = 0; yh < 4; yh += 2) {
+        int rr[8], cc[8];
+        C v[8];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int r = ti + tr + 16 * x;
-          if (r < u && c < u && r >= c)
-            U[(int64_t)c * u + r] = csub(front_entry<C>(a, s, f, p, m, p + r, p + c), acc[x][y]);
+        for (int e = 0; e < 8; ++e) {
+          const int r = ti + tr + 16 * (e & 3), c = tj + tc + 16 * (yh + (e >> 2));
+          rr[e] = (r < u && c < u && r >= c) ? p + r : -1;
+          cc[e] = p + c;
+          v[e] = czero<C>();
         }
+        add_children<C, 8>(a, s, f, m, rr, cc, v);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (rr[e] >= 0) {
+            const int r = rr[e] - p, c = cc[e] - p;
+            U[(int64_t)c * u + r] = csub(v[e], acc[e & 3][yh + (e >> 2)]);
+          }
       }
     }
   }
-  __syncthreads();
+  // the parent needs only the update block: release it before the inverse
+  publish(q, s * a.nfronts + f);
   invert_blocked(F, m, p, invd + p);
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   for (int c = wave; c < p; c += 4)
@@ -628,8 +706,7 @@ __global__ __launch_bounds__(kThreads) void k_front_small(KArgs a, Queue q, cons
     const int f = order[t / a.nsys], s = t % a.nsys;
     if (q.wait) wait_children(q, a, s, f);
     trace_mark(q, t, 1);
-    small_front<R>(a, s, f, smem_raw);
-    publish(q, s * a.nfronts + f);
+    small_front<R>(a, q, s, f, smem_raw);
     trace_mark(q, t, 2);
   }
   leave(q);
@@ -749,15 +826,37 @@ __device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, in
 }
 
 template <typename R>
-__device__ void task_asm(const KArgs& a, int s, int f, int I, int J) {
+__device__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int r0 = ch.lo(I), r1 = ch.hi(I), c0 = ch.lo(J), c1 = ch.hi(J);
   const int nr = r1 - r0, nc = c1 - c0;
-  for (int idx = threadIdx.x; idx < nr * nc; idx += kThreads) {
-    const int c = c0 + idx / nr, r = r0 + idx % nr;
-    if (r >= c) *front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c) = front_entry<C>(a, s, f, ch.p, ch.m, r, c);
-    else if (c < ch.p) *front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c) = czero<C>();
+  const bool piv = c0 < ch.p;  // pivot chunks hold original entries
+  C* sv = reinterpret_cast<C*>(smem);
+  int* nbv = reinterpret_cast<int*>(sv + 5 * kBW);
+  if (piv) stage_columns(a, s, f, c0, nc, sv, nbv);
+  __syncthreads();
+  // lane = row, wave w takes the columns w, w+4, ...: four per batch
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = r0 + lane;
+#pragma unroll 1
+  for (int tb = 0; tb < 16; tb += 4) {
+    int rr[4], cc[4];
+    C v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int t = wave + 4 * (tb + e), c = c0 + t;
+      const bool ok = lane < nr && t < nc && r >= c;
+      rr[e] = ok ? r : -1;
+      cc[e] = c;
+      v[e] = (ok && piv) ? staged_entry(sv, nbv, t, r, c) : czero<C>();
+    }
+    add_children<C, 4>(a, s, f, ch.m, rr, cc, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int t = wave + 4 * (tb + e), c = c0 + t;
+      if (lane < nr && t < nc && (r >= c || piv)) *front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c) = v[e];
+    }
   }
 }
 
@@ -897,7 +996,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     trace_mark(q, t, 1);
     int tile = 0, ver = 0;
     if (type == T_ASM) {
-      task_asm<R>(a, s, f, I, J);
+      task_asm<R>(a, s, f, I, J, smem_raw);
       tile = tile_id(I, J);
       ver = 1;
     } else if (type == T_DIAG) {
@@ -913,6 +1012,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
       tile = tile_id(I, J);
       ver = k + 2;
     }
+    drain_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
       __hip_atomic_store(st + tile, ver, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
