@@ -210,6 +210,13 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
           for (int I = J; I < R; ++I) push(3, f, k, I, J);
       }
     }
+    // INV(k) after the level's steps: the rest of each pivot block's inverse,
+    // once step k's TRSM tasks are done (the last block with no TRSM inverts in DIAG)
+    for (int q = L.first; q < L.first + L.count; ++q) {
+      const int f = A.level_fronts[q];
+      const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
+      for (int k = 0; k < nbk && k < R - 1; ++k) push(4, f, k, k, k);
+    }
   }
   P.ntile_tasks = (int32_t)(tasks.size() / 5);
 }
@@ -303,7 +310,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.lds_limit = (size_t)lds_limit;
   const size_t cs = P.csize;
   // the tile kernels need the diagonal task's 64 x 64 block in LDS
-  if ((size_t)(64 * 64 + 2 * 64 + 1024) * cs > (size_t)lds_limit - 512) {
+  if (fdfd::tile_lds_entries() * cs > (size_t)lds_limit - 512) {
     delete h;
     return fail(nullptr, FDFD_ERR_HIP, "device LDS too small for 64-wide front blocks");
   }

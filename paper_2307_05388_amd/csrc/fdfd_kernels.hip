@@ -503,12 +503,13 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scrat
   }
 }
 
-// In-place inverse of the unit-lower nb x nb (nb <= 64) block at F: each wave
-// inverts one 16 x 16 diagonal sub-block (lane j builds column j), then the
-// off-diagonal sub-blocks follow in ascending block columns and rows,
-// X_ij = -X_ii sum_{j<=k<i} L_ik X_kj, through the 16 x 16 scratch T.
+// In-place inverse of the unit-lower nb x nb (nb <= 64) block at F, in two
+// parts.  invert_diag16: each wave inverts one 16 x 16 diagonal sub-block
+// (lane j builds column j).  invert_offdiag: the off-diagonal sub-blocks in
+// ascending block columns and rows, X_ij = -X_ii sum_{j<=k<i} L_ik X_kj,
+// through the 16 x 16 scratch T (reads the X_ii left by invert_diag16).
 template <typename C>
-__device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
+__device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsb = (nb + 15) / 16;
   if (wave < nsb) {
@@ -533,6 +534,11 @@ __device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
     }
   }
   __syncthreads();
+}
+
+template <typename C>
+__device__ __forceinline__ void invert_offdiag(C* F, int ld, int nb, C* T) {
+  const int nsb = (nb + 15) / 16;
   const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
   for (int jb = 0; jb + 1 < nsb; ++jb) {
     for (int ib = jb + 1; ib < nsb; ++ib) {
@@ -576,6 +582,12 @@ __device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
       __syncthreads();
     }
   }
+}
+
+template <typename C>
+__device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
+  invert_diag16(F, ld, nb);
+  invert_offdiag(F, ld, nb, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -735,7 +747,7 @@ struct TileArgs {
   int32_t ntiles;
 };
 
-enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3 };
+enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3, T_INV = 4 };
 
 struct Chunks {
   int p, u, m, nbk, nut;
@@ -826,7 +838,7 @@ __device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, in
 }
 
 template <typename R>
-__device__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
+__device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int r0 = ch.lo(I), r1 = ch.hi(I), c0 = ch.lo(J), c1 = ch.hi(J);
@@ -860,10 +872,17 @@ __device__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned ch
   }
 }
 
-// DIAG(k): LDL^T of the nb x nb pivot block and the in-place inverse of its
-// unit-lower factor, both blocked by 16 (see ldl_blocked / invert_blocked).
+// DIAG(k): LDL^T of the nb x nb pivot block, blocked by 16, and the inverses
+// of its 16 x 16 diagonal sub-blocks in place of theirs (what the TRSM tasks
+// of step k use).  When no TRSM follows (last pivot block of a front without
+// update rows) the off-diagonal sub-blocks are inverted here too (kDiagFull);
+// otherwise INV(k) (kInvOnly) turns them into those of L_kk^-1 once every TRSM
+// of step k has read them.  The forward and backward sweeps apply the whole
+// inverse.  One routine for both task types keeps a single inlined copy.
+enum { kDiagPart = 0, kDiagFull = 1, kInvOnly = 2 };
+
 template <typename R>
-__device__ void task_diag(const KArgs& a, int s, int f, int k, unsigned char* smem) {
+__device__ __forceinline__ void task_diag(const KArgs& a, int s, int f, int k, int mode, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   C* B = reinterpret_cast<C*>(smem);  // kBW x kBW, column major
   C* dd = B + kBW * kBW;
@@ -873,60 +892,106 @@ __device__ void task_diag(const KArgs& a, int s, int f, int k, unsigned char* sm
   const int k0 = k * kBW, nb = min(kBW, p - k0);
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m + k0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool inv_only = mode == kInvOnly;
   for (int c = wave; c < nb; c += 4)
-    for (int r = lane; r < nb; r += 64) B[c * kBW + r] = (r >= c) ? L[(int64_t)c * m + r] : czero<C>();
+    for (int r = lane; r < nb; r += 64)
+      B[c * kBW + r] = (inv_only ? r > c : r >= c) ? L[(int64_t)c * m + r] : czero<C>();
   __syncthreads();
-  const double anorm = anorm_of(a, s);
-  const double thr = a.tau * anorm;
+  double anorm = 0.0;
   int npert = 0, nonfin = 0;
   double minr = INFINITY;
-  ldl_blocked(B, kBW, nb, nb, dd, invd, T, thr, anorm, npert, minr, nonfin);
-  invert_blocked(B, kBW, nb, T);
-  for (int c = wave; c < nb; c += 4)
-    for (int r = c + lane; r < nb; r += 64) L[(int64_t)c * m + r] = (r > c) ? B[c * kBW + r] : dd[c];
-  if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
+  if (!inv_only) {
+    anorm = anorm_of(a, s);
+    ldl_blocked(B, kBW, nb, nb, dd, invd, T, a.tau * anorm, anorm, npert, minr, nonfin);
+    invert_diag16(B, kBW, nb);
+  }
+  if (mode != kDiagPart) invert_offdiag(B, kBW, nb, T);
+  if (inv_only) {
+    for (int c = wave; c < nb; c += 4)
+      if (lane < nb && (lane >> 4) > (c >> 4)) L[(int64_t)c * m + lane] = B[c * kBW + lane];
+  } else {
+    for (int c = wave; c < nb; c += 4)
+      for (int r = c + lane; r < nb; r += 64) L[(int64_t)c * m + r] = (r > c) ? B[c * kBW + r] : dd[c];
+    if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
+  }
 }
 
-// tile (I,k) <- F_Ik Xinv^T D^-1: out[r][j] = sum_{q<=j} F[r][q] Xinv[j][q] / d_j
+// TRSM(I,k): tile (I,k) <- F_Ik L_kk^-T D_k^-1 by block forward substitution
+// over the 16-column blocks J of the pivot block, with w_JJ = L_JJ^-1 in the
+// diagonal sub-blocks:  V_J = F_J - sum_{K<J} X_K L_JK^T,  X_J = V_J w_JJ^T.
+// Thread t owns rows t%32 and t%32 + 32 and columns 2 (t/32) + {0,1} of a block.
 template <typename R>
-__device__ void task_trsm(const KArgs& a, int s, int f, int k, int I, unsigned char* smem) {
+__device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, int I, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  C* As = reinterpret_cast<C*>(smem);
-  C* Bs = As + 16 * kBW;
+  C* Xs = reinterpret_cast<C*>(smem);  // kBW x kBW column major: F_Ik, then X in place
+  C* Ls = Xs + kBW * kBW;              // kBW x kBW: the pivot block (L_JK, w_JJ, D)
+  C* Vs = Ls + kBW * kBW;              // kBW x 16
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
   const int r0 = ch.lo(I), nr = ch.hi(I) - r0;
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  C acc[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
-  tile_abt<C>(nr, nb, nb, [&](int r, int q) { return L[(int64_t)(k0 + q) * m + r0 + r]; },
-              [&](int j, int q) {
-                C v = czero<C>();
-                if (q < j) v = L[(int64_t)(k0 + q) * m + k0 + j];
-                else if (q == j) v.x = 1;
-                return v;
-              },
-              As, Bs, acc);
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-#pragma unroll
-  for (int y = 0; y < 4; ++y) {
-    const int j = tc + 16 * y;
-    if (j >= nb) continue;
-    const C invj = cinv(L[(int64_t)(k0 + j) * m + k0 + j]);
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int r = tr + 16 * x;
-      if (r < nr) L[(int64_t)(k0 + j) * m + r0 + r] = cmul(acc[x][y], invj);
-    }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // zero padding beyond nr rows / nb columns keeps the products finite
+  for (int c = wave; c < kBW; c += 4) {
+    const C* col = L + (int64_t)(k0 + c) * m;
+    Xs[c * kBW + lane] = (c < nb && lane < nr) ? col[r0 + lane] : czero<C>();
+    Ls[c * kBW + lane] = (c < nb && lane >= c && lane < nb) ? col[k0 + lane] : czero<C>();
   }
+  __syncthreads();
+  const int ra = threadIdx.x & 31, cb = 2 * (threadIdx.x >> 5);
+  const int nsb = (nb + 15) / 16;
+  for (int J = 0; J < nsb; ++J) {
+    const int j0 = 16 * J;
+    C v[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) v[x][y] = Xs[(j0 + cb + y) * kBW + ra + 32 * x];
+    for (int q = 0; q < j0; ++q) {
+      const C x0 = Xs[q * kBW + ra], x1 = Xs[q * kBW + ra + 32];
+      const C l0 = Ls[q * kBW + j0 + cb], l1 = Ls[q * kBW + j0 + cb + 1];
+      v[0][0] = cfms(v[0][0], x0, l0);
+      v[0][1] = cfms(v[0][1], x0, l1);
+      v[1][0] = cfms(v[1][0], x1, l0);
+      v[1][1] = cfms(v[1][1], x1, l1);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) Vs[(cb + y) * kBW + ra + 32 * x] = v[x][y];
+    __syncthreads();
+    C o[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) o[x][y] = czero<C>();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const C v0 = Vs[q * kBW + ra], v1 = Vs[q * kBW + ra + 32];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int c = cb + y;
+        const C st = Ls[(j0 + q) * kBW + j0 + c];
+        C w;  // w_JJ[c][q]: unit diagonal, zero above
+        w.x = q < c ? st.x : (q == c ? 1 : 0);
+        w.y = q < c ? st.y : 0;
+        o[0][y] = cadd(o[0][y], cmul(v0, w));
+        o[1][y] = cadd(o[1][y], cmul(v1, w));
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) Xs[(j0 + cb + y) * kBW + ra + 32 * x] = o[x][y];
+    __syncthreads();
+  }
+  for (int c = wave; c < nb; c += 4)
+    if (lane < nr) L[(int64_t)(k0 + c) * m + r0 + lane] = cmul(Xs[c * kBW + lane], cinv(Ls[c * kBW + c]));
 }
 
 // tile (I,J) -= L_Ik D_k L_Jk^T
 template <typename R>
-__device__ void task_upd(const KArgs& a, int s, int f, int k, int I, int J, unsigned char* smem) {
+__device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   C* As = reinterpret_cast<C*>(smem);
   C* Bs = As + 16 * kBW;
@@ -985,6 +1050,8 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
       } else if (type == T_TRSM) {
         wait_value(st + tile_id(k, k), k + 2, a.st);
         wait_value(st + tile_id(I, k), k + 1, a.st);
+      } else if (type == T_INV) {
+        for (int i = k + 1; i < ch.nbk + ch.nut; ++i) wait_value(st + tile_id(i, k), k + 2, a.st);
       } else {
         wait_value(st + tile_id(I, k), k + 2, a.st);
         wait_value(st + tile_id(J, k), k + 2, a.st);
@@ -999,9 +1066,10 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
       task_asm<R>(a, s, f, I, J, smem_raw);
       tile = tile_id(I, J);
       ver = 1;
-    } else if (type == T_DIAG) {
-      task_diag<R>(a, s, f, k, smem_raw);
-      tile = tile_id(k, k);
+    } else if (type == T_DIAG || type == T_INV) {
+      task_diag<R>(a, s, f, k, type == T_INV ? kInvOnly : k == ch.nbk + ch.nut - 1 ? kDiagFull : kDiagPart,
+                   smem_raw);
+      tile = type == T_INV ? -1 : tile_id(k, k);
       ver = k + 2;
     } else if (type == T_TRSM) {
       task_trsm<R>(a, s, f, k, I, smem_raw);
@@ -1014,7 +1082,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     }
     drain_stores();
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && tile >= 0) {
       __hip_atomic_store(st + tile, ver, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (type == T_UPD && J >= ch.nbk && k == ch.nbk - 1)
         __hip_atomic_fetch_add(ta.done + (int64_t)s * a.nfronts + f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1546,9 +1614,7 @@ unsigned persistent_grid(const Plan& P, size_t lds, int ntasks) {
 // LDS of the task-graph kernel: the diagonal task's block and pivots, or the
 // two 16-deep operand panels of the tile products, whichever is larger.
 size_t tile_lds(const Plan& P) {
-  const size_t diag = (size_t)(kBW * kBW + 2 * kBW + 1024);
-  const size_t gemm = (size_t)(2 * 16 * kBW);
-  return (diag > gemm ? diag : gemm) * P.csize;
+  return tile_lds_entries() * P.csize;
 }
 
 template <typename R>

@@ -143,6 +143,10 @@ hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, in
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st);
 hipError_t launch_status_reset(Plan& P, hipStream_t st);
 size_t solve_lds_bytes(const Plan& P, int nrhs);
+
+// Complex entries of LDS the tile-graph tasks need: the TRSM task's 64 x 64
+// tile, 64 x 64 pivot block and 64 x 16 buffer, the largest of the task types.
+inline size_t tile_lds_entries() { return 2 * 64 * 64 + 64 * 16; }
 // FDFD_PROFILE helpers (fdfd_api.cpp)
 hipEvent_t profile_event(Plan& P);
 void profile_collect(Plan& P);
