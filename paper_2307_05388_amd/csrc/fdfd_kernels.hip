@@ -526,6 +526,8 @@ __device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
           if (k >= j) v = cfms(v, F[(o + k) * ld + o + i], x[k]);
       }
       x[i] = v;
+      // keeps the row's LDS loads from being hoisted across rows (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (j < b) {
 #pragma unroll
@@ -549,7 +551,7 @@ __device__ __forceinline__ void invert_offdiag(C* F, int ld, int nb, C* T) {
       for (int kb = jb; kb < ib; ++kb) {
         const int rk = 16 * kb, bk = min(16, nb - rk);
         const bool diag = kb == jb;
-#pragma unroll
+#pragma unroll 4
         for (int q = 0; q < 16; ++q) {
           if (q < bk) {  // uniform across the workgroup
             // X_{kb,jb}[q][c]: unit lower on the diagonal block
@@ -567,7 +569,7 @@ __device__ __forceinline__ void invert_offdiag(C* F, int ld, int nb, C* T) {
       __syncthreads();
       if (r < bi && c < bj) {
         C v = czero<C>();
-#pragma unroll
+#pragma unroll 4
         for (int q = 0; q < 16; ++q) {
           const C xl = F[(ri + q) * ld + ri + r];
           C xv;
@@ -670,24 +672,24 @@ __device__ void small_front(const KArgs& a, const Queue& q, int s, int f, unsign
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
       }
-      // children's contributions to the update block, eight entries per batch
+      // children's contributions to the update block, one register column per batch
 #pragma unroll
-      for (int yh = 0; yh < 4; yh += 2) {
-        int rr[8], cc[8];
-        C v[8];
+      for (int y = 0; y < 4; ++y) {
+        int rr[4], cc[4];
+        C v[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int r = ti + tr + 16 * (e & 3), c = tj + tc + 16 * (yh + (e >> 2));
+        for (int e = 0; e < 4; ++e) {
+          const int r = ti + tr + 16 * e, c = tj + tc + 16 * y;
           rr[e] = (r < u && c < u && r >= c) ? p + r : -1;
           cc[e] = p + c;
           v[e] = czero<C>();
         }
-        add_children<C, 8>(a, s, f, m, rr, cc, v);
+        add_children<C, 4>(a, s, f, m, rr, cc, v);
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
+        for (int e = 0; e < 4; ++e)
           if (rr[e] >= 0) {
             const int r = rr[e] - p, c = cc[e] - p;
-            U[(int64_t)c * u + r] = csub(v[e], acc[e & 3][yh + (e >> 2)]);
+            U[(int64_t)c * u + r] = csub(v[e], acc[e][y]);
           }
       }
     }
@@ -708,8 +710,10 @@ __device__ void small_front(const KArgs& a, const Queue& q, int s, int f, unsign
 
 // Persistent launch over fronts order[0 .. ntasks/nsys): with q.wait set, a
 // front first waits for its children (claimed earlier in the same launch).
+// Two waves per SIMD: with up to three fronts' panels per CU in LDS, register
+// use (not LDS) would otherwise hold the kernel to one workgroup per CU.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_front_small(KArgs a, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, const int32_t* order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
   for (;;) {
