@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run a plain device fill and copy of this many MiB, the reference "
+                         "for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -106,6 +109,14 @@ def main():
     from paper_2307_05388_amd.fdfd import FDFD_GRAD_SUM_SYSTEMS
 
     dev = torch.device("cuda:0")
+    if args.copy_mb > 0:
+        # known traffic: the fill writes copy_mb MiB, each copy reads and writes copy_mb MiB
+        src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = P.make_problem(args.config)
     omegas = P.omegas(p)
     T = args.warmup + args.steps

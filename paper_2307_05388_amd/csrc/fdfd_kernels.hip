@@ -117,6 +117,34 @@ __device__ __forceinline__ double2 sym_scale(const KArgs& a, int s, int n) {
 // Entry (r, c), r >= c, of front f before elimination: the original entry of
 // S*A (only in pivot columns) plus the children's update blocks (extend-add in
 // gather form: every entry reads its contributions, fixed child order).
+// Data one workgroup writes and another reads within the same launch (update
+// matrices, tiles of large fronts, sweep vectors) moves through agent-coherent
+// accesses: relaxed agent-scope atomics, i.e. loads and stores with the sc1
+// bit, which bypass the per-XCD caches that are not coherent with each other.
+// The completion flags then only need the writer's stores to have completed
+// before the flag is set; no agent-scope fence (an L2 write-back or
+// invalidate, serialised per XCD and costing microseconds when hundreds of
+// workgroups issue them) runs per task.
+template <typename C> __device__ __forceinline__ C ld_ag(const C* p) {
+  typedef unsigned long long u64;
+  u64* q = reinterpret_cast<u64*>(const_cast<C*>(p));
+  u64 w[sizeof(C) / 8];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(C) / 8); ++i) w[i] = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  C v;
+  __builtin_memcpy(&v, w, sizeof(C));
+  return v;
+}
+
+template <typename C> __device__ __forceinline__ void st_ag(C* p, C v) {
+  typedef unsigned long long u64;
+  u64* q = reinterpret_cast<u64*>(p);
+  u64 w[sizeof(C) / 8];
+  __builtin_memcpy(w, &v, sizeof(C));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(C) / 8); ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Original (symmetrised) operator entries of the pivot columns [c0, c0 + nc)
 // of front f, one thread per column, staged for the assembly loops:
 // sv[5 t] = diagonal, sv[5 t + 1 + d] = coupling to neighbour d (x-1, x+1,
@@ -167,7 +195,7 @@ __device__ __forceinline__ void add_children(const KArgs& a, int s, int f, int m
     }
     C v[NB];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) v[e] = (gr[e] >= 0 && gc[e] >= 0) ? Uc[(int64_t)gc[e] * nu + gr[e]] : czero<C>();
+    for (int e = 0; e < NB; ++e) v[e] = (gr[e] >= 0 && gc[e] >= 0) ? ld_ag(Uc + (int64_t)gc[e] * nu + gr[e]) : czero<C>();
 #pragma unroll
     for (int e = 0; e < NB; ++e) val[e] = cadd(val[e], v[e]);
   }
@@ -318,7 +346,6 @@ __device__ __forceinline__ int claim(const Queue& q, int* sh) {
 
 __device__ __forceinline__ void leave(const Queue& q) {
   if (threadIdx.x == 0) {
-    __threadfence();
     const int n = atomicAdd(&q.counter[1], 1);
     if (n == (int)(gridDim.x * gridDim.y * gridDim.z) - 1) {
       q.counter[0] = 0;
@@ -328,8 +355,9 @@ __device__ __forceinline__ void leave(const Queue& q) {
 }
 
 // Polls with relaxed agent-scope loads (they read past the non-coherent
-// caches without invalidating them); the caller issues one acquire fence once
-// every awaited flag is seen.
+// caches without invalidating them).  Once every awaited flag is seen the
+// caller issues a workgroup-scope acquire (it keeps the data loads below the
+// poll; those loads are agent-coherent themselves) and a barrier.
 __device__ __forceinline__ void wait_flag(const Queue& q, const int32_t* p) {
   int it = 0;
   while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != q.epoch) {
@@ -345,7 +373,7 @@ __device__ __forceinline__ void wait_children(const Queue& q, const KArgs& a, in
   if (threadIdx.x == 0) {
     for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k)
       wait_flag(q, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
 }
@@ -353,22 +381,23 @@ __device__ __forceinline__ void wait_children(const Queue& q, const KArgs& a, in
 __device__ __forceinline__ void wait_parent(const Queue& q, const KArgs& a, int s, int f) {
   if (threadIdx.x == 0 && a.parent[f] >= 0) {
     wait_flag(q, q.done + (int64_t)s * a.nfronts + a.parent[f]);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
 }
 
-// Every wave waits until its global stores are acknowledged by L2 before the
-// barrier; the one agent-scope release by thread 0 then writes L2 back for all
-// of them (a workgroup barrier alone does not wait for other waves' stores).
+// Before a completion flag is set, every wave waits until its (agent-coherent)
+// stores have completed; a workgroup barrier alone does not wait for other
+// waves' stores.  The compiler-level release fence keeps the stores above it.
 __device__ __forceinline__ void drain_stores() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained (gfx9 encoding)
 }
 
 __device__ __forceinline__ void publish(const Queue& q, int64_t idx) {
   drain_stores();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(q.done + idx, q.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(q.done + idx, q.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,7 +718,7 @@ __device__ void small_front(const KArgs& a, const Queue& q, int s, int f, unsign
         for (int e = 0; e < 4; ++e)
           if (rr[e] >= 0) {
             const int r = rr[e] - p, c = cc[e] - p;
-            U[(int64_t)c * u + r] = csub(v[e], acc[e][y]);
+            st_ag(U + (int64_t)c * u + r, csub(v[e], acc[e][y]));
           }
       }
     }
@@ -871,7 +900,7 @@ __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, in
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int t = wave + 4 * (tb + e), c = c0 + t;
-      if (lane < nr && t < nc && (r >= c || piv)) *front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c) = v[e];
+      if (lane < nr && t < nc && (r >= c || piv)) st_ag(front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c), v[e]);
     }
   }
 }
@@ -899,7 +928,7 @@ __device__ __forceinline__ void task_diag(const KArgs& a, int s, int f, int k, i
   const bool inv_only = mode == kInvOnly;
   for (int c = wave; c < nb; c += 4)
     for (int r = lane; r < nb; r += 64)
-      B[c * kBW + r] = (inv_only ? r > c : r >= c) ? L[(int64_t)c * m + r] : czero<C>();
+      B[c * kBW + r] = (inv_only ? r > c : r >= c) ? ld_ag(L + (int64_t)c * m + r) : czero<C>();
   __syncthreads();
   double anorm = 0.0;
   int npert = 0, nonfin = 0;
@@ -912,10 +941,10 @@ __device__ __forceinline__ void task_diag(const KArgs& a, int s, int f, int k, i
   if (mode != kDiagPart) invert_offdiag(B, kBW, nb, T);
   if (inv_only) {
     for (int c = wave; c < nb; c += 4)
-      if (lane < nb && (lane >> 4) > (c >> 4)) L[(int64_t)c * m + lane] = B[c * kBW + lane];
+      if (lane < nb && (lane >> 4) > (c >> 4)) st_ag(L + (int64_t)c * m + lane, B[c * kBW + lane]);
   } else {
     for (int c = wave; c < nb; c += 4)
-      for (int r = c + lane; r < nb; r += 64) L[(int64_t)c * m + r] = (r > c) ? B[c * kBW + r] : dd[c];
+      for (int r = c + lane; r < nb; r += 64) st_ag(L + (int64_t)c * m + r, (r > c) ? B[c * kBW + r] : dd[c]);
     if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
   }
 }
@@ -938,8 +967,8 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
   // zero padding beyond nr rows / nb columns keeps the products finite
   for (int c = wave; c < kBW; c += 4) {
     const C* col = L + (int64_t)(k0 + c) * m;
-    Xs[c * kBW + lane] = (c < nb && lane < nr) ? col[r0 + lane] : czero<C>();
-    Ls[c * kBW + lane] = (c < nb && lane >= c && lane < nb) ? col[k0 + lane] : czero<C>();
+    Xs[c * kBW + lane] = (c < nb && lane < nr) ? ld_ag(col + r0 + lane) : czero<C>();
+    Ls[c * kBW + lane] = (c < nb && lane >= c && lane < nb) ? ld_ag(col + k0 + lane) : czero<C>();
   }
   __syncthreads();
   const int ra = threadIdx.x & 31, cb = 2 * (threadIdx.x >> 5);
@@ -990,7 +1019,7 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
     __syncthreads();
   }
   for (int c = wave; c < nb; c += 4)
-    if (lane < nr) L[(int64_t)(k0 + c) * m + r0 + lane] = cmul(Xs[c * kBW + lane], cinv(Ls[c * kBW + c]));
+    if (lane < nr) st_ag(L + (int64_t)(k0 + c) * m + r0 + lane, cmul(Xs[c * kBW + lane], cinv(Ls[c * kBW + c])));
 }
 
 // tile (I,J) -= L_Ik D_k L_Jk^T
@@ -1008,10 +1037,10 @@ __device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, in
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
-  tile_abt<C>(nr, nc, nb, [&](int r, int q) { return L[(int64_t)(k0 + q) * m + r0 + r]; },
+  tile_abt<C>(nr, nc, nb, [&](int r, int q) { return ld_ag(L + (int64_t)(k0 + q) * m + r0 + r); },
               [&](int c, int q) {
                 const C* col = L + (int64_t)(k0 + q) * m;
-                return cmul(col[c0 + c], col[k0 + q]);
+                return cmul(ld_ag(col + c0 + c), ld_ag(col + k0 + q));
               },
               As, Bs, acc);
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
@@ -1024,7 +1053,7 @@ __device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, in
       const int c = c0 + tc + 16 * y;
       if (c >= c0 + nc || r < c) continue;
       C* dst = front_elem<C>(a, s, f, ch.p, ch.u, m, r, c);
-      *dst = csub(*dst, acc[x][y]);
+      st_ag(dst, csub(ld_ag(dst), acc[x][y]));
     }
   }
 }
@@ -1061,7 +1090,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
         wait_value(st + tile_id(J, k), k + 2, a.st);
         wait_value(st + tile_id(I, J), k + 1, a.st);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     __syncthreads();
     trace_mark(q, t, 1);
@@ -1087,9 +1116,9 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     drain_stores();
     __syncthreads();
     if (threadIdx.x == 0 && tile >= 0) {
-      __hip_atomic_store(st + tile, ver, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(st + tile, ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (type == T_UPD && J >= ch.nbk && k == ch.nbk - 1)
-        __hip_atomic_fetch_add(ta.done + (int64_t)s * a.nfronts + f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(ta.done + (int64_t)s * a.nfronts + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     trace_mark(q, t, 2);
   }
@@ -1153,7 +1182,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     }
     for (int k = cb; k < ce; ++k) {
       const int gr = g[(k - cb) * m + r];
-      if (gr >= 0) v = cadd(v, W[(int64_t)col * a.sum_u + a.upd_ptr[a.child_list[k]] + gr]);
+      if (gr >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[k]] + gr));
     }
     V[col * m + r] = v;
   }
@@ -1199,7 +1228,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
     const int col = idx / m, r = idx - col * m;
     if (r < p) Y[(int64_t)col * a.N + pb + r] = cmul(V[col * m + r], cinv(L[(int64_t)r * m + r]));
-    else W[(int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p)] = V[col * m + r];
+    else st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), V[col * m + r]);
   }
 }
 
@@ -1228,7 +1257,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
     const int col = idx / m, r = idx - col * m;
-    X[col * m + r] = Y[(int64_t)col * a.N + (r < p ? pb + r : ui[r - p])];
+    X[col * m + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1298,7 +1327,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   for (int idx = threadIdx.x; idx < p * nrhs; idx += kThreads) {
     const int col = idx / p, r = idx - col * p;
     const C x = X[col * m + r];
-    Y[(int64_t)col * a.N + pb + r] = x;
+    st_ag(Y + (int64_t)col * a.N + pb + r, x);
     double2* o = O + (int64_t)col * a.N + a.perm[pb + r];
     const double2 xv = to_d2(x);
     *o = w.accumulate ? dadd(*o, xv) : xv;
