@@ -145,6 +145,27 @@ template <typename C> __device__ __forceinline__ void st_ag(C* p, C v) {
   for (int i = 0; i < (int)(sizeof(C) / 8); ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Copies a column-major global block (leading dimension ld; rows < nrows,
+// columns < ncols; tri = 0 all, 1 lower with diagonal, 2 strictly lower) into
+// a zero-padded kBW x kBW LDS block.  Lane = row, wave w takes columns w,
+// w+4, ...; all sixteen loads of a thread are in flight before the first
+// store, so the block costs about one memory latency.
+enum { kAll = 0, kLower = 1, kStrict = 2 };
+
+template <typename C>
+__device__ __forceinline__ void stage_block(C* S, const C* g, int64_t ld, int nrows, int ncols, int tri) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  C v[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = wave + 4 * t;
+    const bool keep = c < ncols && lane < nrows && (tri == kAll || lane > c || (tri == kLower && lane == c));
+    v[t] = keep ? ld_ag(g + (int64_t)c * ld + lane) : czero<C>();
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) S[(wave + 4 * t) * kBW + lane] = v[t];
+}
+
 // Original (symmetrised) operator entries of the pivot columns [c0, c0 + nc)
 // of front f, one thread per column, staged for the assembly loops:
 // sv[5 t] = diagonal, sv[5 t + 1 + d] = coupling to neighbour d (x-1, x+1,
@@ -813,56 +834,6 @@ __device__ __forceinline__ void wait_at_least(const int32_t* p, int v, DevStatus
   }
 }
 
-// C[r][c] (64 x 64 register tile, 4 x 4 per thread) += sum_q A[r][q] B[c][q]
-// over q < K in chunks of 16 staged in LDS (k-major).  The next chunk is
-// loaded into registers while the current one is multiplied.  loadA/loadB
-// return the operands for (row, q).
-template <typename C, typename FA, typename FB>
-__device__ __forceinline__ void tile_abt(int na, int nb_, int K, FA loadA, FB loadB, C* As, C* Bs, C acc[4][4]) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  C pa[4], pb[4];
-  for (int q0 = 0; q0 < K; q0 += 16) {
-    if (q0 == 0) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int idx = threadIdx.x + e * kThreads;
-        const int qq = idx >> 6, r = idx & 63;
-        const bool in = qq < min(16, K);
-        pa[e] = (in && r < na) ? loadA(r, qq) : czero<C>();
-        pb[e] = (in && r < nb_) ? loadB(r, qq) : czero<C>();
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      As[threadIdx.x + e * kThreads] = pa[e];
-      Bs[threadIdx.x + e * kThreads] = pb[e];
-    }
-    __syncthreads();
-    if (q0 + 16 < K) {
-      const int q1 = q0 + 16, kq = min(16, K - q1);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int idx = threadIdx.x + e * kThreads;
-        const int qq = idx >> 6, r = idx & 63;
-        pa[e] = (qq < kq && r < na) ? loadA(r, q1 + qq) : czero<C>();
-        pb[e] = (qq < kq && r < nb_) ? loadB(r, q1 + qq) : czero<C>();
-      }
-    }
-#pragma unroll 1
-    for (int qq = 0; qq < 16; ++qq) {
-      C av[4], bv[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) av[x] = As[qq * kBW + tr + 16 * x];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) bv[y] = Bs[qq * kBW + tc + 16 * y];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
-    }
-    __syncthreads();
-  }
-}
 
 template <typename C>
 __device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, int u, int m, int r, int c) {
@@ -926,9 +897,7 @@ __device__ __forceinline__ void task_diag(const KArgs& a, int s, int f, int k, i
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m + k0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool inv_only = mode == kInvOnly;
-  for (int c = wave; c < nb; c += 4)
-    for (int r = lane; r < nb; r += 64)
-      B[c * kBW + r] = (inv_only ? r > c : r >= c) ? ld_ag(L + (int64_t)c * m + r) : czero<C>();
+  stage_block(B, L, m, nb, nb, inv_only ? kStrict : kLower);
   __syncthreads();
   double anorm = 0.0;
   int npert = 0, nonfin = 0;
@@ -965,11 +934,8 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // zero padding beyond nr rows / nb columns keeps the products finite
-  for (int c = wave; c < kBW; c += 4) {
-    const C* col = L + (int64_t)(k0 + c) * m;
-    Xs[c * kBW + lane] = (c < nb && lane < nr) ? ld_ag(col + r0 + lane) : czero<C>();
-    Ls[c * kBW + lane] = (c < nb && lane >= c && lane < nb) ? ld_ag(col + k0 + lane) : czero<C>();
-  }
+  stage_block(Xs, L + (int64_t)k0 * m + r0, m, nr, nb, kAll);
+  stage_block(Ls, L + (int64_t)k0 * m + k0, m, nb, nb, kLower);
   __syncthreads();
   const int ra = threadIdx.x & 31, cb = 2 * (threadIdx.x >> 5);
   const int nsb = (nb + 15) / 16;
@@ -1022,38 +988,93 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
     if (lane < nr) st_ag(L + (int64_t)(k0 + c) * m + r0 + lane, cmul(Xs[c * kBW + lane], cinv(Ls[c * kBW + c])));
 }
 
-// tile (I,J) -= L_Ik D_k L_Jk^T
+// Matrix-core (MFMA) product of two LDS-resident complex 64 x 64 operands:
+// O[c][r] = sum_q A[q][r] B[q][c] d_q (all column major with leading dimension
+// kBW, zero padded; Ds holds d_q).  Wave w owns output rows 16w..16w+15 as four 16 x 16
+// blocks; per block and 4-deep k-step the complex product is four real
+// 16x16x4 MFMAs (re += ar br - ai bi, im += ar bi + ai br).  Operand lanes:
+// A row l%16 / B column l%16 at k = l/16; the result rows per register differ
+// between the f64 and f32 instructions (Mfma::row).  O may alias A or B: the
+// products finish (barrier) before O is written, and a barrier follows.
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+template <typename R, typename C>
+__device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, const C* Ds, C* O) {
+  typedef typename Mfma<R>::v4 v4;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = l & 15, kq = l >> 4;
+  v4 re[4], im[4];
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    re[bj] = v4{0, 0, 0, 0};
+    im[bj] = v4{0, 0, 0, 0};
+  }
+#pragma unroll 4
+  for (int k0 = 0; k0 < kBW; k0 += 4) {
+    const int q = k0 + kq;
+    const C av = A[q * kBW + 16 * wave + i];
+    const R nai = -av.y;
+    const C dq = Ds[q];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const C bv = cmul(B[q * kBW + 16 * bj + i], dq);
+      re[bj] = Mfma<R>::op(av.x, bv.x, re[bj]);
+      re[bj] = Mfma<R>::op(nai, bv.y, re[bj]);
+      im[bj] = Mfma<R>::op(av.x, bv.y, im[bj]);
+      im[bj] = Mfma<R>::op(av.y, bv.x, im[bj]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      C v;
+      v.x = re[bj][r];
+      v.y = im[bj][r];
+      O[(16 * bj + i) * kBW + 16 * wave + Mfma<R>::row(l, r)] = v;
+    }
+  __syncthreads();
+}
+
+// UPD(I,J,k): tile (I,J) -= L_Ik D_k L_Jk^T.  L_Ik, L_Jk and D_k are staged in
+// LDS, multiplied on the matrix cores, and the product is subtracted column by
+// column (coalesced).
 template <typename R>
 __device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  C* As = reinterpret_cast<C*>(smem);
-  C* Bs = As + 16 * kBW;
+  C* As = reinterpret_cast<C*>(smem);  // As[q][r] = L[r0 + r][k0 + q]; then the product
+  C* Bs = As + kBW * kBW;              // Bs[q][c] = L[c0 + c][k0 + q]
+  C* Ds = Bs + kBW * kBW;              // d_q
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
   const int r0 = ch.lo(I), nr = ch.hi(I) - r0, c0 = ch.lo(J), nc = ch.hi(J) - c0;
-  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  C acc[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
-  tile_abt<C>(nr, nc, nb, [&](int r, int q) { return ld_ag(L + (int64_t)(k0 + q) * m + r0 + r); },
-              [&](int c, int q) {
-                const C* col = L + (int64_t)(k0 + q) * m;
-                return cmul(ld_ag(col + c0 + c), ld_ag(col + k0 + q));
-              },
-              As, Bs, acc);
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int r = r0 + tr + 16 * x;
-    if (r >= r0 + nr) continue;
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int c = c0 + tc + 16 * y;
-      if (c >= c0 + nc || r < c) continue;
-      C* dst = front_elem<C>(a, s, f, ch.p, ch.u, m, r, c);
-      st_ag(dst, csub(ld_ag(dst), acc[x][y]));
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) Ds[lane] = lane < nb ? ld_ag(L + (int64_t)lane * m + k0 + lane) : czero<C>();
+  stage_block(As, L + r0, m, nr, nb, kAll);
+  stage_block(Bs, L + c0, m, nc, nb, kAll);
+  __syncthreads();
+  mfma_tile_abt<R>(As, Bs, Ds, As);
+  for (int c = wave; c < nc; c += 4) {
+    const int r = lane;
+    if (r < nr && r0 + r >= c0 + c) {
+      C* dst = front_elem<C>(a, s, f, ch.p, ch.u, m, r0 + r, c0 + c);
+      st_ag(dst, csub(ld_ag(dst), As[c * kBW + r]));
     }
   }
 }
