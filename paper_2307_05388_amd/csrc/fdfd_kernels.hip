@@ -153,7 +153,8 @@ template <typename C> __device__ __forceinline__ void st_ag(C* p, C v) {
 enum { kAll = 0, kLower = 1, kStrict = 2 };
 
 template <typename C>
-__device__ __forceinline__ void stage_block(C* S, const C* g, int64_t ld, int nrows, int ncols, int tri) {
+__device__ __forceinline__ void stage_block(C* S, const C* g, int64_t ld, int nrows, int ncols, int tri,
+                                            const C* scale = nullptr, int64_t scale_stride = 0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   C v[16];
 #pragma unroll
@@ -161,6 +162,16 @@ __device__ __forceinline__ void stage_block(C* S, const C* g, int64_t ld, int nr
     const int c = wave + 4 * t;
     const bool keep = c < ncols && lane < nrows && (tri == kAll || lane > c || (tri == kLower && lane == c));
     v[t] = keep ? ld_ag(g + (int64_t)c * ld + lane) : czero<C>();
+  }
+  if (scale) {  // column c times scale[c * scale_stride] (the same for the whole wave)
+    C d[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = wave + 4 * t;
+      d[t] = c < ncols ? ld_ag(scale + (int64_t)c * scale_stride) : czero<C>();
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = cmul(v[t], d[t]);
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t) S[(wave + 4 * t) * kBW + lane] = v[t];
@@ -989,8 +1000,8 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
 }
 
 // Matrix-core (MFMA) product of two LDS-resident complex 64 x 64 operands:
-// O[c][r] = sum_q A[q][r] B[q][c] d_q (all column major with leading dimension
-// kBW, zero padded; Ds holds d_q).  Wave w owns output rows 16w..16w+15 as four 16 x 16
+// O[c][r] = sum_q A[q][r] B[q][c] (all column major with leading dimension
+// kBW, zero padded).  Wave w owns output rows 16w..16w+15 as four 16 x 16
 // blocks; per block and 4-deep k-step the complex product is four real
 // 16x16x4 MFMAs (re += ar br - ai bi, im += ar bi + ai br).  Operand lanes:
 // A row l%16 / B column l%16 at k = l/16; the result rows per register differ
@@ -1013,7 +1024,7 @@ template <> struct Mfma<float> {
 };
 
 template <typename R, typename C>
-__device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, const C* Ds, C* O) {
+__device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, C* O) {
   typedef typename Mfma<R>::v4 v4;
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = l & 15, kq = l >> 4;
@@ -1028,14 +1039,19 @@ __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, const C* D
     const int q = k0 + kq;
     const C av = A[q * kBW + 16 * wave + i];
     const R nai = -av.y;
-    const C dq = Ds[q];
+    C bv[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) bv[bj] = B[q * kBW + 16 * bj + i];
+    // eight independent accumulators per pass, so no MFMA waits on the previous one
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
-      const C bv = cmul(B[q * kBW + 16 * bj + i], dq);
-      re[bj] = Mfma<R>::op(av.x, bv.x, re[bj]);
-      re[bj] = Mfma<R>::op(nai, bv.y, re[bj]);
-      im[bj] = Mfma<R>::op(av.x, bv.y, im[bj]);
-      im[bj] = Mfma<R>::op(av.y, bv.x, im[bj]);
+      re[bj] = Mfma<R>::op(av.x, bv[bj].x, re[bj]);
+      im[bj] = Mfma<R>::op(av.x, bv[bj].y, im[bj]);
+    }
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      re[bj] = Mfma<R>::op(nai, bv[bj].y, re[bj]);
+      im[bj] = Mfma<R>::op(av.y, bv[bj].x, im[bj]);
     }
   }
   __syncthreads();
@@ -1051,32 +1067,35 @@ __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, const C* D
   __syncthreads();
 }
 
-// UPD(I,J,k): tile (I,J) -= L_Ik D_k L_Jk^T.  L_Ik, L_Jk and D_k are staged in
-// LDS, multiplied on the matrix cores, and the product is subtracted column by
-// column (coalesced).
+// UPD(I,J,k): tile (I,J) -= L_Ik D_k L_Jk^T.  L_Ik and L_Jk D_k are staged in
+// LDS, multiplied on the matrix cores, and the product is subtracted from the
+// tile with all of a thread's loads in flight together (coalesced columns).
 template <typename R>
 __device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   C* As = reinterpret_cast<C*>(smem);  // As[q][r] = L[r0 + r][k0 + q]; then the product
-  C* Bs = As + kBW * kBW;              // Bs[q][c] = L[c0 + c][k0 + q]
-  C* Ds = Bs + kBW * kBW;              // d_q
+  C* Bs = As + kBW * kBW;              // Bs[q][c] = L[c0 + c][k0 + q] d_q
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
   const int r0 = ch.lo(I), nr = ch.hi(I) - r0, c0 = ch.lo(J), nc = ch.hi(J) - c0;
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (wave == 0) Ds[lane] = lane < nb ? ld_ag(L + (int64_t)lane * m + k0 + lane) : czero<C>();
   stage_block(As, L + r0, m, nr, nb, kAll);
-  stage_block(Bs, L + c0, m, nc, nb, kAll);
+  stage_block(Bs, L + c0, m, nc, nb, kAll, L + k0, m + 1);
   __syncthreads();
-  mfma_tile_abt<R>(As, Bs, Ds, As);
-  for (int c = wave; c < nc; c += 4) {
-    const int r = lane;
-    if (r < nr && r0 + r >= c0 + c) {
-      C* dst = front_elem<C>(a, s, f, ch.p, ch.u, m, r0 + r, c0 + c);
-      st_ag(dst, csub(ld_ag(dst), As[c * kBW + r]));
-    }
+  mfma_tile_abt<R>(As, Bs, As);
+  C* dst[16];
+  C v[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = wave + 4 * t;
+    const bool ok = c < nc && lane < nr && r0 + lane >= c0 + c;
+    dst[t] = ok ? front_elem<C>(a, s, f, ch.p, ch.u, m, r0 + lane, c0 + c) : nullptr;
+    v[t] = ok ? ld_ag(dst[t]) : czero<C>();
   }
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+    if (dst[t]) st_ag(dst[t], csub(v[t], As[(wave + 4 * t) * kBW + lane]));
 }
 
 template <typename R>
