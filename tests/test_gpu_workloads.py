@@ -1,0 +1,176 @@
+"""GPU checks at the full sizes of the five workloads, in the launch
+configuration the benchmark times (default leaf size, persistent kernels).
+
+Where the CPU oracle finishes in seconds (300 x 300) the fields, adjoint fields
+and gradients are compared element by element.  Above that the checks are
+properties that hold at any size:
+  * the relative residual ||b - A x|| / ||b|| with the oracle's own operator
+    (matrix-free, float64; Eq. 2);
+  * the adjoint identity g^T x = lam^T b, which holds exactly when A x = b and
+    A^T lam = g (Eq. 4 with the cached factor);
+  * the permittivity gradient (Eq. 3) against central differences of
+    F = |c^H x|^2 computed in float64 (h = 1e-4, 32 seeded design pixels);
+  * batch invariance: eight wavelengths factored in one launch give the same
+    bits as each wavelength factored alone.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2307_05388_amd import problems as P
+from gpu_util import gpu_iteration, make_plan, rel, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _adjoint_identity(out, b):
+    """max over (system, rhs) of |g^T x - lam^T b| / |g^T x|."""
+    worst = 0.0
+    for s in range(b.shape[0]):
+        for r in range(b.shape[1]):
+            gx = np.dot(out["g"][s, r], out["x"][s, r])
+            lb = np.dot(out["lam"][s, r], b[s, r])
+            worst = max(worst, abs(gx - lb) / abs(gx))
+    return worst
+
+
+def test_plain300_matches_oracle_both_precisions(oracle):
+    """The benchmark workload (300 x 300, N = 90,000): complex128 factors and
+    complex64 factors with float64 refinement, element by element against the
+    oracle's banded LU on the same permittivity."""
+    p = P.make_problem("plain300")
+    eps = P.design_eps(p, t=0)
+    b = P.sources(p)
+    c = P.objective_vector(p)
+    ref = oracle.design_iteration(p.nx, p.ny, p.npml, P.omegas(p), eps, b, c=c)
+    for prec, max_ir, tol, bar in (("c128", 0, 0.0, 1e-10), ("c64", 10, 1e-12, 1e-8)):
+        plan = make_plan(p, prec)
+        out = gpu_iteration(plan, p, eps, b, c=c, max_ir=max_ir, tol=tol)
+        ex, el, eg = rel(out["x"], ref["x"]), rel(out["lam"], ref["lam"]), rel(out["grad"], ref["grad"])
+        r = oracle.relative_residual(p.nx, p.ny, p.npml, P.omegas(p)[0], eps, out["x"][0, 0], b[0, 0])
+        say(f"plain300 {prec}: x {ex:.2e} lam {el:.2e} grad {eg:.2e} residual {r:.2e}", out["info"]["status_str"])
+        assert ex < bar and el < bar and eg < 10 * bar
+        assert r < 1e-10
+        plan.close()
+
+
+def test_diff500_gradient_matches_central_differences(oracle):
+    """500 x 500 with in/out guides: the autograd path (forward solve, adjoint
+    with the cached factor, gradient kernel) against central differences of F
+    in float64 on 32 seeded design pixels; relative error over them <= 1e-4."""
+    torch = torch_cuda()
+    from paper_2307_05388_amd.autograd import fdfd_fields, mode_overlap
+    dev = torch.device("cuda:0")
+    p = P.make_problem("diff500")
+    om = P.omegas(p)
+    base = torch.from_numpy(P.base_eps(p)).to(dev)
+    b = torch.from_numpy(P.sources(p)).to(dev)
+    c = torch.from_numpy(P.objective_vector(p)).to(dev)
+    i0, i1, j0, j1 = p.design
+    vals = P.design_values(p, 0)
+    plan = make_plan(p, "c128")
+    eps_d = torch.from_numpy(vals).to(dev).requires_grad_(True)
+    x = fdfd_fields(eps_d, plan, base, p.design, om, b)
+    F = mode_overlap(x, c)
+    F.backward()
+    g_ad = eps_d.grad.cpu().numpy()
+    eps_full = P.base_eps(p)
+    eps_full[j0:j1, i0:i1] = vals
+    res = oracle.relative_residual(p.nx, p.ny, p.npml, om[0], eps_full, x.detach()[0, 0].cpu().numpy(),
+                                   P.sources(p)[0, 0])
+    assert res < 1e-10
+
+    def F_at(v):
+        e = base.clone()
+        e[j0:j1, i0:i1] = torch.from_numpy(v).to(dev)
+        plan.refactor(e, om)
+        return float(mode_overlap(plan.solve(b), c).item())
+
+    h = 1e-4
+    px = P.fd_pixels(p, 32)
+    g_fd, g_px = [], []
+    for n in px:
+        j, i = divmod(int(n), p.nx)
+        v = vals.copy()
+        v[j - j0, i - i0] += h
+        fp = F_at(v)
+        v[j - j0, i - i0] -= 2 * h
+        fm = F_at(v)
+        g_fd.append((fp - fm) / (2 * h))
+        g_px.append(g_ad[j - j0, i - i0])
+    g_fd, g_px = np.array(g_fd), np.array(g_px)
+    e = np.linalg.norm(g_px - g_fd) / np.linalg.norm(g_fd)
+    say(f"diff500: residual {res:.2e}, gradient vs central differences {e:.2e} over {len(px)} pixels")
+    assert e <= 1e-4
+    plan.close()
+
+
+def test_mux400_batched_wavelengths_and_sources(oracle):
+    """400 x 400, eight wavelengths x two source profiles: one analysis, eight
+    factors in one launch, sixteen forward and adjoint solves.  Every field
+    solves its system (oracle residual; <= 1e-10 once refined in float64),
+    every adjoint satisfies the adjoint identity, complex64 + refinement agrees
+    with complex128, and the batched factors are bit-identical to
+    single-wavelength factors."""
+    torch = torch_cuda()
+    p = P.make_problem("mux400")
+    eps = P.design_eps(p)
+    b = P.sources(p)
+    c = P.objective_vector(p)
+    om = P.omegas(p)
+    outs = {}
+    # (form, refinement steps, tolerance): complex128 without and with float64
+    # refinement, complex64 with refinement
+    for name, prec, max_ir, tol in (("c128", "c128", 0, 0.0), ("c128+ir", "c128", 2, 1e-12),
+                                    ("c64+ir", "c64", 10, 1e-12)):
+        plan = make_plan(p, prec)
+        out = gpu_iteration(plan, p, eps, b, c=c, max_ir=max_ir, tol=tol)
+        res = np.array([[oracle.relative_residual(p.nx, p.ny, p.npml, om[s], eps, out["x"][s, r], b[s, r])
+                         for r in range(p.nrhs)] for s in range(p.nsys)])
+        adj = _adjoint_identity(out, b)
+        info = out["info"]
+        say(f"mux400 {name}: residual per system/rhs max {res.max():.2e} median {np.median(res):.2e}, "
+            f"adjoint identity {adj:.2e}, refinement steps {info['ir_steps_solve']}/{info['ir_steps_adjoint']}",
+            info["status_str"])
+        if max_ir:
+            assert res.max() < 1e-10
+        else:
+            assert res.max() < 1e-9   # unrefined complex128: growth of the unpivoted LDL^T
+        assert adj < 1e-10
+        outs[name] = out
+        plan.close()
+    assert rel(outs["c64+ir"]["x"], outs["c128+ir"]["x"]) < 1e-9
+    assert rel(outs["c64+ir"]["grad"], outs["c128+ir"]["grad"]) < 1e-8
+    assert rel(outs["c128"]["x"], outs["c128+ir"]["x"]) < 1e-8
+    dev = torch.device("cuda:0")
+    for s in (0, p.nsys - 1):
+        q = dataclasses.replace(p, wavelengths_um=(p.wavelengths_um[s],))
+        plan = make_plan(q, "c128")
+        plan.refactor(torch.from_numpy(eps).to(dev), P.omegas(q))
+        x1 = plan.solve(torch.from_numpy(np.ascontiguousarray(b[s:s + 1])).to(dev)).cpu().numpy()
+        assert np.array_equal(x1[0], outs["c128"]["x"][s])
+        plan.close()
+
+
+def test_large2000_full_size(oracle):
+    """2000 x 2000 (N = 4,000,000, 40-cell PML): complex128 factorisation and
+    both solves at full size, first unrefined, then with float64 refinement
+    (the <= 1e-10 residual bar); oracle residual and adjoint identity."""
+    p = P.make_problem("large2000")
+    eps = P.design_eps(p)
+    b = P.sources(p)
+    c = P.objective_vector(p)
+    plan = make_plan(p, "c128")
+    for max_ir, tol, bar in ((0, 0.0, 1e-9), (2, 1e-12, 1e-10)):
+        out = gpu_iteration(plan, p, eps, b, c=c, max_ir=max_ir, tol=tol)
+        res = oracle.relative_residual(p.nx, p.ny, p.npml, P.omegas(p)[0], eps, out["x"][0, 0], b[0, 0])
+        adj = _adjoint_identity(out, b)
+        info = out["info"]
+        say(f"large2000 max_ir={max_ir}: residual {res:.2e}, adjoint identity {adj:.2e}, "
+            f"refinement steps {info['ir_steps_solve']}/{info['ir_steps_adjoint']}, fronts {info['nfronts']}, "
+            f"factor {info['factor_bytes'] / 2**30:.2f} GiB", info["status_str"])
+        assert res < bar
+        assert adj < 1e-10
+        assert np.all(np.isfinite(out["grad"]))
+    plan.close()
