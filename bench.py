@@ -180,7 +180,9 @@ def main():
     # roofline of the dominant kernel, from an event-timed pass of the same steps
     prof_plan, _, prof_ms, _, prof_info, _ = run_mode(args, p, best, eps_all, b, c, omegas, profile=True)
     prof_plan.close()
-    out["roofline"] = roofline(prof_info["kernels"], best, args.steps)
+    from paper_2307_05388_amd.rocprof_summary import read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{p.name}_{best}.md"))
+    out["roofline"] = roofline(prof_info["kernels"], best, args.steps, traffic)
     out["kernels"] = {k: {"launches": v["launches"], "ms_per_step": v["total_ms"] / args.steps,
                           "avg_us": 1e3 * v["total_ms"] / max(1, v["launches"])}
                       for k, v in prof_info["kernels"].items() if v["launches"]}
@@ -190,9 +192,11 @@ def main():
     print(json.dumps(out))
 
 
-def roofline(stats, prec, steps):
+def roofline(stats, prec, steps, traffic=None):
     """Achieved rate of the kernel with the largest event time: its algorithmic
-    bytes (sweeps, residual) or flops (factorisation) over its summed launch time."""
+    bytes (sweeps, residual) or flops (factorisation) over its summed launch time.
+    traffic: the committed counter summary for this workload if it was measured
+    on the current kernel source (HBM bytes per launch), else None."""
     name, k = max(((n, v) for n, v in stats.items() if v["launches"]), key=lambda kv: kv[1]["total_ms"])
     sec = k["total_ms"] * 1e-3
     if k["alg_bytes"] > 0:
@@ -203,8 +207,13 @@ def roofline(stats, prec, steps):
         bound, unit, peak = "mfma", "TFLOP/s", PEAKS[prec]
         achieved = k["alg_flops"] / sec / 1e12
         per_launch = k["alg_flops"] / k["launches"]
+    kname = f"k_{name}<{'double' if prec == 'c128' else 'float'}>"
+    hbm = None
+    if traffic and kname in traffic["kernels"]:
+        hbm = traffic["kernels"][kname]["bytes"]
     return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "launches_per_step": k["launches"] / steps,
+            "frac": achieved / peak, "traffic": hbm, "traffic_unit": "HBM bytes per launch",
+            "launches_per_step": k["launches"] / steps,
             "avg_launch_us": 1e3 * k["total_ms"] / k["launches"], "alg_per_launch": per_launch}
 
 
