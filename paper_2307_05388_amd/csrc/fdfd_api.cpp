@@ -191,23 +191,31 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       for (int I = 0; I < R; ++I)
         for (int J = 0; J <= I; ++J) push(0, f, 0, I, J);
     }
+    // Step k: DIAG(0) (k = 0 only); FUSED(k+1) = TRSM(k+1,k) + UPD(k+1,k+1,k) +
+    // DIAG(k+1) while block k+1 is a pivot block; the other TRSM(I,k); the other
+    // UPD(I,J,k).  Every task waits only for tasks listed before it.
     for (int k = 0; k < kmax; ++k) {
+      if (k == 0)
+        for (int q = L.first; q < L.first + L.count; ++q) push(1, A.level_fronts[q], 0, 0, 0);
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int f = A.level_fronts[q];
-        if ((A.npiv[f] + T - 1) / T > k) push(1, f, k, k, k);
+        const int nbk = (A.npiv[f] + T - 1) / T;
+        if (k + 1 < nbk) push(5, f, k + 1, k + 1, k + 1);
       }
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int f = A.level_fronts[q];
         const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
         if (nbk <= k) continue;
-        for (int I = k + 1; I < R; ++I) push(2, f, k, I, k);
+        for (int I = k + 1; I < R; ++I)
+          if (!(I == k + 1 && k + 1 < nbk)) push(2, f, k, I, k);
       }
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int f = A.level_fronts[q];
         const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
         if (nbk <= k) continue;
         for (int J = k + 1; J < R; ++J)
-          for (int I = J; I < R; ++I) push(3, f, k, I, J);
+          for (int I = J; I < R; ++I)
+            if (!(I == k + 1 && J == k + 1 && k + 1 < nbk)) push(3, f, k, I, J);
       }
     }
     // INV(k) after the level's steps: the rest of each pivot block's inverse,

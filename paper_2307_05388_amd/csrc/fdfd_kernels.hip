@@ -812,7 +812,7 @@ struct TileArgs {
   int32_t ntiles;
 };
 
-enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3, T_INV = 4 };
+enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3, T_INV = 4, T_FUSED = 5 };
 
 struct Chunks {
   int p, u, m, nbk, nut;
@@ -896,6 +896,39 @@ __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, in
 // inverse.  One routine for both task types keeps a single inlined copy.
 enum { kDiagPart = 0, kDiagFull = 1, kInvOnly = 2 };
 
+// The LDS part of DIAG on a staged kBW x kBW block B (lower triangle): LDL^T,
+// 16 x 16 diagonal inverses, and for kDiagFull also the off-diagonal inverse
+// blocks; d in dd, 1/d in invd, T a 16 x 64 scratch.  kInvOnly: B holds the
+// factor of an earlier DIAG and only the off-diagonal inverse blocks are formed.
+template <typename R, typename C>
+__device__ __forceinline__ void diag_core(const KArgs& a, int s, C* B, C* dd, C* invd, C* T, int nb, int mode) {
+  double anorm = 0.0;
+  int npert = 0, nonfin = 0;
+  double minr = INFINITY;
+  if (mode != kInvOnly) {
+    anorm = anorm_of(a, s);
+    ldl_blocked(B, kBW, nb, nb, dd, invd, T, a.tau * anorm, anorm, npert, minr, nonfin);
+    invert_diag16(B, kBW, nb);
+  }
+  if (mode != kDiagPart) invert_offdiag(B, kBW, nb, T);
+  if (mode != kInvOnly && threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
+}
+
+// Writes the factored kBW x kBW pivot block from LDS to the panel (inverse
+// blocks below the diagonal, d on it); kInvOnly writes only the off-diagonal
+// 16 x 16 inverse blocks.
+template <typename C>
+__device__ __forceinline__ void diag_store(C* L, int m, const C* B, const C* dd, int nb, bool inv_only) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (inv_only) {
+    for (int c = wave; c < nb; c += 4)
+      if (lane < nb && (lane >> 4) > (c >> 4)) st_ag(L + (int64_t)c * m + lane, B[c * kBW + lane]);
+  } else {
+    for (int c = wave; c < nb; c += 4)
+      for (int r = c + lane; r < nb; r += 64) st_ag(L + (int64_t)c * m + r, (r > c) ? B[c * kBW + r] : dd[c]);
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void task_diag(const KArgs& a, int s, int f, int k, int mode, unsigned char* smem) {
   typedef typename Cx<R>::T C;
@@ -906,48 +939,20 @@ __device__ __forceinline__ void task_diag(const KArgs& a, int s, int f, int k, i
   const int p = a.npiv[f], m = p + a.nupd[f];
   const int k0 = k * kBW, nb = min(kBW, p - k0);
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m + k0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool inv_only = mode == kInvOnly;
-  stage_block(B, L, m, nb, nb, inv_only ? kStrict : kLower);
+  stage_block(B, L, m, nb, nb, mode == kInvOnly ? kStrict : kLower);
   __syncthreads();
-  double anorm = 0.0;
-  int npert = 0, nonfin = 0;
-  double minr = INFINITY;
-  if (!inv_only) {
-    anorm = anorm_of(a, s);
-    ldl_blocked(B, kBW, nb, nb, dd, invd, T, a.tau * anorm, anorm, npert, minr, nonfin);
-    invert_diag16(B, kBW, nb);
-  }
-  if (mode != kDiagPart) invert_offdiag(B, kBW, nb, T);
-  if (inv_only) {
-    for (int c = wave; c < nb; c += 4)
-      if (lane < nb && (lane >> 4) > (c >> 4)) st_ag(L + (int64_t)c * m + lane, B[c * kBW + lane]);
-  } else {
-    for (int c = wave; c < nb; c += 4)
-      for (int r = c + lane; r < nb; r += 64) st_ag(L + (int64_t)c * m + r, (r > c) ? B[c * kBW + r] : dd[c]);
-    if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
-  }
+  diag_core<R>(a, s, B, dd, invd, T, nb, mode);
+  diag_store(L, m, B, dd, nb, mode == kInvOnly);
 }
 
-// TRSM(I,k): tile (I,k) <- F_Ik L_kk^-T D_k^-1 by block forward substitution
-// over the 16-column blocks J of the pivot block, with w_JJ = L_JJ^-1 in the
-// diagonal sub-blocks:  V_J = F_J - sum_{K<J} X_K L_JK^T,  X_J = V_J w_JJ^T.
-// Thread t owns rows t%32 and t%32 + 32 and columns 2 (t/32) + {0,1} of a block.
-template <typename R>
-__device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, int I, unsigned char* smem) {
-  typedef typename Cx<R>::T C;
-  C* Xs = reinterpret_cast<C*>(smem);  // kBW x kBW column major: F_Ik, then X in place
-  C* Ls = Xs + kBW * kBW;              // kBW x kBW: the pivot block (L_JK, w_JJ, D)
-  C* Vs = Ls + kBW * kBW;              // kBW x 16
-  const Chunks ch(a.npiv[f], a.nupd[f]);
-  const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
-  const int r0 = ch.lo(I), nr = ch.hi(I) - r0;
-  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // zero padding beyond nr rows / nb columns keeps the products finite
-  stage_block(Xs, L + (int64_t)k0 * m + r0, m, nr, nb, kAll);
-  stage_block(Ls, L + (int64_t)k0 * m + k0, m, nb, nb, kLower);
-  __syncthreads();
+// TRSM in LDS: X <- F L_kk^-T (without D^-1) for a staged kBW x kBW tile Xs
+// (in place) and pivot block Ls, by block forward substitution over the
+// 16-column blocks J of the pivot block, with w_JJ = L_JJ^-1 in the diagonal
+// sub-blocks:  V_J = F_J - sum_{K<J} X_K L_JK^T,  X_J = V_J w_JJ^T.  Thread t
+// owns rows t%32 and t%32 + 32 and columns 2 (t/32) + {0,1} of a block.
+// Vs: kBW x 16 scratch.  Ends with a barrier.
+template <typename C>
+__device__ __forceinline__ void trsm_core(C* Xs, const C* Ls, C* Vs, int nb) {
   const int ra = threadIdx.x & 31, cb = 2 * (threadIdx.x >> 5);
   const int nsb = (nb + 15) / 16;
   for (int J = 0; J < nsb; ++J) {
@@ -995,6 +1000,25 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
       for (int y = 0; y < 2; ++y) Xs[(j0 + cb + y) * kBW + ra + 32 * x] = o[x][y];
     __syncthreads();
   }
+}
+
+// TRSM(I,k): tile (I,k) <- F_Ik L_kk^-T D_k^-1.
+template <typename R>
+__device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, int I, unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  C* Xs = reinterpret_cast<C*>(smem);  // kBW x kBW column major: F_Ik, then X in place
+  C* Ls = Xs + kBW * kBW;              // kBW x kBW: the pivot block (L_JK, w_JJ, D)
+  C* Vs = Ls + kBW * kBW;              // kBW x 16
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
+  const int r0 = ch.lo(I), nr = ch.hi(I) - r0;
+  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // zero padding beyond nr rows / nb columns keeps the products finite
+  stage_block(Xs, L + (int64_t)k0 * m + r0, m, nr, nb, kAll);
+  stage_block(Ls, L + (int64_t)k0 * m + k0, m, nb, nb, kLower);
+  __syncthreads();
+  trsm_core(Xs, Ls, Vs, nb);
   for (int c = wave; c < nb; c += 4)
     if (lane < nr) st_ag(L + (int64_t)(k0 + c) * m + r0 + lane, cmul(Xs[c * kBW + lane], cinv(Ls[c * kBW + c])));
 }
@@ -1098,6 +1122,59 @@ __device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, in
     if (dst[t]) st_ag(dst[t], csub(v[t], As[(wave + 4 * t) * kBW + lane]));
 }
 
+// FUSED(k): the critical chain of one pivot step in one workgroup,
+// TRSM(k, k-1) -> UPD(k, k, k-1) -> DIAG(k), with the intermediate tiles kept
+// in LDS.  L_{k,k-1} = X D^-1 is written out (and its version published
+// before the update, so the other updates of step k-1 can use it); the update
+// uses A = X D^-1 and B = X (= L_{k,k-1} D); the updated diagonal tile is
+// factored without a round trip through memory.
+template <typename R>
+__device__ __forceinline__ void task_fused(const KArgs& a, int s, int f, int k, int mode, int32_t* st,
+                                           unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  C* Xs = reinterpret_cast<C*>(smem);  // tile (k, k-1): F, X, L = X D^-1, then the update product
+  C* Ls = Xs + kBW * kBW;              // pivot block k-1; then X (B operand); then tile (k, k)
+  C* Vs = Ls + kBW * kBW;              // kBW x 16 scratch; D_{k-1}
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int m = ch.m, kp0 = (k - 1) * kBW, k0 = k * kBW, nb = min(kBW, ch.p - k0);
+  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  stage_block(Xs, L + (int64_t)kp0 * m + k0, m, nb, kBW, kAll);
+  stage_block(Ls, L + (int64_t)kp0 * m + kp0, m, kBW, kBW, kLower);
+  __syncthreads();
+  trsm_core(Xs, Ls, Vs, kBW);
+  if (threadIdx.x < kBW) Vs[threadIdx.x] = cinv(Ls[threadIdx.x * kBW + threadIdx.x]);
+  __syncthreads();
+  for (int c = wave; c < kBW; c += 4) {
+    const C x = Xs[c * kBW + lane];
+    const C l = cmul(x, Vs[c]);
+    Ls[c * kBW + lane] = x;
+    Xs[c * kBW + lane] = l;
+    if (lane < nb) st_ag(L + (int64_t)(kp0 + c) * m + k0 + lane, l);
+  }
+  drain_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(st + tile_id(k, k - 1), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  mfma_tile_abt<R>(Xs, Ls, Xs);
+  // tile (k, k) - product, into Ls (lower triangle), then DIAG(k) with its
+  // pivots and scratch in the Xs region
+  C t[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = wave + 4 * q;
+    const bool keep = c < nb && lane < nb && lane >= c;
+    t[q] = keep ? csub(ld_ag(L + (int64_t)(k0 + c) * m + k0 + lane), Xs[c * kBW + lane]) : czero<C>();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) Ls[(wave + 4 * q) * kBW + lane] = t[q];
+  __syncthreads();
+  C* dd = Xs;
+  C* invd = dd + kBW;
+  C* T = invd + kBW;
+  diag_core<R>(a, s, Ls, dd, invd, T, nb, mode);
+  diag_store(L + (int64_t)k0 * m + k0, m, Ls, dd, nb, false);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, Queue q) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1125,6 +1202,10 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
         wait_value(st + tile_id(I, k), k + 1, a.st);
       } else if (type == T_INV) {
         for (int i = k + 1; i < ch.nbk + ch.nut; ++i) wait_value(st + tile_id(i, k), k + 2, a.st);
+      } else if (type == T_FUSED) {
+        wait_value(st + tile_id(k - 1, k - 1), k + 1, a.st);
+        wait_value(st + tile_id(k, k - 1), k, a.st);
+        wait_value(st + tile_id(k, k), k, a.st);
       } else {
         wait_value(st + tile_id(I, k), k + 2, a.st);
         wait_value(st + tile_id(J, k), k + 2, a.st);
@@ -1147,6 +1228,10 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     } else if (type == T_TRSM) {
       task_trsm<R>(a, s, f, k, I, smem_raw);
       tile = tile_id(I, k);
+      ver = k + 2;
+    } else if (type == T_FUSED) {
+      task_fused<R>(a, s, f, k, k == ch.nbk + ch.nut - 1 ? kDiagFull : kDiagPart, st, smem_raw);
+      tile = tile_id(k, k);
       ver = k + 2;
     } else {
       task_upd<R>(a, s, f, k, I, J, smem_raw);
