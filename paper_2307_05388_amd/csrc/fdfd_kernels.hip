@@ -1318,10 +1318,21 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     const C* Xb = L + (int64_t)k0 * m + k0;
     for (int col = 0; col < nrhs; ++col) {
       const C* Vb = V + col * m + k0;
+      // j = wave, wave + 4, ... < lane: eight predicated loads in flight together
       C acc = czero<C>();
-      if (lane < kn) {
-#pragma unroll 4
-        for (int j = wave; j < lane; j += 4) acc = cadd(acc, cmul(Xb[(int64_t)j * m + lane], Vb[j]));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        C xv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int j = wave + 4 * (8 * h + t);
+          xv[t] = (lane < kn && j < lane) ? Xb[(int64_t)j * m + lane] : czero<C>();
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int j = wave + 4 * (8 * h + t);
+          if (lane < kn && j < lane) acc = cadd(acc, cmul(xv[t], Vb[j]));
+        }
       }
       red[wave * kBW + lane] = acc;
       __syncthreads();
@@ -1336,15 +1347,13 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
       for (int col = 0; col < nrhs; ++col) {
         const C* Vb = V + col * m + k0;
         C acc = V[col * m + i];
-        int j = 0;
-        for (; j + 16 <= kn; j += 16) {
-          C l[16];
+        for (int j = 0; j < kn; j += 8) {  // predicated batches: one memory latency each
+          C l[8];
 #pragma unroll
-          for (int t = 0; t < 16; ++t) l[t] = L[(int64_t)(k0 + j + t) * m + i];
+          for (int t = 0; t < 8; ++t) l[t] = j + t < kn ? L[(int64_t)(k0 + j + t) * m + i] : czero<C>();
 #pragma unroll
-          for (int t = 0; t < 16; ++t) acc = cfms(acc, l[t], Vb[j + t]);
+          for (int t = 0; t < 8; ++t) acc = cfms(acc, l[t], j + t < kn ? Vb[j + t] : czero<C>());
         }
-        for (; j < kn; ++j) acc = cfms(acc, L[(int64_t)(k0 + j) * m + i], Vb[j]);
         V[col * m + i] = acc;
       }
     }
@@ -1400,15 +1409,13 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
         const C* Xc = X + col * m;
         C acc = czero<C>();
         if (lane < kn) {
-          int i = r0;
-          for (; i + 8 <= r1; i += 8) {
+          for (int i = r0; i < r1; i += 8) {  // predicated batches: one memory latency each
             C l[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) l[t] = Lc[i + t];
+            for (int t = 0; t < 8; ++t) l[t] = i + t < r1 ? Lc[i + t] : czero<C>();
 #pragma unroll
-            for (int t = 0; t < 8; ++t) acc = cadd(acc, cmul(l[t], Xc[i + t]));
+            for (int t = 0; t < 8; ++t) acc = cadd(acc, cmul(l[t], i + t < r1 ? Xc[i + t] : czero<C>()));
           }
-          for (; i < r1; ++i) acc = cadd(acc, cmul(Lc[i], Xc[i]));
         }
         red[(col * 4 + wave) * kBW + lane] = acc;
       }
@@ -1429,7 +1436,14 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
         const C* Xb = X + col * m + k0;
         C acc = czero<C>();
         if (lane < kn) {
-          for (int i = max(r0, lane + 1); i < r1; ++i) acc = cadd(acc, cmul(Xcol[i], Xb[i]));
+          const int i0 = max(r0, lane + 1);
+          for (int i = i0; i < r1; i += 8) {  // predicated batches: one memory latency each
+            C l[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) l[t] = i + t < r1 ? Xcol[i + t] : czero<C>();
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc = cadd(acc, cmul(l[t], i + t < r1 ? Xb[i + t] : czero<C>()));
+          }
         }
         red[(col * 4 + wave) * kBW + lane] = acc;
       }
