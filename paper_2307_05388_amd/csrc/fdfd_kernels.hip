@@ -479,10 +479,14 @@ __device__ void ldl_sub16(C* F, int ld, int o, int b, int m, C* dd, C* invd, C* 
         invd[o + k] = inv;
       }
       const C lk = cmul(row[k], inv);
+      // Branch-free: lanes l < o + j only touch entries above the diagonal,
+      // which are never published (colbuf reads start at k) nor stored.
 #pragma unroll
       for (int j = k + 1; j < 16; ++j)
-        if (j < b && l >= o + j) row[j] = cfms(row[j], lk, cj[j]);
-      if (l > o + k) row[k] = lk;
+        if (j < b) row[j] = cfms(row[j], lk, cj[j]);
+      const bool below = l > o + k;
+      row[k].x = below ? lk.x : row[k].x;
+      row[k].y = below ? lk.y : row[k].y;
       __builtin_amdgcn_wave_barrier();
     }
   }
@@ -530,8 +534,9 @@ __device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const 
     C lr[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) lr[q] = q < b ? F[(o + q) * ld + r] : czero<C>();
-    const int cend = min(p, r + 1);
-    for (int c = c0 + wave; c < cend; c += 4) {
+    // uniform trip count: rows r < c update entries above the diagonal,
+    // which no later step reads
+    for (int c = c0 + wave; c < p; c += 4) {
       const C* sc = Lsc + (c - c0) * 16;
       C acc = F[c * ld + r];
 #pragma unroll
@@ -575,17 +580,18 @@ __device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
   const int nsb = (nb + 15) / 16;
   if (wave < nsb) {
     const int o = 16 * wave, b = min(16, nb - o), j = lane;
+    // Branch-free: x[k] = 0 for k < j, so the full sums over k < i give the
+    // column (and 0 above the diagonal); only i < b is tested (uniform).
     C x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       C v = czero<C>();
-      if (i == j) {
-        v.x = 1;
-      } else if (i > j && i < b) {
+      if (i < b) {
 #pragma unroll
-        for (int k = 0; k < i; ++k)
-          if (k >= j) v = cfms(v, F[(o + k) * ld + o + i], x[k]);
+        for (int k = 0; k < i; ++k) v = cfms(v, F[(o + k) * ld + o + i], x[k]);
       }
+      v.x = i == j ? 1 : v.x;
+      v.y = i == j ? 0 : v.y;
       x[i] = v;
       // keeps the row's LDS loads from being hoisted across rows (register pressure)
       __builtin_amdgcn_sched_barrier(0);
