@@ -438,6 +438,26 @@ __device__ __forceinline__ void publish(const Queue& q, int64_t idx) {
 // ... so no index arithmetic needs a division.
 // ---------------------------------------------------------------------------
 
+// Matrix-core instructions used on LDS-resident operands: 16x16x4 products in
+// the factor precision.  Operand lanes: A row l%16 / B column l%16 at
+// k = l/16; the result row of register r differs between the f64 and f32
+// instructions (row()); its column is l%16.
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
 template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
   v.x = __shfl(v.x, lane);
   v.y = __shfl(v.y, lane);
@@ -546,12 +566,61 @@ __device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const 
   }
 }
 
+// Trailing update on the matrix cores for a kBW x kBW block (ld = kBW, the
+// DIAG task): F[r][c] -= sum_q L[r][o+q] d_q L[c][o+q] for c0 <= c <= r < kBW,
+// with c0 = o + 16.  The d-scaled rows go to Bt[q][c] (scratch, 16 x kBW);
+// the lower 16 x 16 output blocks are shared out over the waves, K = 16 as
+// four 4-deep k-steps of four real MFMAs.  Entries above the diagonal inside
+// diagonal blocks are updated too; nothing reads them.
+template <typename C>
+__device__ __forceinline__ void trail_mfma(C* F, int o, int b, int c0, int p, const C* dd, C* Bt) {
+  typedef decltype(F->x) R;
+  typedef typename Mfma<R>::v4 v4;
+  for (int idx = threadIdx.x; idx < 16 * kBW; idx += kThreads) {
+    const int q = idx >> 6, c = idx & 63;
+    Bt[idx] = (q < b && c >= c0 && c < p) ? cmul(F[(o + q) * kBW + c], dd[o + q]) : czero<C>();
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, i = l & 15, kq = l >> 4;
+  const int nbr = (kBW - c0) >> 4, bb0 = c0 >> 4, nblk = nbr * (nbr + 1) / 2;
+  for (int bid = wave; bid < nblk; bid += 4) {
+    // bid -> (bi, bj), bj <= bi, counted from bb0
+    int bi = 0, rem = bid;
+    while (rem > bi) {
+      rem -= bi + 1;
+      ++bi;
+    }
+    const int BI = bb0 + bi, BJ = bb0 + rem;
+    v4 re = v4{0, 0, 0, 0}, im = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int q = 4 * ks + kq;
+      const C av = F[(o + q) * kBW + 16 * BI + i];
+      const C bv = Bt[q * kBW + 16 * BJ + i];
+      re = Mfma<R>::op(av.x, bv.x, re);
+      im = Mfma<R>::op(av.x, bv.y, im);
+      re = Mfma<R>::op(-av.y, bv.y, re);
+      im = Mfma<R>::op(av.y, bv.x, im);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      C* dst = F + (16 * BJ + i) * kBW + 16 * BI + Mfma<R>::row(l, rr);
+      C v = *dst;
+      v.x -= re[rr];
+      v.y -= im[rr];
+      *dst = v;
+    }
+  }
+}
+
 // Blocked right-looking LDL^T of the first p (<= 64) columns of an m-row LDS
 // panel: per 16-column sub-block, wave 0 factors the diagonal sub-block, all
 // threads solve the rows below it and update the remaining panel columns.
 // Leaves the unit-lower L in place and d, 1/d in dd / invd.
 // scratch: 16 x 64 entries of LDS (pivot column buffer, scaled columns).
-template <typename C>
+// DiagTile: the kBW x kBW pivot block of the DIAG task (ld = m = kBW), whose
+// trailing updates run on the matrix cores.
+template <bool DiagTile = false, typename C>
 __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scratch, double thr, double anorm,
                             int& npert, double& minr, int& nonfin) {
   for (int o = 0; o < p; o += 16) {
@@ -563,7 +632,8 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scrat
       __syncthreads();
     }
     if (o + b < p) {
-      trail16(F, ld, o, b, o + b, p, m, dd, scratch);
+      if (DiagTile) trail_mfma(F, o, b, o + b, p, dd, scratch);
+      else trail16(F, ld, o, b, o + b, p, m, dd, scratch);
       __syncthreads();
     }
   }
@@ -913,7 +983,7 @@ __device__ __forceinline__ void diag_core(const KArgs& a, int s, C* B, C* dd, C*
   double minr = INFINITY;
   if (mode != kInvOnly) {
     anorm = anorm_of(a, s);
-    ldl_blocked(B, kBW, nb, nb, dd, invd, T, a.tau * anorm, anorm, npert, minr, nonfin);
+    ldl_blocked<true>(B, kBW, kBW, nb, dd, invd, T, a.tau * anorm, anorm, npert, minr, nonfin);
     invert_diag16(B, kBW, nb);
   }
   if (mode != kDiagPart) invert_offdiag(B, kBW, nb, T);
@@ -1037,22 +1107,6 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
 // A row l%16 / B column l%16 at k = l/16; the result rows per register differ
 // between the f64 and f32 instructions (Mfma::row).  O may alias A or B: the
 // products finish (barrier) before O is written, and a barrier follows.
-template <typename R> struct Mfma;
-template <> struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-template <> struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
-
 template <typename R, typename C>
 __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, C* O) {
   typedef typename Mfma<R>::v4 v4;
@@ -1093,6 +1147,59 @@ __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, C* O) {
       v.x = re[bj][r];
       v.y = im[bj][r];
       O[(16 * bj + i) * kBW + 16 * wave + Mfma<R>::row(l, r)] = v;
+    }
+  __syncthreads();
+}
+
+// Lower block triangle of the same product (the 10 of 16 output blocks with
+// bj <= bi; what a diagonal tile's update needs), shared out over the waves
+// three, three, two and two blocks at a time.  O may alias A or B.
+template <typename R, typename C>
+__device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O) {
+  typedef typename Mfma<R>::v4 v4;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = l & 15, kq = l >> 4;
+  // (bi, bj) per wave: {(3,0),(3,1),(0,0)}, {(3,2),(3,3),(1,0)}, {(2,0),(2,1)}, {(2,2),(1,1)}
+  const int nblk = wave < 2 ? 3 : 2;
+  int bi[3], bj[3];
+  bi[0] = wave < 2 ? 3 : 2;
+  bj[0] = wave == 0 ? 0 : wave == 1 ? 2 : wave == 2 ? 0 : 2;
+  bi[1] = wave < 2 ? 3 : wave == 2 ? 2 : 1;
+  bj[1] = wave == 0 ? 1 : wave == 1 ? 3 : 1;
+  bi[2] = wave == 0 ? 0 : 1;
+  bj[2] = 0;
+  v4 re[3], im[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    re[t] = v4{0, 0, 0, 0};
+    im[t] = v4{0, 0, 0, 0};
+  }
+#pragma unroll 4
+  for (int k0 = 0; k0 < kBW; k0 += 4) {
+    const int q = k0 + kq;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t < nblk) {  // uniform per wave
+        const C av = A[q * kBW + 16 * bi[t] + i];
+        const C bv = B[q * kBW + 16 * bj[t] + i];
+        re[t] = Mfma<R>::op(av.x, bv.x, re[t]);
+        im[t] = Mfma<R>::op(av.x, bv.y, im[t]);
+        re[t] = Mfma<R>::op(-av.y, bv.y, re[t]);
+        im[t] = Mfma<R>::op(av.y, bv.x, im[t]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (t < nblk) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C v;
+        v.x = re[t][r];
+        v.y = im[t][r];
+        O[(16 * bj[t] + i) * kBW + 16 * bi[t] + Mfma<R>::row(l, r)] = v;
+      }
     }
   __syncthreads();
 }
@@ -1161,7 +1268,7 @@ __device__ __forceinline__ void task_fused(const KArgs& a, int s, int f, int k, 
   drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(st + tile_id(k, k - 1), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  mfma_tile_abt<R>(Xs, Ls, Xs);
+  mfma_tile_abt_lower<R>(Xs, Ls, Xs);
   // tile (k, k) - product, into Ls (lower triangle), then DIAG(k) with its
   // pivots and scratch in the Xs region
   C t[16];
