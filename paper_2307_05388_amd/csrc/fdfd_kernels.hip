@@ -1389,6 +1389,8 @@ struct SweepArgs {
   void* wv;
   const int* flag;     // refinement converged: skip the launch
   int32_t nrhs, scale_src, accumulate;
+  DevStatus* st;       // with status_mode >= 0: record "no refinement" for that solve
+  int32_t status_mode; // -1, 0 (forward solve) or 1 (adjoint solve)
 };
 
 // One front of the forward sweep.  V = [rhs_p; 0] + the children's update
@@ -1590,6 +1592,18 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   if (done(w.flag)) return;
+  if (w.status_mode >= 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    // a solve without refinement: no steps, no residual, no failure
+    if (w.status_mode == 0) {
+      w.st->ir_steps_solve = 0;
+      w.st->rel_solve = -1.0;
+      w.st->ir_failed_solve = 0;
+    } else {
+      w.st->ir_steps_adj = 0;
+      w.st->rel_adj = -1.0;
+      w.st->ir_failed_adj = 0;
+    }
+  }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
   for (;;) {
@@ -1956,7 +1970,7 @@ size_t sweep_lds(const Plan& P, int nrhs) {
 // One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src.
 template <typename R>
 void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
-           int accumulate, const int* flag, hipStream_t st) {
+           int accumulate, const int* flag, hipStream_t st, int status_mode = -1) {
   const int nt = P.an.nfronts * P.desc.nsys;
   const size_t lds = sweep_lds(P, nrhs);
   SweepArgs w;
@@ -1968,6 +1982,8 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   w.nrhs = nrhs;
   w.scale_src = scale_in;
   w.accumulate = accumulate;
+  w.st = P.status;
+  w.status_mode = status_mode;
   const int32_t* lf = P.t.level_fronts;
   const int nsys = P.desc.nsys;
   // algorithmic bytes: the lower-trapezoid factor once, the input vector read
@@ -2010,6 +2026,11 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
   double2* xdst = mode == 0 ? x_out : P.xw;
   const int scale = mode == 0 ? 1 : 0;
   const int* flag = &P.status->ir_flag;
+  if (max_ir <= 0) {
+    // no refinement: the forward sweep records the solve's status itself
+    sweep<R>(P, a, rhs, xdst, nrhs, scale, 0, nullptr, st, mode);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_ir_begin, dim3(1), dim3(1), 0, st, P.status);
   sweep<R>(P, a, rhs, xdst, nrhs, scale, 0, nullptr, st);
   ResArgs ra;
@@ -2039,7 +2060,7 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
     Prof pr(P, st, KC_RESIDUAL, rbytes, 0.0);
     hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
   }
-  hipLaunchKernelGGL(k_ir_end, dim3(1), dim3(1), 0, st, P.status, mode, max_ir > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_ir_end, dim3(1), dim3(1), 0, st, P.status, mode, 1);
   return hipGetLastError();
 }
 
