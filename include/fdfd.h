@@ -29,8 +29,12 @@
  *
  * Streams and errors.  Calls enqueue on hip_stream (a hipStream_t; NULL is
  * the null stream) and return without synchronising, except fdfd_analyze,
- * fdfd_query and fdfd_destroy.  Argument and state errors are returned at
- * once and enqueue nothing.  Numeric conditions found on the device (pivot
+ * fdfd_query and fdfd_destroy.  The enqueued work reads no per-call state from
+ * the host, so a caller may record refactor / solve / adjoint calls into its
+ * own HIP graph (stream capture) and replay it: each replay uses the values
+ * then in the captured buffers, and the omegas given at capture (plans made
+ * with FDFD_PROFILE or FDFD_TRACE excepted).  Argument and state errors are
+ * returned at once and enqueue nothing.  Numeric conditions found on the device (pivot
  * perturbation, non-finite values, refinement that misses its tolerance) are
  * recorded in a device status word and reported by fdfd_query.  No C++
  * exception crosses this interface.  A plan is not thread safe.
@@ -64,6 +68,11 @@ typedef enum {
                                   /* only fdfd_query / fdfd_get_table work     */
 #define FDFD_PROFILE 2            /* bracket every kernel launch with HIP events */
                                   /* (read with fdfd_kernel_stats)             */
+#define FDFD_GRAPH 4              /* record the launch chain of each refactor,  */
+                                  /* solve and adjoint call in a HIP graph once */
+                                  /* per argument set (pointers, sizes, omegas, */
+                                  /* refinement settings) and replay it; not    */
+                                  /* with FDFD_PROFILE or FDFD_TRACE            */
 
 typedef struct {
   int32_t nx, ny;          /* grid cells, nx, ny >= 2                           */
@@ -73,7 +82,7 @@ typedef struct {
   int32_t prec;            /* fdfd_prec                                         */
   int32_t device;          /* HIP device ordinal, -1 = current device          */
   int32_t leaf;            /* cells per undivided dissection leaf, 0 = default */
-  int32_t flags;           /* FDFD_ANALYZE_HOST_ONLY                            */
+  int32_t flags;           /* FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH */
   int64_t mem_cap_bytes;   /* refuse plans needing more device memory, 0 = off  */
 } fdfd_desc;
 

@@ -114,6 +114,10 @@ fdfd_status alloc(Plan& P, void** dst, size_t bytes) {
 }
 
 void free_all(Plan& P) {
+  for (auto& g : P.graphs) (void)hipGraphExecDestroy(g.exec);
+  P.graphs.clear();
+  if (P.cap_stream) (void)hipStreamDestroy(P.cap_stream);
+  P.cap_stream = nullptr;
   for (const auto& t : P.pending) {
     (void)hipEventDestroy(t.e0);
     (void)hipEventDestroy(t.e1);
@@ -229,6 +233,64 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
   P.ntile_tasks = (int32_t)(tasks.size() / 5);
 }
 
+// Graph replay of launch chains (FDFD_GRAPH).  A chain is recorded on the
+// plan's own capture stream (the caller's may be the null stream, which cannot
+// be captured), instantiated once per argument set and launched on the
+// caller's stream.  While the caller records a graph of its own, the chain is
+// launched directly into that recording.
+constexpr size_t kMaxGraphs = 16;
+
+template <typename Launch>
+fdfd_status run_chain(Plan& P, std::vector<uint64_t> key, hipStream_t st, const char* what, Launch launch) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool outer = hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+  if (!(P.desc.flags & FDFD_GRAPH) || outer) {
+    const hipError_t e = launch(st);
+    return e == hipSuccess ? FDFD_OK : hip_fail(&P, e, what);
+  }
+  size_t i = 0;
+  while (i < P.graphs.size() && P.graphs[i].key != key) ++i;
+  if (i == P.graphs.size()) {
+    if (P.graphs.size() >= kMaxGraphs) {
+      // the oldest graph may still run on the last stream
+      (void)hipStreamSynchronize(P.last_stream);
+      (void)hipStreamSynchronize(st);
+      (void)hipGraphExecDestroy(P.graphs.front().exec);
+      P.graphs.erase(P.graphs.begin());
+    }
+    hipError_t e = hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(&P, e, "hipStreamBeginCapture");
+    const hipError_t el = launch(P.cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(P.cap_stream, &g);
+    if (el != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(&P, el != hipSuccess ? el : e, what);
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiateWithFlags(&ex, g, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(&P, e, "hipGraphInstantiate");
+    P.graphs.push_back(Plan::GraphEntry{std::move(key), ex});
+    ++P.graph_records;
+    i = P.graphs.size() - 1;
+  } else if (i + 1 != P.graphs.size()) {
+    Plan::GraphEntry g = std::move(P.graphs[i]);
+    P.graphs.erase(P.graphs.begin() + i);
+    P.graphs.push_back(std::move(g));
+    i = P.graphs.size() - 1;
+  }
+  const hipError_t e = hipGraphLaunch(P.graphs[i].exec, st);
+  return e == hipSuccess ? FDFD_OK : hip_fail(&P, e, "hipGraphLaunch");
+}
+
+inline uint64_t bits(const void* p) { return (uint64_t)(uintptr_t)p; }
+inline uint64_t bits(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, sizeof(u));
+  return u;
+}
+
 fdfd_status check_desc(const fdfd_desc* d) {
   if (!d) return fail(nullptr, FDFD_ERR_ARG, "desc is NULL");
   if (d->nx < 2 || d->ny < 2) return fail(nullptr, FDFD_ERR_ARG, "nx and ny must be >= 2");
@@ -239,6 +301,10 @@ fdfd_status check_desc(const fdfd_desc* d) {
   if (d->prec != FDFD_C128 && d->prec != FDFD_C64_IR) return fail(nullptr, FDFD_ERR_ARG, "unknown precision");
   if (d->leaf < 0) return fail(nullptr, FDFD_ERR_ARG, "leaf must be >= 0");
   if (d->mem_cap_bytes < 0) return fail(nullptr, FDFD_ERR_ARG, "mem_cap_bytes must be >= 0");
+  if (d->flags & ~(FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH))
+    return fail(nullptr, FDFD_ERR_ARG, "unknown desc flags");
+  if ((d->flags & FDFD_GRAPH) && ((d->flags & FDFD_PROFILE) || std::getenv("FDFD_TRACE")))
+    return fail(nullptr, FDFD_ERR_ARG, "FDFD_GRAPH cannot be combined with FDFD_PROFILE or FDFD_TRACE");
   if ((int64_t)d->nx * d->ny > ((int64_t)1 << 28)) return fail(nullptr, FDFD_ERR_ARG, "grid too large");
   return FDFD_OK;
 }
@@ -277,6 +343,13 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.host_only = (desc->flags & FDFD_ANALYZE_HOST_ONLY) != 0;
   P.is_c64 = desc->prec == FDFD_C64_IR;
   P.csize = P.is_c64 ? 8 : 16;
+  // static pivoting threshold: sqrt of the factor precision's unit roundoff
+  // unless FDFD_PIVOT_TAU overrides it
+  P.pivot_tau = P.is_c64 ? 2.44140625e-4 : 1.0536712127723509e-8;
+  if (const char* t = std::getenv("FDFD_PIVOT_TAU")) {
+    const double v = std::atof(t);
+    if (v > 0.0 && v < 1.0) P.pivot_tau = v;
+  }
   const int leaf = desc->leaf > 0 ? desc->leaf : env_int("FDFD_LEAF", 36);
   const std::string err = fdfd::analyze_grid(desc->nx, desc->ny, leaf, P.an);
   if (!err.empty()) {
@@ -394,9 +467,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(alloc(P, (void**)&P.res, nsys * R * N * 16));
     TRY(alloc(P, (void**)&P.partial, nsys * R * P.res_blocks * 16));
     TRY(alloc(P, (void**)&P.status, sizeof(fdfd::DevStatus)));
-    TRY(alloc(P, (void**)&P.counters, 64));
+    TRY(alloc(P, (void**)&P.counters, fdfd::kCounterBytes));
     TRY(alloc(P, (void**)&P.done, nsys * (int64_t)A.nfronts * 4));
-    hipError_t e = hipMemset(P.counters, 0, 64);
+    hipError_t e = hipMemset(P.counters, 0, fdfd::kCounterBytes);
     if (e == hipSuccess) e = hipMemset(P.done, 0, nsys * (int64_t)A.nfronts * 4);
     if (e == hipSuccess) e = hipMemset(P.status, 0, sizeof(fdfd::DevStatus));
     if (e != hipSuccess) {
@@ -412,6 +485,13 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
       for (int k = 0; k < 4; ++k) {
         P.trace_cap[k] = caps[k];
         if (caps[k] > 0) TRY(alloc(P, (void**)&P.trace_buf[k], (size_t)caps[k] * 4 * sizeof(long long)));
+      }
+    }
+    if (desc->flags & FDFD_GRAPH) {
+      e = hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        st = hip_fail(&P, e, "hipStreamCreate");
+        goto bad;
       }
     }
     e = hipHostMalloc((void**)&P.status_host, sizeof(fdfd::DevStatus), hipHostMallocDefault);
@@ -455,8 +535,12 @@ fdfd_status fdfd_refactor(fdfd_plan plan, const double* eps_dev, int64_t eps_sys
   DeviceGuard guard(P.device);
   P.omega_host = om;
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = fdfd::launch_refactor(P, eps_dev, eps_sys_stride, st);
-  if (e != hipSuccess) return hip_fail(&P, e, "refactor launch");
+  std::vector<uint64_t> key = {0, bits(eps_dev), (uint64_t)eps_sys_stride};
+  for (double w : om) key.push_back(bits(w));
+  const fdfd_status r = run_chain(P, std::move(key), st, "refactor launch", [&](hipStream_t s) {
+    return fdfd::launch_refactor(P, eps_dev, eps_sys_stride, s);
+  });
+  if (r != FDFD_OK) return r;
   P.last_stream = st;
   P.factored = true;
   return FDFD_OK;
@@ -474,8 +558,12 @@ fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t n
   if (!(ir_tol > 0.0)) ir_tol = 1e-12;
   DeviceGuard guard(P.device);
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = fdfd::launch_solve(P, 0, (const double2*)b_dev, (double2*)x_dev, nrhs, max_ir, ir_tol, st);
-  if (e != hipSuccess) return hip_fail(&P, e, "solve launch");
+  const fdfd_status r = run_chain(
+      P, {1, bits(b_dev), bits(x_dev), (uint64_t)nrhs, (uint64_t)max_ir, bits(ir_tol)}, st, "solve launch",
+      [&](hipStream_t s) {
+        return fdfd::launch_solve(P, 0, (const double2*)b_dev, (double2*)x_dev, nrhs, max_ir, ir_tol, s);
+      });
+  if (r != FDFD_OK) return r;
   P.last_stream = st;
   return FDFD_OK;
 }
@@ -494,10 +582,18 @@ fdfd_status fdfd_adjoint_grad(fdfd_plan plan, const void* x_dev, const void* g_d
   if (!(ir_tol > 0.0)) ir_tol = 1e-12;
   DeviceGuard guard(P.device);
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = fdfd::launch_solve(P, 1, (const double2*)g_dev, nullptr, nrhs, max_ir, ir_tol, st);
-  if (e != hipSuccess) return hip_fail(&P, e, "adjoint launch");
-  e = fdfd::launch_gradient(P, (const double2*)x_dev, P.xw, nrhs, (double2*)lambda_dev, grad_dev, flags, st);
-  if (e != hipSuccess) return hip_fail(&P, e, "gradient launch");
+  const fdfd_status r = run_chain(
+      P,
+      {2, bits(x_dev), bits(g_dev), (uint64_t)nrhs, (uint64_t)max_ir, bits(ir_tol), bits(lambda_dev),
+       bits(grad_dev), (uint64_t)flags},
+      st, "adjoint launch", [&](hipStream_t s) {
+        hipError_t e = fdfd::launch_solve(P, 1, (const double2*)g_dev, nullptr, nrhs, max_ir, ir_tol, s);
+        if (e == hipSuccess)
+          e = fdfd::launch_gradient(P, (const double2*)x_dev, P.xw, nrhs, (double2*)lambda_dev, grad_dev, flags,
+                                    s);
+        return e;
+      });
+  if (r != FDFD_OK) return r;
   P.last_stream = st;
   return FDFD_OK;
 }

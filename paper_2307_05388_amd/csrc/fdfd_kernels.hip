@@ -355,12 +355,25 @@ __global__ __launch_bounds__(kThreads) void k_anorm(KArgs a) {
 constexpr int kSpinLimit = 1 << 24;
 
 struct Queue {
-  int32_t* counter;  // [0] next item, [1] workgroups that have left
+  int32_t* counter;  // [0] next item, [1] workgroups that have left, [kEpochSlot] last epoch
   int32_t* done;     // [nsys][nfronts] epoch of the last completion
   DevStatus* st;
   long long* trace;  // optional: per item claim / ready / finish times and workgroup
-  int32_t epoch, ntasks, wait;
+  int32_t ntasks, wait;
 };
+
+// The launch's epoch is read from device memory (one past the previous
+// launch's) rather than passed by the host, so the same launch recorded in a
+// HIP graph gets a fresh epoch on every replay.  Every workgroup reads it
+// before it can leave, and the last one to leave stores it back.  The value
+// was written by an earlier launch on the stream, which the launch boundary
+// makes visible, so a plain (cached) load suffices: an agent-scope load from
+// thousands of workgroups at once would queue on one memory channel.  The
+// value is made wave-uniform explicitly; left to the compiler it shifted the
+// register allocation of the forward sweep into scratch spills.
+__device__ __forceinline__ int launch_epoch(const Queue& q) {
+  return __builtin_amdgcn_readfirstlane(q.counter[kEpochSlot]) + 1;
+}
 
 __device__ __forceinline__ void trace_mark(const Queue& q, int t, int slot) {
   if (q.trace && threadIdx.x == 0 && t < q.ntasks) q.trace[4 * (int64_t)t + slot] = (long long)wall_clock64();
@@ -376,12 +389,13 @@ __device__ __forceinline__ int claim(const Queue& q, int* sh) {
   return t;
 }
 
-__device__ __forceinline__ void leave(const Queue& q) {
+__device__ __forceinline__ void leave(const Queue& q, int ep) {
   if (threadIdx.x == 0) {
     const int n = atomicAdd(&q.counter[1], 1);
     if (n == (int)(gridDim.x * gridDim.y * gridDim.z) - 1) {
       q.counter[0] = 0;
       q.counter[1] = 0;
+      __hip_atomic_store(q.counter + kEpochSlot, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -390,9 +404,9 @@ __device__ __forceinline__ void leave(const Queue& q) {
 // caches without invalidating them).  Once every awaited flag is seen the
 // caller issues a workgroup-scope acquire (it keeps the data loads below the
 // poll; those loads are agent-coherent themselves) and a barrier.
-__device__ __forceinline__ void wait_flag(const Queue& q, const int32_t* p) {
+__device__ __forceinline__ void wait_flag(const Queue& q, int ep, const int32_t* p) {
   int it = 0;
-  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != q.epoch) {
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep) {
     if (++it > kSpinLimit) {
       atomicExch(&q.st->spin_timeout, 1);
       break;
@@ -401,18 +415,18 @@ __device__ __forceinline__ void wait_flag(const Queue& q, const int32_t* p) {
   }
 }
 
-__device__ __forceinline__ void wait_children(const Queue& q, const KArgs& a, int s, int f) {
+__device__ __forceinline__ void wait_children(const Queue& q, int ep, const KArgs& a, int s, int f) {
   if (threadIdx.x == 0) {
     for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k)
-      wait_flag(q, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
+      wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ void wait_parent(const Queue& q, const KArgs& a, int s, int f) {
+__device__ __forceinline__ void wait_parent(const Queue& q, int ep, const KArgs& a, int s, int f) {
   if (threadIdx.x == 0 && a.parent[f] >= 0) {
-    wait_flag(q, q.done + (int64_t)s * a.nfronts + a.parent[f]);
+    wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + a.parent[f]);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
@@ -426,10 +440,10 @@ __device__ __forceinline__ void drain_stores() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained (gfx9 encoding)
 }
 
-__device__ __forceinline__ void publish(const Queue& q, int64_t idx) {
+__device__ __forceinline__ void publish(const Queue& q, int ep, int64_t idx) {
   drain_stores();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(q.done + idx, q.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(q.done + idx, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,7 +751,7 @@ __device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
 // diagonal.
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ void small_front(const KArgs& a, const Queue& q, int s, int f, unsigned char* smem_raw) {
+__device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f, unsigned char* smem_raw) {
   typedef typename Cx<R>::T C;
   C* F = reinterpret_cast<C*>(smem_raw);
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
@@ -832,7 +846,7 @@ __device__ void small_front(const KArgs& a, const Queue& q, int s, int f, unsign
     }
   }
   // the parent needs only the update block: release it before the inverse
-  publish(q, s * a.nfronts + f);
+  publish(q, ep, s * a.nfronts + f);
   invert_blocked(F, m, p, invd + p);
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   for (int c = wave; c < p; c += 4)
@@ -853,16 +867,17 @@ template <typename R>
 __global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, const int32_t* order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
+  const int ep = launch_epoch(q);
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
     const int f = order[t / a.nsys], s = t % a.nsys;
-    if (q.wait) wait_children(q, a, s, f);
+    if (q.wait) wait_children(q, ep, a, s, f);
     trace_mark(q, t, 1);
-    small_front<R>(a, q, s, f, smem_raw);
+    small_front<R>(a, q, ep, s, f, smem_raw);
     trace_mark(q, t, 2);
   }
-  leave(q);
+  leave(q, ep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1292,6 +1307,7 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, Queue q) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
+  const int ep = launch_epoch(q);
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
@@ -1360,7 +1376,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     }
     trace_mark(q, t, 2);
   }
-  leave(q);
+  leave(q, ep);
 }
 
 // Clears tile versions and completion counts before the task-graph launch.
@@ -1606,17 +1622,18 @@ __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Qu
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
+  const int ep = launch_epoch(q);
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
     const int f = order[t / a.nsys], s = t % a.nsys;
-    if (q.wait) wait_children(q, a, s, f);
+    if (q.wait) wait_children(q, ep, a, s, f);
     trace_mark(q, t, 1);
     fwd_front<R>(a, w, s, f, smem_raw);
-    publish(q, (int64_t)s * a.nfronts + f);
+    publish(q, ep, (int64_t)s * a.nfronts + f);
     trace_mark(q, t, 2);
   }
-  leave(q);
+  leave(q, ep);
 }
 
 // Backward sweep: items in reverse level order (root first), each waits for its parent.
@@ -1625,18 +1642,19 @@ __global__ __launch_bounds__(kThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Qu
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
+  const int ep = launch_epoch(q);
   const int F = a.nfronts;
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
     const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
-    if (q.wait) wait_parent(q, a, s, f);
+    if (q.wait) wait_parent(q, ep, a, s, f);
     trace_mark(q, t, 1);
     bwd_front<R>(a, w, s, f, smem_raw);
-    publish(q, (int64_t)s * F + f);
+    publish(q, ep, (int64_t)s * F + f);
     trace_mark(q, t, 2);
   }
-  leave(q);
+  leave(q, ep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1850,8 +1868,8 @@ KArgs make_args(Plan& P) {
   a.fac = P.fac;
   a.upd = P.upd;
   a.st = P.status;
-  // pivot threshold tau * ||SA||_max with tau = sqrt(unit roundoff)
-  a.tau = P.is_c64 ? 2.44140625e-4 : 1.0536712127723509e-8;
+  // pivot threshold tau * ||SA||_max, by default tau = sqrt(unit roundoff)
+  a.tau = P.pivot_tau;
   a.nfronts = P.an.nfronts;
   return a;
 }
@@ -1873,7 +1891,6 @@ Queue make_queue(Plan& P, int ntasks, int wait, int trace_kind = -1) {
     q.trace = P.trace_buf[trace_kind];
     P.trace_n[trace_kind] = ntasks;
   }
-  q.epoch = ++P.epoch;
   q.ntasks = ntasks;
   q.wait = wait;
   return q;

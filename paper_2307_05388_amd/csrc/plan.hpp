@@ -74,6 +74,7 @@ struct Plan {
   int device = 0;
   bool is_c64 = false;
   size_t csize = 16;           // bytes of one factor scalar (complex)
+  double pivot_tau = 0;        // pivots below pivot_tau * ||SA||_max are perturbed
   DevTables t;
   std::vector<LevelPlan> levels;
   int32_t ntile_tasks = 0;     // tasks of the tile graph (one system)
@@ -100,11 +101,11 @@ struct Plan {
   double* partial = nullptr;   // nsys * max_rhs * res_blocks * 2
   int32_t res_blocks = 0;
   DevStatus* status = nullptr;
-  int32_t* counters = nullptr;  // [0..1] persistent-queue counters, [2] residual blocks
+  int32_t* counters = nullptr;  // [0..1] persistent-queue counters, [2] residual blocks,
+                                // [kEpochSlot] epoch of the last persistent launch
   int32_t* done = nullptr;      // [nsys][nfronts] completion epochs
   int32_t* tile_state = nullptr;  // [nsys][ntiles] tile versions
   int32_t* tile_done = nullptr;   // [nsys][nfronts] finished update tiles
-  int32_t epoch = 0;            // last epoch handed to a persistent launch
   DevStatus* status_host = nullptr;  // pinned
   int64_t device_bytes = 0;
   std::vector<void*> allocations;
@@ -125,11 +126,26 @@ struct Plan {
   std::vector<double> front_lbytes;  // bytes of the lower-trapezoid factor
   double factor_lbytes = 0;          // sum of front_lbytes (one system)
 
+  // FDFD_GRAPH: each call's launch chain, recorded once per argument set on
+  // cap_stream and replayed on the caller's stream (least recently used last)
+  struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  int64_t graph_records = 0;         // chains recorded so far (a measurement aid)
+
   hipStream_t last_stream = nullptr;
   std::vector<double> omega_host;
   bool factored = false;
   std::string last_error;
 };
+
+// The epoch of the last persistent launch sits in its own 128-byte line of
+// the counters array, apart from the counters that take atomics.
+constexpr int kEpochSlot = 32;
+constexpr size_t kCounterBytes = 256;
 
 // Kernel launchers (fdfd_kernels.hip).  Each returns hipSuccess or the first
 // launch error.

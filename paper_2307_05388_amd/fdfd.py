@@ -19,6 +19,7 @@ FDFD_OK, FDFD_ERR_ARG, FDFD_ERR_STATE, FDFD_ERR_NOMEM, FDFD_ERR_HIP, FDFD_ERR_NU
 FDFD_C128, FDFD_C64_IR = 0, 1
 FDFD_ANALYZE_HOST_ONLY = 1
 FDFD_PROFILE = 2
+FDFD_GRAPH = 4
 FDFD_GRAD_ACCUMULATE, FDFD_GRAD_SUM_SYSTEMS = 1, 2
 FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE = 0, 1, 2
 
@@ -121,13 +122,14 @@ class Plan:
     """Cached analysis + factors of one grid (all systems share the pattern)."""
 
     def __init__(self, nx, ny, npml_x, npml_y=None, nsys=1, max_rhs=1, prec="c128",
-                 device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False):
+                 device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False, graph=False):
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         d = Desc(nx=nx, ny=ny, npml_x=npml_x, npml_y=npml_x if npml_y is None else npml_y,
                  nsys=nsys, max_rhs=max_rhs, prec=FDFD_C64_IR if prec in ("c64", FDFD_C64_IR) else FDFD_C128,
                  device=device, leaf=leaf,
-                 flags=(FDFD_ANALYZE_HOST_ONLY if host_only else 0) | (FDFD_PROFILE if profile else 0),
+                 flags=(FDFD_ANALYZE_HOST_ONLY if host_only else 0) | (FDFD_PROFILE if profile else 0)
+                 | (FDFD_GRAPH if graph else 0),
                  mem_cap_bytes=mem_cap_bytes)
         if prec not in ("c64", "c128", FDFD_C64_IR, FDFD_C128):
             raise ValueError(f"unknown precision {prec!r}")

@@ -1,0 +1,110 @@
+"""HIP-graph replay of the design iteration.
+
+Two forms, both against plain launches of the same plan type on the same
+inputs, on several replays with a new permittivity each time (written into the
+captured buffer) and eager work between the replays:
+  - FDFD_GRAPH: the library records each call's launch chain once per argument
+    set and replays it;
+  - the caller records refactor + solve + objective + adjoint/gradient into one
+    torch CUDA graph.
+The kernels and launch shapes are the same in every form, so results must be
+bitwise equal.
+"""
+import numpy as np
+import pytest
+
+from paper_2307_05388_amd import problems as P
+from gpu_util import say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("c128", 0, 0.0), ("c64", 8, 1e-11)]
+
+
+def _setup(torch):
+    # two wavelengths x two source profiles; large enough for the tile graph
+    p = P.custom_problem(150, 131, 12, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss"))
+    dev = torch.device("cuda:0")
+    eps = [torch.from_numpy(np.stack([P.design_eps(p, t=t + 5 * s) for s in range(p.nsys)])).to(dev)
+           for t in range(4)]
+    b = torch.from_numpy(P.sources(p)).to(dev)
+    c = torch.from_numpy(P.objective_vector(p)).to(dev)
+    return p, eps, b, c
+
+
+def _iteration(plan, p, eps, b, cc, x, g, grad, max_ir, tol):
+    import torch
+    plan.refactor(eps, P.omegas(p))
+    plan.solve(b, x=x, max_ir=max_ir, tol=tol)
+    ov = torch.matmul(x, cc)
+    torch.mul(cc[None, None, :], ov.conj()[..., None], out=g)
+    plan.adjoint_grad(x, g, grad=grad, max_ir=max_ir, tol=tol)
+
+
+@pytest.mark.parametrize("prec,max_ir,tol", CASES)
+def test_library_graph_replay_matches_plain_launches(prec, max_ir, tol):
+    torch = torch_cuda()
+    from paper_2307_05388_amd.fdfd import Plan
+    p, eps, b, c = _setup(torch)
+    say(f"graph (library) {prec} {p.nx}x{p.ny} nsys={p.nsys} nrhs={p.nrhs}")
+    cc = c.conj()
+    plans = {k: Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, graph=(k == "graph"))
+             for k in ("plain", "graph")}
+    bufs = {k: (torch.empty_like(eps[0]), torch.empty_like(b), torch.empty_like(b),
+                torch.empty((p.nsys, p.N), dtype=torch.float64, device=b.device)) for k in plans}
+    for t in range(len(eps)):
+        out = {}
+        for k, plan in plans.items():
+            e_in, x, g, grad = bufs[k]
+            e_in.copy_(eps[t])
+            _iteration(plan, p, e_in, b, cc, x, g, grad, max_ir, tol)
+            torch.cuda.synchronize()
+            out[k] = (x.clone(), grad.clone(), plan.query())
+        assert out["plain"][2]["status"] in (0, 6), out["plain"][2]
+        for key in ("status", "ir_steps_solve", "ir_steps_adjoint", "n_perturbed"):
+            assert out["graph"][2][key] == out["plain"][2][key], key
+        assert torch.equal(out["graph"][0], out["plain"][0]), f"x differs at step {t}"
+        assert torch.equal(out["graph"][1], out["plain"][1]), f"gradient differs at step {t}"
+    for plan in plans.values():
+        plan.close()
+
+
+@pytest.mark.parametrize("prec,max_ir,tol", CASES)
+def test_caller_captured_design_iteration(prec, max_ir, tol):
+    torch = torch_cuda()
+    from paper_2307_05388_amd.fdfd import Plan
+    p, eps, b, c = _setup(torch)
+    say(f"graph (torch capture) {prec} {p.nx}x{p.ny} nsys={p.nsys} nrhs={p.nrhs}")
+    cc = c.conj()
+    ref_plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec)
+    cap_plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec)
+    e_in = eps[0].clone()
+    x, g = torch.empty_like(b), torch.empty_like(b)
+    grad = torch.empty((p.nsys, p.N), dtype=torch.float64, device=b.device)
+    rx, rg = torch.empty_like(b), torch.empty_like(b)
+    rgrad = torch.empty_like(grad)
+    # one plain iteration on the side stream first, as torch asks before capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        _iteration(cap_plan, p, e_in, b, cc, x, g, grad, max_ir, tol)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        _iteration(cap_plan, p, e_in, b, cc, x, g, grad, max_ir, tol)
+    for t in range(1, len(eps)):
+        e_in.copy_(eps[t])
+        graph.replay()
+        torch.cuda.synchronize()
+        info = cap_plan.query()
+        # plain launches of another plan on the same permittivity, between replays
+        _iteration(ref_plan, p, eps[t], b, cc, rx, rg, rgrad, max_ir, tol)
+        torch.cuda.synchronize()
+        assert info["status"] in (0, 6), info
+        assert torch.equal(x, rx), f"x differs at replay {t}"
+        assert torch.equal(grad, rgrad), f"gradient differs at replay {t}"
+        say(f"  replay {t}: bitwise equal, ir steps {info['ir_steps_solve']}/{info['ir_steps_adjoint']}")
+    del graph
+    ref_plan.close()
+    cap_plan.close()
