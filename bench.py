@@ -190,8 +190,9 @@ def main():
                       "n_perturbed": r["info"]["n_perturbed"], **acc.get(m, {})}
                   for m, r in results.items()},
         "analysis": {k: results[best]["info"][k] for k in ("nfronts", "nlevels", "nnz_factor", "refactor_flops",
-                                                          "factor_bytes", "leaf")},
+                                                          "factor_bytes", "leaf", "small_levels")},
     }
+    out["caching"] = caching_speedup(args, p, best, eps_all, b, c, omegas, rb["ms_per_step"])
     # roofline of the dominant kernel, from an event-timed pass of the same steps
     prof_plan, _, prof_ms, _, prof_info, _ = run_mode(args, p, best, eps_all, b, c, omegas, profile=True)
     prof_plan.close()
@@ -230,6 +231,54 @@ def roofline(stats, prec, steps, traffic=None):
             "frac": achieved / peak, "traffic": hbm, "traffic_unit": "HBM bytes per launch",
             "launches_per_step": k["launches"] / steps,
             "avg_launch_us": 1e3 * k["total_ms"] / k["launches"], "alg_per_launch": per_launch}
+
+
+# The paper's caching speedups (CPU, not GPU-vs-CPU): total simulation time
+# without and with cached symbolic/numeric factorisations.
+PAPER_CONTEXT = {
+    "hardware": "2.4 GHz Intel Xeon Gold, 8 cores, Intel oneMKL PARDISO (precision not stated)",
+    "duplexer_10wl": {"no_cache_s": 833, "cached_s": 179, "speedup": 4.7, "iterations": 164},
+    "mode_mux_6wl_3modes": {"no_cache_s": 6076, "cached_s": 712, "speedup": 8.5, "iterations": 333},
+    "footprint_sweep_max_speedup": 9.2,
+}
+
+
+def caching_speedup(args, p, mode, eps_all, b, c, omegas, cached_ms, reps=3):
+    """The paper's comparison on this GPU: an iteration that caches nothing
+    (for the forward and for the adjoint solve alike: symbolic analysis, device
+    set-up, numeric factorisation, solve) against the cached iteration measured
+    above.  Wall-clock, synchronised, median of reps."""
+    import torch
+    from paper_2307_05388_amd.fdfd import Plan, FDFD_GRAD_SUM_SYSTEMS
+    prec = mode.split("+")[0]
+    max_ir = args.max_ir if prec == "c64" else 0
+    kw = dict(nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=args.leaf)
+    cc = c.conj()
+    sf, nocache = [], []
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = Plan(p.nx, p.ny, p.npml, host_only=True, **kw)
+        sf.append(time.perf_counter() - t0)
+        h.close()
+        eps = eps_all[r % len(eps_all)]
+        t0 = time.perf_counter()
+        plan = Plan(p.nx, p.ny, p.npml, **kw)
+        plan.refactor(eps, omegas)
+        x = plan.solve(b, max_ir=max_ir, tol=args.ir_tol)
+        ov = torch.matmul(x, cc)
+        g = (cc[None, None, :] * ov.conj()[..., None]).contiguous()
+        torch.cuda.synchronize()
+        plan.close()
+        plan = Plan(p.nx, p.ny, p.npml, **kw)
+        plan.refactor(eps, omegas)
+        plan.adjoint_grad(x, g, flags=FDFD_GRAD_SUM_SYSTEMS, max_ir=max_ir, tol=args.ir_tol)
+        torch.cuda.synchronize()
+        plan.close()
+        nocache.append(time.perf_counter() - t0)
+    t_nc = 1e3 * float(np.median(nocache))
+    return {"symbolic_analysis_ms": 1e3 * float(np.median(sf)), "no_cache_ms_per_iter": t_nc,
+            "cached_ms_per_iter": cached_ms, "speedup": t_nc / cached_ms, "paper": PAPER_CONTEXT}
 
 
 def cpu_baseline(p):

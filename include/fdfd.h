@@ -83,6 +83,11 @@ typedef struct {
   int32_t device;          /* HIP device ordinal, -1 = current device          */
   int32_t leaf;            /* cells per undivided dissection leaf, 0 = default */
   int32_t flags;           /* FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH */
+  int32_t small_lds;       /* LDS bytes a front may use in the one-workgroup-  */
+                           /* per-front kernel (the bottom levels whose fronts */
+                           /* all fit run there, the rest as 64 x 64 tile     */
+                           /* tasks); 0 = default (64 KiB), -1 = tiles only   */
+  int32_t reserved;        /* must be 0                                         */
   int64_t mem_cap_bytes;   /* refuse plans needing more device memory, 0 = off  */
 } fdfd_desc;
 
@@ -108,7 +113,7 @@ typedef struct {
   double rel_residual_solve;   /* max over columns of ||Sb - SAx|| / ||Sb||        */
   double rel_residual_adjoint; /* max over columns of ||g - SA lam'|| / ||g||      */
   int32_t device_flags;      /* raw device status bits                            */
-  int32_t pad_;
+  int32_t small_levels;      /* bottom tree levels run one workgroup per front    */
 } fdfd_info;
 
 /*

@@ -300,6 +300,8 @@ fdfd_status check_desc(const fdfd_desc* d) {
   if (d->max_rhs < 1 || d->max_rhs > 64) return fail(nullptr, FDFD_ERR_ARG, "max_rhs must be in [1, 64]");
   if (d->prec != FDFD_C128 && d->prec != FDFD_C64_IR) return fail(nullptr, FDFD_ERR_ARG, "unknown precision");
   if (d->leaf < 0) return fail(nullptr, FDFD_ERR_ARG, "leaf must be >= 0");
+  if (d->small_lds < -1) return fail(nullptr, FDFD_ERR_ARG, "small_lds must be >= -1");
+  if (d->reserved != 0) return fail(nullptr, FDFD_ERR_ARG, "reserved must be 0");
   if (d->mem_cap_bytes < 0) return fail(nullptr, FDFD_ERR_ARG, "mem_cap_bytes must be >= 0");
   if (d->flags & ~(FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH))
     return fail(nullptr, FDFD_ERR_ARG, "unknown desc flags");
@@ -395,7 +397,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     delete h;
     return fail(nullptr, FDFD_ERR_HIP, "device LDS too small for 64-wide front blocks");
   }
-  size_t small_cap = (size_t)env_int("FDFD_SMALL_LDS", 65536);
+  size_t small_cap = desc->small_lds > 0    ? (size_t)desc->small_lds
+                     : desc->small_lds < 0  ? 0
+                                            : (size_t)env_int("FDFD_SMALL_LDS", 65536);
   // a few hundred bytes stay free for the kernels' static LDS
   const size_t lds_dyn = (size_t)lds_limit - 512;
   small_cap = std::min(small_cap, lds_dyn);
@@ -615,6 +619,7 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   info->max_front = A.max_front;
   info->max_pivots = A.max_piv;
   info->leaf = A.leaf;
+  info->small_levels = P.small_prefix;
   info->min_pivot_ratio = -1.0;
   info->rel_residual_solve = -1.0;
   info->rel_residual_adjoint = -1.0;

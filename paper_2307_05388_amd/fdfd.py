@@ -33,6 +33,7 @@ class Desc(ctypes.Structure):
                 ("nsys", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("leaf", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("small_lds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("mem_cap_bytes", ctypes.c_int64)]
 
 
@@ -46,7 +47,7 @@ class Info(ctypes.Structure):
                 ("min_pivot_ratio", ctypes.c_double),
                 ("ir_steps_solve", ctypes.c_int32), ("ir_steps_adjoint", ctypes.c_int32),
                 ("rel_residual_solve", ctypes.c_double), ("rel_residual_adjoint", ctypes.c_double),
-                ("device_flags", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("device_flags", ctypes.c_int32), ("small_levels", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -122,12 +123,20 @@ class Plan:
     """Cached analysis + factors of one grid (all systems share the pattern)."""
 
     def __init__(self, nx, ny, npml_x, npml_y=None, nsys=1, max_rhs=1, prec="c128",
-                 device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False, graph=False):
+                 device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False, graph=False,
+                 small_lds=0, tuned=True):
+        """With leaf = small_lds = 0 and tuned=True the front layout comes from
+        the autotuner's table for this workload when it has an entry."""
         self._lib = load_library()
         self._h = ctypes.c_void_p()
+        if tuned and leaf == 0 and small_lds == 0 and not host_only:
+            from .autotune import lookup
+            hit = lookup(nx, ny, npml_x, nsys, max_rhs, "c64" if prec in ("c64", FDFD_C64_IR) else "c128")
+            if hit:
+                leaf, small_lds = hit
         d = Desc(nx=nx, ny=ny, npml_x=npml_x, npml_y=npml_x if npml_y is None else npml_y,
                  nsys=nsys, max_rhs=max_rhs, prec=FDFD_C64_IR if prec in ("c64", FDFD_C64_IR) else FDFD_C128,
-                 device=device, leaf=leaf,
+                 device=device, leaf=leaf, small_lds=small_lds,
                  flags=(FDFD_ANALYZE_HOST_ONLY if host_only else 0) | (FDFD_PROFILE if profile else 0)
                  | (FDFD_GRAPH if graph else 0),
                  mem_cap_bytes=mem_cap_bytes)
@@ -196,7 +205,7 @@ class Plan:
     def query(self):
         info = Info()
         st = self._lib.fdfd_query(self._h, ctypes.byref(info))
-        out = {k: getattr(info, k) for k, _ in Info._fields_ if k != "pad_"}
+        out = {k: getattr(info, k) for k, _ in Info._fields_}
         out["status"] = st
         out["status_str"] = self._lib.fdfd_status_str(st).decode()
         if st not in (FDFD_OK, FDFD_WARN_PIVOT):

@@ -20,17 +20,8 @@ def make_plan(p, prec="c128", max_rhs=None, leaf=0, small_lds=None):
     """Plan for problem p; small_lds overrides the LDS budget of the fused
     small-front kernel (0 forces the blocked large-front path everywhere)."""
     from paper_2307_05388_amd.fdfd import Plan
-    old = os.environ.get("FDFD_SMALL_LDS")
-    if small_lds is not None:
-        os.environ["FDFD_SMALL_LDS"] = str(small_lds)
-    try:
-        return Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=max_rhs or p.nrhs, prec=prec, leaf=leaf)
-    finally:
-        if small_lds is not None:
-            if old is None:
-                os.environ.pop("FDFD_SMALL_LDS", None)
-            else:
-                os.environ["FDFD_SMALL_LDS"] = old
+    sl = 0 if small_lds is None else (-1 if small_lds == 0 else small_lds)
+    return Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=max_rhs or p.nrhs, prec=prec, leaf=leaf, small_lds=sl)
 
 
 def gpu_iteration(plan, p, eps, b, g=None, c=None, max_ir=0, tol=0.0):

@@ -131,7 +131,8 @@ def _desc(**kw):
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(ny=0), dict(npml_x=5), dict(npml_y=-1), dict(nsys=0),
                                  dict(nsys=65), dict(max_rhs=0), dict(prec=7), dict(leaf=-2),
                                  dict(mem_cap_bytes=-1), dict(flags=F.FDFD_ANALYZE_HOST_ONLY | 64),
-                                 dict(flags=F.FDFD_ANALYZE_HOST_ONLY | F.FDFD_GRAPH | F.FDFD_PROFILE)])
+                                 dict(flags=F.FDFD_ANALYZE_HOST_ONLY | F.FDFD_GRAPH | F.FDFD_PROFILE),
+                                 dict(small_lds=-2), dict(reserved=1)])
 def test_analyze_rejects_bad_descriptors(lib, bad):
     h = ctypes.c_void_p(123)
     st = lib.fdfd_analyze(ctypes.byref(_desc(**bad)), ctypes.byref(h))
