@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-caching", action="store_true", help="skip the no-caching comparison")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a plain device fill and copy of this many MiB, the reference "
@@ -192,7 +193,8 @@ def main():
         "analysis": {k: results[best]["info"][k] for k in ("nfronts", "nlevels", "nnz_factor", "refactor_flops",
                                                           "factor_bytes", "leaf", "small_levels")},
     }
-    out["caching"] = caching_speedup(args, p, best, eps_all, b, c, omegas, rb["ms_per_step"])
+    if not args.no_caching:
+        out["caching"] = caching_speedup(args, p, best, eps_all, b, c, omegas, rb["ms_per_step"])
     # roofline of the dominant kernel, from an event-timed pass of the same steps
     prof_plan, _, prof_ms, _, prof_info, _ = run_mode(args, p, best, eps_all, b, c, omegas, profile=True)
     prof_plan.close()

@@ -404,11 +404,14 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   const size_t lds_dyn = (size_t)lds_limit - 512;
   small_cap = std::min(small_cap, lds_dyn);
 
-  P.sweep_levels = env_int("FDFD_SWEEP_LEVELS", 0) != 0;
-  P.small_levels = env_int("FDFD_SMALL_LEVELS", 0) != 0;
+
   std::vector<int32_t> tasks, tile_base, is_tiled;
   build_schedule(P, small_cap, tasks, tile_base, is_tiled);
-  if (P.small_levels) P.small_prefix = 0;
+  // the fronts factored one workgroup per front store the single-GEMV panel
+  // form; the sweeps take them one wavefront per front
+  P.wave_levels = P.small_prefix;
+  P.wave_ld = 0;
+  for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
   const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
   if (max_solve_lds > lds_dyn) {
     delete h;
@@ -455,6 +458,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(upload(P, &P.t.tile_base, tile_base));
     TRY(upload(P, &P.t.is_tiled, is_tiled));
     TRY(upload(P, &P.t.parent, A.parent));
+    TRY(upload(P, &P.t.height, A.height));
     TRY(upload(P, &P.t.fac_off, A.fac_off));
     TRY(upload(P, &P.t.upd_off, A.upd_off));
     TRY(upload(P, &P.t.gmap_ptr, A.gmap_ptr));

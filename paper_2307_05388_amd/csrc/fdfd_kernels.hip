@@ -65,7 +65,7 @@ __device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_doub
 // Everything a kernel needs about the plan, passed by value.
 struct KArgs {
   const int32_t *pbeg, *npiv, *nupd, *child_ptr, *child_list, *upd_ptr, *upd_idx;
-  const int32_t *gmap, *nbr_row, *perm, *iperm, *parent;
+  const int32_t *gmap, *nbr_row, *perm, *iperm, *parent, *height;
   const int64_t *fac_off, *upd_off, *gmap_ptr;
   int32_t nx, ny, N, nsys;
   int64_t fac_total, upd_total, sum_u;
@@ -478,6 +478,12 @@ template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
   return v;
 }
 
+template <typename C> __device__ __forceinline__ C shfl_xor_c(C v, int mask) {
+  v.x = __shfl_xor(v.x, mask);
+  v.y = __shfl_xor(v.y, mask);
+  return v;
+}
+
 // LDL^T of the b x b (b <= 16) diagonal sub-block at (o, o) together with the
 // rows below it up to row 63, by wave 0 alone: lane l holds row l of the
 // sub-block's columns in registers.  Each step the lanes of the sub-block
@@ -848,12 +854,23 @@ __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f
   // the parent needs only the update block: release it before the inverse
   publish(q, ep, s * a.nfronts + f);
   invert_blocked(F, m, p, invd + p);
+  // Stored panel of a small front (p <= 64, one diagonal block): D on the
+  // diagonal, Xinv = L11^-1 strictly below it, and M = L21 Xinv below the
+  // pivot rows, M[r][c] = L21[r][c] + sum_{c < k < p} L21[r][k] Xinv[k][c].
+  // With M the sweeps of the front need no triangular chain: forward
+  // z = Xinv v_p and v_u -= M v_p, backward x_p = Xinv^T y_p - M^T x_u.
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   for (int c = wave; c < p; c += 4)
     for (int r = lane; r < m; r += 64) {
       C v = czero<C>();
-      if (r > c) v = F[c * m + r];
-      else if (r == c) v = dd[c];
+      if (r >= p) {
+        v = F[c * m + r];
+        for (int k = c + 1; k < p; ++k) v = cadd(v, cmul(F[k * m + r], F[c * m + k]));
+      } else if (r > c) {
+        v = F[c * m + r];
+      } else if (r == c) {
+        v = dd[c];
+      }
       L[(int64_t)c * m + r] = v;
     }
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
@@ -1407,38 +1424,87 @@ struct SweepArgs {
   int32_t nrhs, scale_src, accumulate;
   DevStatus* st;       // with status_mode >= 0: record "no refinement" for that solve
   int32_t status_mode; // -1, 0 (forward solve) or 1 (adjoint solve)
+  int32_t lev_lo, lev_hi;  // the launch's fronts have heights in [lev_lo, lev_hi);
+                           // fronts outside finished in an earlier launch
+  int32_t wave_ld;         // wave-item launches: LDS entries per wave and RHS
 };
+
+// Waits of a sweep launch: only on fronts of the same launch (the others
+// finished before the launch began and carry an older epoch).  Called by one
+// thread, which spins; the caller orders its later loads after it.
+__device__ __forceinline__ void sweep_wait_children(const Queue& q, int ep, const KArgs& a, const SweepArgs& w,
+                                                    int s, int f) {
+  for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k) {
+    const int c = a.child_list[k];
+    if (a.height[c] >= w.lev_lo) wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + c);
+  }
+}
+
+__device__ __forceinline__ void sweep_wait_parent(const Queue& q, int ep, const KArgs& a, const SweepArgs& w,
+                                                  int s, int f) {
+  const int par = a.parent[f];
+  if (par >= 0 && a.height[par] < w.lev_hi) wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + par);
+}
+
+__device__ __forceinline__ void sweep_status(const SweepArgs& w) {
+  if (w.status_mode >= 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    // a solve without refinement: no steps, no residual, no failure
+    if (w.status_mode == 0) {
+      w.st->ir_steps_solve = 0;
+      w.st->rel_solve = -1.0;
+      w.st->ir_failed_solve = 0;
+    } else {
+      w.st->ir_steps_adj = 0;
+      w.st->rel_adj = -1.0;
+      w.st->ir_failed_adj = 0;
+    }
+  }
+}
+
+// Loads in flight per thread in the sweeps: the sweeps stream the factor once,
+// so the time of a front is its load rounds times the memory latency; every
+// loop below issues kSweepBatch independent loads before it uses the first.
+constexpr int kSweepBatch = 16;
 
 // One front of the forward sweep.  V = [rhs_p; 0] + the children's update
 // vectors; then for each kBW-wide pivot block: V_blk <- Xinv V_blk with the
 // inverted unit-lower diagonal block stored in the panel (four waves split the
-// columns, partial sums meet in LDS), and V_below -= L_below,blk V_blk (one
-// row per thread).  Finally y_p = D^-1 V_p and the update vector is V_u.
+// columns, partial sums meet in LDS), and V_below -= L_below,blk V_blk (two
+// rows per thread, all of a row pair's loads in flight together).  Finally
+// y_p = D^-1 V_p and the update vector is V_u.
 template <typename R>
 __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
-  C* red = reinterpret_cast<C*>(smem);  // 4 x kBW partial sums
-  C* V = red + 4 * kBW;                 // nrhs x m
+  C* red = reinterpret_cast<C*>(smem);  // nrhs x 4 x 2 kBW partial sums
+  C* V = red + 8 * kBW * nrhs;          // nrhs x m
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
   const double2* B = w.src + (int64_t)s * nrhs * a.N;
-  const int cb = a.child_ptr[f], ce = a.child_ptr[f + 1];
+  const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
     const int col = idx / m, r = idx - col * m;
-    C v = czero<C>();
-    if (r < p) {
-      const int n = a.perm[pb + r];
-      double2 bv = B[(int64_t)col * a.N + n];
-      if (w.scale_src) bv = dmul(bv, sym_scale(a, s, n));
-      v = from_d2<C>(bv);
+    // the gather rows of up to two children first, then every value load
+    int gr[2];
+    int64_t base[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      gr[k] = k < nch ? g[k * m + r] : -1;
+      base[k] = k < nch ? (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] : 0;
     }
-    for (int k = cb; k < ce; ++k) {
-      const int gr = g[(k - cb) * m + r];
-      if (gr >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[k]] + gr));
+    double2 bv = make_double2(0.0, 0.0);
+    if (r < p) bv = B[(int64_t)col * a.N + a.perm[pb + r]];
+    C cv[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) cv[k] = gr[k] >= 0 ? ld_ag(W + base[k] + gr[k]) : czero<C>();
+    if (r < p && w.scale_src) bv = dmul(bv, sym_scale(a, s, a.perm[pb + r]));
+    C v = cadd(from_d2<C>(bv), cadd(cv[0], cv[1]));
+    for (int k = 2; k < nch; ++k) {
+      const int gk = g[k * m + r];
+      if (gk >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] + gk));
     }
     V[col * m + r] = v;
   }
@@ -1447,48 +1513,69 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   for (int k0 = 0; k0 < p; k0 += kBW) {
     const int kn = min(kBW, p - k0), k1 = k0 + kn;
     const C* Xb = L + (int64_t)k0 * m + k0;
-    for (int col = 0; col < nrhs; ++col) {
-      const C* Vb = V + col * m + k0;
-      // j = wave, wave + 4, ... < lane: eight predicated loads in flight together
-      C acc = czero<C>();
+    {
+      // V_blk <- Xinv V_blk: lane = row, wave w takes columns w, w+4, ... < lane
+      C xv[16];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        C xv[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int j = wave + 4 * (8 * h + t);
-          xv[t] = (lane < kn && j < lane) ? Xb[(int64_t)j * m + lane] : czero<C>();
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int j = wave + 4 * (8 * h + t);
-          if (lane < kn && j < lane) acc = cadd(acc, cmul(xv[t], Vb[j]));
-        }
+      for (int t = 0; t < 16; ++t) {
+        const int j = wave + 4 * t;
+        xv[t] = (lane < kn && j < lane) ? Xb[(int64_t)j * m + lane] : czero<C>();
       }
-      red[wave * kBW + lane] = acc;
-      __syncthreads();
-      if (wave == 0 && lane < kn) {
-        C t = Vb[lane];
-        t = cadd(t, cadd(cadd(red[lane], red[kBW + lane]), cadd(red[2 * kBW + lane], red[3 * kBW + lane])));
-        V[col * m + k0 + lane] = t;
-      }
-      __syncthreads();
-    }
-    for (int i = k1 + threadIdx.x; i < m; i += kThreads) {
       for (int col = 0; col < nrhs; ++col) {
         const C* Vb = V + col * m + k0;
-        C acc = V[col * m + i];
-        for (int j = 0; j < kn; j += 8) {  // predicated batches: one memory latency each
-          C l[8];
+        C acc = czero<C>();
 #pragma unroll
-          for (int t = 0; t < 8; ++t) l[t] = j + t < kn ? L[(int64_t)(k0 + j + t) * m + i] : czero<C>();
-#pragma unroll
-          for (int t = 0; t < 8; ++t) acc = cfms(acc, l[t], j + t < kn ? Vb[j + t] : czero<C>());
+        for (int t = 0; t < 16; ++t) {
+          const int j = wave + 4 * t;
+          acc = cadd(acc, cmul(xv[t], j < kn ? Vb[j] : czero<C>()));
         }
-        V[col * m + i] = acc;
+        red[(col * 4 + wave) * kBW + lane] = acc;
       }
     }
     __syncthreads();
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
+      const int col = idx / kn, j = idx - col * kn;
+      const C* rr = red + col * 4 * kBW + j;
+      V[col * m + k0 + j] =
+          cadd(V[col * m + k0 + j], cadd(cadd(rr[0], rr[kBW]), cadd(rr[2 * kBW], rr[3 * kBW])));
+    }
+    __syncthreads();
+    // V_below -= L_below,blk V_blk, 128 rows per step: lane = row of a 64-row
+    // chunk, wave w takes columns w, w+4, ...; all 32 loads of a thread are in
+    // flight together and the four column groups meet in LDS.
+    for (int rc = k1; rc < m; rc += 2 * kBW) {
+      const int i0 = rc + lane, i1 = i0 + kBW;
+      C l0[16], l1[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int j = wave + 4 * t;
+        const C* Lj = L + (int64_t)(k0 + min(j, kn - 1)) * m;
+        l0[t] = j < kn && i0 < m ? Lj[i0] : czero<C>();
+        l1[t] = j < kn && i1 < m ? Lj[i1] : czero<C>();
+      }
+      for (int col = 0; col < nrhs; ++col) {
+        const C* Vb = V + col * m + k0;
+        C a0 = czero<C>(), a1 = czero<C>();
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const int j = wave + 4 * t;
+          const C z = j < kn ? Vb[j] : czero<C>();
+          a0 = cadd(a0, cmul(l0[t], z));
+          a1 = cadd(a1, cmul(l1[t], z));
+        }
+        red[(col * 4 + wave) * 2 * kBW + lane] = a0;
+        red[(col * 4 + wave) * 2 * kBW + kBW + lane] = a1;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < 2 * kBW * nrhs; idx += kThreads) {
+        const int col = idx / (2 * kBW), r = idx - col * 2 * kBW, i = rc + r;
+        if (i < m) {
+          const C* rr = red + col * 8 * kBW + r;
+          V[col * m + i] = csub(V[col * m + i], cadd(cadd(rr[0], rr[2 * kBW]), cadd(rr[4 * kBW], rr[6 * kBW])));
+        }
+      }
+      __syncthreads();
+    }
   }
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
     const int col = idx / m, r = idx - col * m;
@@ -1505,18 +1592,77 @@ template <typename C> __device__ __forceinline__ C wave_sum(C v) {
   return v;
 }
 
+// Column dot products of the backward sweep for NR right-hand sides:
+// lane l of wave w owns column jj = 16 w + (l & 15) of the block and the rows
+// r0 + (l >> 4) + 4 t of [r0, r1): one load instruction covers 16 columns x 4
+// consecutive rows, kSweepBatch loads per thread are in flight per step, and
+// the four row phases of a column meet through two lane exchanges.  Returns
+// the column sums in the lanes with l < 16.
+template <int NR, typename C>
+__device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, int m, int r0, int r1, C* acc) {
+  const int q = (threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = czero<C>();
+  for (int i = r0 + q; i < r1; i += 4 * kSweepBatch) {
+    C l[kSweepBatch];
+#pragma unroll
+    for (int t = 0; t < kSweepBatch; ++t) l[t] = colok && i + 4 * t < r1 ? Lc[i + 4 * t] : czero<C>();
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+#pragma unroll
+      for (int t = 0; t < kSweepBatch; ++t)
+        acc[c] = cadd(acc[c], cmul(l[t], i + 4 * t < r1 ? X[c * m + i + 4 * t] : czero<C>()));
+  }
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    acc[c] = cadd(acc[c], shfl_xor_c(acc[c], 16));
+    acc[c] = cadd(acc[c], shfl_xor_c(acc[c], 32));
+  }
+}
+
+// X[col][k0 + jj] (op)= column sums for right-hand sides [c0, c0 + NR); op:
+// subtract (below-block rows) or add into tmp (diagonal block).
+template <int NR, typename C>
+__device__ __forceinline__ void bwd_group(const C* L, C* X, C* tmp, int m, int k0, int kn, int k1, int c0,
+                                          bool diag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int jj = 16 * wave + (lane & 15);
+  const bool colok = jj < kn;
+  C acc[NR];
+  if (!diag) {
+    bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m, colok, X + c0 * m, m, k1, m, acc);
+    if (colok && lane < 16)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) X[(c0 + c) * m + k0 + jj] = csub(X[(c0 + c) * m + k0 + jj], acc[c]);
+  } else {
+    // x_blk[jj] = X_blk[jj] + sum_{jj < i < kn} Xinv[i][jj] X_blk[i]
+    bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m + k0, colok, X + c0 * m + k0, m, jj + 1, kn, acc);
+    if (colok && lane < 16)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) tmp[(c0 + c) * kBW + jj] = cadd(X[(c0 + c) * m + k0 + jj], acc[c]);
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ void bwd_block(const C* L, C* X, C* tmp, int m, int k0, int kn, int k1, int nrhs,
+                                          bool diag) {
+  for (int c0 = 0; c0 < nrhs; c0 += 2) {
+    if (nrhs - c0 >= 2) bwd_group<2>(L, X, tmp, m, k0, kn, k1, c0, diag);
+    else bwd_group<1>(L, X, tmp, m, k0, kn, k1, c0, diag);
+  }
+}
+
 // One front of the backward sweep.  X = [z_p; x(update rows)]; for kBW-wide
 // blocks from the last: X_blk -= L_below,blk^T X_below, then
-// X_blk <- Xinv^T X_blk.  Both are column dot products: one wave per column,
-// lanes over rows, coalesced.  x_p goes to y and to the grid-order output.
+// X_blk <- Xinv^T X_blk (column dot products, bwd_dots).  x_p goes to y and to
+// the grid-order output.
 template <typename R>
 __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
   C* tmp = reinterpret_cast<C*>(smem);  // nrhs x kBW
-  C* red = tmp + nrhs * kBW;             // nrhs x 4 x kBW partial sums
-  C* X = red + 4 * nrhs * kBW;
+  C* X = tmp + nrhs * kBW;
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
@@ -1525,66 +1671,15 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     X[col * m + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int k1 = p;
   while (k1 > 0) {
     const int k0 = ((k1 - 1) / kBW) * kBW;
     const int kn = k1 - k0;
-    // (a) X_blk[j] -= sum_{i >= k1} L[i][k0+j] X[i]: lane = column j, the four
-    // waves split the rows; every lane walks down its own (contiguous) column.
-    {
-      const int rows = m - k1, per = (rows + 3) / 4;
-      const int r0 = k1 + wave * per, r1 = min(m, r0 + per);
-      const C* Lc = L + (int64_t)(k0 + lane) * m;
-      for (int col = 0; col < nrhs; ++col) {
-        const C* Xc = X + col * m;
-        C acc = czero<C>();
-        if (lane < kn) {
-          for (int i = r0; i < r1; i += 8) {  // predicated batches: one memory latency each
-            C l[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) l[t] = i + t < r1 ? Lc[i + t] : czero<C>();
-#pragma unroll
-            for (int t = 0; t < 8; ++t) acc = cadd(acc, cmul(l[t], i + t < r1 ? Xc[i + t] : czero<C>()));
-          }
-        }
-        red[(col * 4 + wave) * kBW + lane] = acc;
-      }
+    if (k1 < m) {
+      bwd_block(L, X, tmp, m, k0, kn, k1, nrhs, false);
+      __syncthreads();
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
-      const int col = idx / kn, j = idx - col * kn;
-      const C* rr = red + col * 4 * kBW + j;
-      X[col * m + k0 + j] = csub(X[col * m + k0 + j], cadd(cadd(rr[0], rr[kBW]), cadd(rr[2 * kBW], rr[3 * kBW])));
-    }
-    __syncthreads();
-    // (b) x_blk[j] = X_blk[j] + sum_{j < i < kn} Xinv[i][j] X_blk[i], same layout
-    {
-      const int per = (kn + 3) / 4;
-      const int r0 = wave * per, r1 = min(kn, r0 + per);
-      const C* Xcol = L + (int64_t)(k0 + lane) * m + k0;
-      for (int col = 0; col < nrhs; ++col) {
-        const C* Xb = X + col * m + k0;
-        C acc = czero<C>();
-        if (lane < kn) {
-          const int i0 = max(r0, lane + 1);
-          for (int i = i0; i < r1; i += 8) {  // predicated batches: one memory latency each
-            C l[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) l[t] = i + t < r1 ? Xcol[i + t] : czero<C>();
-#pragma unroll
-            for (int t = 0; t < 8; ++t) acc = cadd(acc, cmul(l[t], i + t < r1 ? Xb[i + t] : czero<C>()));
-          }
-        }
-        red[(col * 4 + wave) * kBW + lane] = acc;
-      }
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
-      const int col = idx / kn, j = idx - col * kn;
-      const C* rr = red + col * 4 * kBW + j;
-      tmp[col * kBW + j] = cadd(X[col * m + k0 + j], cadd(cadd(rr[0], rr[kBW]), cadd(rr[2 * kBW], rr[3 * kBW])));
-    }
+    bwd_block(L, X, tmp, m, k0, kn, k1, nrhs, true);
     __syncthreads();
     for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
       const int col = idx / kn, j = idx - col * kn;
@@ -1608,18 +1703,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   if (done(w.flag)) return;
-  if (w.status_mode >= 0 && blockIdx.x == 0 && threadIdx.x == 0) {
-    // a solve without refinement: no steps, no residual, no failure
-    if (w.status_mode == 0) {
-      w.st->ir_steps_solve = 0;
-      w.st->rel_solve = -1.0;
-      w.st->ir_failed_solve = 0;
-    } else {
-      w.st->ir_steps_adj = 0;
-      w.st->rel_adj = -1.0;
-      w.st->ir_failed_adj = 0;
-    }
-  }
+  sweep_status(w);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
   const int ep = launch_epoch(q);
@@ -1627,7 +1711,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Qu
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
     const int f = order[t / a.nsys], s = t % a.nsys;
-    if (q.wait) wait_children(q, ep, a, s, f);
+    if (q.wait) {
+      if (threadIdx.x == 0) {
+        sweep_wait_children(q, ep, a, w, s, f);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+      __syncthreads();
+    }
     trace_mark(q, t, 1);
     fwd_front<R>(a, w, s, f, smem_raw);
     publish(q, ep, (int64_t)s * a.nfronts + f);
@@ -1648,11 +1738,226 @@ __global__ __launch_bounds__(kThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Qu
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
     const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
-    if (q.wait) wait_parent(q, ep, a, s, f);
+    if (q.wait) {
+      if (threadIdx.x == 0) {
+        sweep_wait_parent(q, ep, a, w, s, f);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+      __syncthreads();
+    }
     trace_mark(q, t, 1);
     bwd_front<R>(a, w, s, f, smem_raw);
     publish(q, ep, (int64_t)s * F + f);
     trace_mark(q, t, 2);
+  }
+  leave(q, ep);
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps over the bottom levels: one wavefront per front.  Those fronts are
+// small (p <= kBW pivots, a few dozen rows), so a whole workgroup per front
+// would leave most threads idle behind its barriers and run too few fronts at
+// once.  Here each of the four waves of a workgroup takes one front of a
+// four-item claim (one atomic per four fronts), lane = row, no workgroup
+// barrier inside a front; the wave's own LDS slice holds the front vector.
+// ---------------------------------------------------------------------------
+// Loads in flight per lane in the wave sweeps: fewer than in the workgroup
+// sweeps, so that four waves per SIMD stay resident (128 registers).
+template <typename R> constexpr int kWaveBatch = sizeof(R) == 8 ? 8 : 16;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void trace_wave(const Queue& q, int t, int slot) {
+  if (q.trace && (threadIdx.x & 63) == 0 && t < q.ntasks) {
+    q.trace[4 * (int64_t)t + slot] = (long long)wall_clock64();
+    if (slot == 0) q.trace[4 * (int64_t)t + 3] = blockIdx.x;
+  }
+}
+
+// Forward sweep of one small front by one wave (panel in the form stored by
+// the small-front factorisation: D, Xinv strictly lower, M below).  V =
+// [rhs_p; 0] + the children's update vectors is gathered into the wave's LDS;
+// then every row is one dot product with the original V_p, independent of the
+// others: z_r = V_r + sum_{j<r} Xinv[r][j] V_j for r < p (y_r = z_r / d_r) and
+// V_r - sum_{j<p} M[r][j] V_j for r >= p (the update vector).  Lane = row.
+template <typename R>
+__device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f, typename Cx<R>::T* V, int ldv) {
+  typedef typename Cx<R>::T C;
+  constexpr int WB = kWaveBatch<R>;
+  const int lane = threadIdx.x & 63;
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const int nrhs = w.nrhs;
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
+  C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
+  const double2* B = w.src + (int64_t)s * nrhs * a.N;
+  const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
+  const int32_t* g = a.gmap + a.gmap_ptr[f];
+  for (int col = 0; col < nrhs; ++col) {
+    C* Vc = V + col * ldv;
+#pragma unroll 1
+    for (int r = lane; r < m; r += 64) {
+      int gr[2];
+      int64_t base[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        gr[k] = k < nch ? g[k * m + r] : -1;
+        base[k] = k < nch ? (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] : 0;
+      }
+      double2 bv = make_double2(0.0, 0.0);
+      if (r < p) bv = B[(int64_t)col * a.N + a.perm[pb + r]];
+      C cv[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) cv[k] = gr[k] >= 0 ? ld_ag(W + base[k] + gr[k]) : czero<C>();
+      if (r < p && w.scale_src) bv = dmul(bv, sym_scale(a, s, a.perm[pb + r]));
+      C v = cadd(from_d2<C>(bv), cadd(cv[0], cv[1]));
+      for (int k = 2; k < nch; ++k) {
+        const int gk = g[k * m + r];
+        if (gk >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] + gk));
+      }
+      Vc[r] = v;
+    }
+  }
+  wave_sync();
+#pragma unroll 1
+  for (int r = lane; r < m; r += 64) {
+    const int jmax = min(r, p);
+    const C dr = r < p ? L[(int64_t)r * m + r] : czero<C>();
+    for (int col = 0; col < nrhs; ++col) {
+      const C* Vc = V + col * ldv;
+      C acc = czero<C>();
+#pragma unroll 1
+      for (int j0 = 0; j0 < p; j0 += WB) {
+        C e[WB];
+#pragma unroll
+        for (int t = 0; t < WB; ++t) e[t] = j0 + t < jmax ? L[(int64_t)(j0 + t) * m + r] : czero<C>();
+#pragma unroll
+        for (int t = 0; t < WB; ++t) acc = cadd(acc, cmul(e[t], j0 + t < jmax ? Vc[j0 + t] : czero<C>()));
+      }
+      if (r < p) Y[(int64_t)col * a.N + pb + r] = cmul(cadd(Vc[r], acc), cinv(dr));
+      else st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), csub(Vc[r], acc));
+    }
+  }
+  wave_sync();
+}
+
+// Backward sweep of one small front by one wave: X = [y_p; x_u] in LDS, then
+// x_j = y_j + sum_{j<i<p} Xinv[i][j] y_i - sum_{i>=p} M[i][j] x_i, lane = column
+// j walking down its contiguous panel column.
+template <typename R>
+__device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f, typename Cx<R>::T* X, int ldv) {
+  typedef typename Cx<R>::T C;
+  constexpr int WB = kWaveBatch<R>;
+  const int lane = threadIdx.x & 63;
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const int nrhs = w.nrhs;
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
+  const int32_t* ui = a.upd_idx + a.upd_ptr[f];
+  for (int col = 0; col < nrhs; ++col)
+#pragma unroll 1
+    for (int r = lane; r < m; r += 64)
+      X[col * ldv + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
+  wave_sync();
+  const C* Lc = L + (int64_t)min(lane, max(p - 1, 0)) * m;
+  double2* O = w.out + (int64_t)s * nrhs * a.N;
+  for (int col = 0; col < nrhs; ++col) {
+    const C* Xc = X + col * ldv;
+    C acc = czero<C>();
+#pragma unroll 1
+    for (int i0 = lane + 1; i0 < m; i0 += WB) {
+      C e[WB];
+#pragma unroll
+      for (int t = 0; t < WB; ++t) e[t] = lane < p && i0 + t < m ? Lc[i0 + t] : czero<C>();
+#pragma unroll
+      for (int t = 0; t < WB; ++t) {
+        const int i = i0 + t;
+        const C xi = i < m ? Xc[i] : czero<C>();
+        acc = i < p ? cadd(acc, cmul(e[t], xi)) : csub(acc, cmul(e[t], xi));
+      }
+    }
+    if (lane < p) {
+      const C x = cadd(Xc[lane], acc);
+      st_ag(Y + (int64_t)col * a.N + pb + lane, x);
+      double2* o = O + (int64_t)col * a.N + a.perm[pb + lane];
+      const double2 xv = to_d2(x);
+      *o = w.accumulate ? dadd(*o, xv) : xv;
+    }
+  }
+  wave_sync();
+}
+
+// Wave-item launches: items claimed four at a time, wave w of the workgroup
+// takes item t0 + w.  Waves of one workgroup only meet at the claim, so a wave
+// may wait for a front that another wave of the same workgroup processes.
+__device__ __forceinline__ int claim4(const Queue& q, int* sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) *sh = atomicAdd(&q.counter[0], 4);
+  __syncthreads();
+  return *sh;
+}
+
+__device__ __forceinline__ void publish_wave(const Queue& q, int ep, int64_t idx) {
+  drain_stores();
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(q.done + idx, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+  typedef typename Cx<R>::T C;
+  if (done(w.flag)) return;
+  sweep_status(w);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
+  const int ep = launch_epoch(q);
+  const int wave = threadIdx.x >> 6;
+  C* V = reinterpret_cast<C*>(smem_raw) + wave * w.nrhs * w.wave_ld;
+  for (;;) {
+    const int t0 = claim4(q, &sh);
+    if (t0 >= q.ntasks) break;
+    const int t = t0 + wave;
+    if (t < q.ntasks) {
+      trace_wave(q, t, 0);
+      const int f = order[t / a.nsys], s = t % a.nsys;
+      if (q.wait && (threadIdx.x & 63) == 0) sweep_wait_children(q, ep, a, w, s, f);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      trace_wave(q, t, 1);
+      fwd_front_wave<R>(a, w, s, f, V, w.wave_ld);
+      publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+      trace_wave(q, t, 2);
+    }
+  }
+  leave(q, ep);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+  typedef typename Cx<R>::T C;
+  if (done(w.flag)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
+  const int ep = launch_epoch(q);
+  const int wave = threadIdx.x >> 6;
+  C* X = reinterpret_cast<C*>(smem_raw) + wave * w.nrhs * w.wave_ld;
+  for (;;) {
+    const int t0 = claim4(q, &sh);
+    if (t0 >= q.ntasks) break;
+    const int t = t0 + wave;
+    if (t < q.ntasks) {
+      trace_wave(q, t, 0);
+      const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
+      if (q.wait && (threadIdx.x & 63) == 0) sweep_wait_parent(q, ep, a, w, s, f);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      trace_wave(q, t, 1);
+      bwd_front_wave<R>(a, w, s, f, X, w.wave_ld);
+      publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+      trace_wave(q, t, 2);
+    }
   }
   leave(q, ep);
 }
@@ -1852,6 +2157,7 @@ KArgs make_args(Plan& P) {
   a.perm = P.t.perm;
   a.iperm = P.t.iperm;
   a.parent = P.t.parent;
+  a.height = P.t.height;
   a.fac_off = P.t.fac_off;
   a.upd_off = P.t.upd_off;
   a.gmap_ptr = P.t.gmap_ptr;
@@ -1980,16 +2286,32 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
 }
 
 size_t sweep_lds(const Plan& P, int nrhs) {
-  // forward: 4 x kBW partials + V; backward: nrhs x kBW + 4 nrhs x kBW + X
-  return ((size_t)kBW * 5 * (nrhs > 1 ? nrhs : 1) + (size_t)P.an.max_front * nrhs) * P.csize;
+  // forward: nrhs x 8 kBW partial sums + V; backward: nrhs x kBW + X
+  return ((size_t)kBW * 8 * (nrhs > 1 ? nrhs : 1) + (size_t)P.an.max_front * nrhs) * P.csize;
 }
 
-// One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src.
+// LDS of the wave-item sweeps: four waves, each with nrhs x wave_ld entries.
+size_t sweep_wave_lds(const Plan& P, int nrhs) { return (size_t)4 * P.wave_ld * nrhs * P.csize; }
+
+// Workgroups of a persistent launch: as many as can be resident at once for
+// this kernel and LDS footprint, never more than the work items.
+unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int g = P.n_cu * per_cu;
+  if (g > nitems) g = nitems;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src.  The
+// bottom P.wave_levels levels run in the wave-item kernels (forward first,
+// backward last), the levels above in the workgroup-per-front kernels.
 template <typename R>
 void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
            int accumulate, const int* flag, hipStream_t st, int status_mode = -1) {
-  const int nt = P.an.nfronts * P.desc.nsys;
-  const size_t lds = sweep_lds(P, nrhs);
+  const int nsys = P.desc.nsys;
+  const size_t lds = sweep_lds(P, nrhs), wlds = sweep_wave_lds(P, nrhs);
   SweepArgs w;
   w.src = src;
   w.out = dst;
@@ -2001,37 +2323,63 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   w.accumulate = accumulate;
   w.st = P.status;
   w.status_mode = status_mode;
+  w.wave_ld = P.wave_ld;
   const int32_t* lf = P.t.level_fronts;
-  const int nsys = P.desc.nsys;
+  const int nlev = (int)P.levels.size();
+  const int lw = P.wave_levels;
+  const int nlow = lw > 0 ? P.levels[lw - 1].first + P.levels[lw - 1].count : 0;
+  const int nhigh = P.an.nfronts - nlow;
   // algorithmic bytes: the lower-trapezoid factor once, the input vector read
   // in one precision and the output written in another
   const double vec_bytes = (double)P.an.N * nrhs * nsys * (16.0 + (double)P.csize);
-  if (P.sweep_levels) {
-    // one launch per tree level: kernel boundaries order the levels
-    for (const LevelPlan& L : P.levels) {
-      const int n = L.count * nsys;
-      Prof pr(P, st, KC_FWD_SWEEP, L.lbytes * nsys + vec_bytes * L.count / P.an.nfronts, 0.0);
-      hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
-                         make_queue(P, n, 0), lf + L.first);
-    }
-    for (size_t l = P.levels.size(); l-- > 0;) {
-      const LevelPlan& L = P.levels[l];
-      const int n = L.count * nsys;
-      Prof pr(P, st, KC_BWD_SWEEP, L.lbytes * nsys + vec_bytes * L.count / P.an.nfronts, 0.0);
-      hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(persistent_grid(P, lds, n)), dim3(kThreads), lds, st, a, w,
-                         make_queue(P, n, 0), lf + L.first);
-    }
-    return;
+  double low_bytes = 0.0;
+  for (int l = 0; l < lw; ++l) low_bytes += P.levels[l].lbytes;
+  const double fb_low = low_bytes * nsys + vec_bytes * nlow / P.an.nfronts;
+  const double fb_high = (P.factor_lbytes - low_bytes) * nsys + vec_bytes * nhigh / P.an.nfronts;
+  const void* fw = (const void*)k_fwd_sweep_waves<R>;
+  const void* bw = (const void*)k_bwd_sweep_waves<R>;
+  const void* fh = (const void*)k_fwd_sweep<R>;
+  const void* bh = (const void*)k_bwd_sweep<R>;
+  // forward: bottom levels, then the rest
+  if (nlow > 0) {
+    SweepArgs wl = w;
+    wl.lev_lo = 0;
+    wl.lev_hi = lw;
+    const int n = nlow * nsys;
+    Prof pr(P, st, KC_FWD_SWEEP, fb_low, 0.0);
+    hipLaunchKernelGGL((k_fwd_sweep_waves<R>), dim3(resident_grid(P, fw, wlds, (n + 3) / 4)), dim3(kThreads), wlds,
+                       st, a, wl, make_queue(P, n, 1, 2), lf);
+    w.status_mode = -1;
   }
-  const unsigned g = persistent_grid(P, lds, nt);
-  const double fb = P.factor_lbytes * nsys + vec_bytes;
-  {
-    Prof pr(P, st, KC_FWD_SWEEP, fb, 0.0);
-    hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1, 2), lf);
+  if (nhigh > 0) {
+    SweepArgs wh = w;
+    wh.lev_lo = lw;
+    wh.lev_hi = nlev;
+    const int n = nhigh * nsys;
+    Prof pr(P, st, KC_FWD_SWEEP, fb_high, 0.0);
+    hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(resident_grid(P, fh, lds, n)), dim3(kThreads), lds, st, a, wh,
+                       make_queue(P, n, 1, nlow > 0 ? -1 : 2), lf + nlow);
   }
-  {
-    Prof pr(P, st, KC_BWD_SWEEP, fb, 0.0);
-    hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(g), dim3(kThreads), lds, st, a, w, make_queue(P, nt, 1, 3), lf);
+  // backward: the top levels first
+  if (nhigh > 0) {
+    SweepArgs wh = w;
+    wh.status_mode = -1;
+    wh.lev_lo = lw;
+    wh.lev_hi = nlev;
+    const int n = nhigh * nsys;
+    Prof pr(P, st, KC_BWD_SWEEP, fb_high, 0.0);
+    hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(resident_grid(P, bh, lds, n)), dim3(kThreads), lds, st, a, wh,
+                       make_queue(P, n, 1, 3), lf + nlow);
+  }
+  if (nlow > 0) {
+    SweepArgs wl = w;
+    wl.status_mode = -1;
+    wl.lev_lo = 0;
+    wl.lev_hi = lw;
+    const int n = nlow * nsys;
+    Prof pr(P, st, KC_BWD_SWEEP, fb_low, 0.0);
+    hipLaunchKernelGGL((k_bwd_sweep_waves<R>), dim3(resident_grid(P, bw, wlds, (n + 3) / 4)), dim3(kThreads), wlds,
+                       st, a, wl, make_queue(P, n, 1, nhigh > 0 ? -1 : 3), lf);
   }
 }
 
@@ -2085,7 +2433,8 @@ template <typename R>
 hipError_t set_lds_limits(int limit) {
   hipError_t e = hipSuccess;
   const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_large_tiles<R>,
-                       (const void*)k_fwd_sweep<R>, (const void*)k_bwd_sweep<R>};
+                       (const void*)k_fwd_sweep<R>,   (const void*)k_bwd_sweep<R>,
+                       (const void*)k_fwd_sweep_waves<R>, (const void*)k_bwd_sweep_waves<R>};
   for (const void* fn : fns) {
     hipFuncAttributes fa;
     hipError_t r = hipFuncGetAttributes(&fa, fn);
@@ -2102,7 +2451,7 @@ hipError_t configure_kernels(Plan& P, int lds_limit) {
   return P.is_c64 ? set_lds_limits<float>(lds_limit) : set_lds_limits<double>(lds_limit);
 }
 
-size_t solve_lds_bytes(const Plan& P, int nrhs) { return sweep_lds(P, nrhs); }
+size_t solve_lds_bytes(const Plan& P, int nrhs) { return std::max(sweep_lds(P, nrhs), sweep_wave_lds(P, nrhs)); }
 
 hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st) {
   return P.is_c64 ? refactor_impl<float>(P, eps, eps_stride, st)

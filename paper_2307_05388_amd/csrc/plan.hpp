@@ -36,7 +36,7 @@ struct DevTables {
   int32_t *gmap = nullptr, *nbr_row = nullptr;
   int32_t *perm = nullptr, *iperm = nullptr;
   int32_t *level_fronts = nullptr;
-  int32_t *parent = nullptr;
+  int32_t *parent = nullptr, *height = nullptr;
   int32_t *tile_tasks = nullptr, *tile_base = nullptr, *is_tiled = nullptr;
   int64_t *fac_off = nullptr, *upd_off = nullptr, *gmap_ptr = nullptr;
 };
@@ -85,8 +85,8 @@ struct Plan {
   size_t small_lds_prefix = 0;
   int32_t n_cu = 256;
   size_t lds_limit = 65536;
-  bool sweep_levels = false;    // sweeps as one launch per level instead of one persistent launch
-  bool small_levels = false;    // small fronts as one launch per level
+  int32_t wave_levels = 0;      // bottom levels swept one wavefront per front
+  int32_t wave_ld = 0;          // largest front (rows) among them
 
   // arenas (device)
   void* fac = nullptr;         // nsys * fac_total scalars

@@ -16,11 +16,18 @@ def torch_cuda():
     return torch
 
 
-def make_plan(p, prec="c128", max_rhs=None, leaf=0, small_lds=None):
+def make_plan(p, prec="c128", max_rhs=None, leaf=0, small_lds=None, like=None):
     """Plan for problem p; small_lds overrides the LDS budget of the fused
-    small-front kernel (0 forces the blocked large-front path everywhere)."""
+    small-front kernel (0 forces the blocked large-front path everywhere).
+    like=q: the front layout the tuned table gives problem q (so that factors
+    of p and q are computed identically)."""
     from paper_2307_05388_amd.fdfd import Plan
     sl = 0 if small_lds is None else (-1 if small_lds == 0 else small_lds)
+    if like is not None and leaf == 0 and small_lds is None:
+        from paper_2307_05388_amd.autotune import lookup
+        hit = lookup(like.nx, like.ny, like.npml, like.nsys, like.nrhs, prec)
+        if hit:
+            leaf, sl = hit
     return Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=max_rhs or p.nrhs, prec=prec, leaf=leaf, small_lds=sl)
 
 

@@ -146,7 +146,7 @@ def test_mux400_batched_wavelengths_and_sources(oracle):
     dev = torch.device("cuda:0")
     for s in (0, p.nsys - 1):
         q = dataclasses.replace(p, wavelengths_um=(p.wavelengths_um[s],))
-        plan = make_plan(q, "c128")
+        plan = make_plan(q, "c128", like=p)
         plan.refactor(torch.from_numpy(eps).to(dev), P.omegas(q))
         x1 = plan.solve(torch.from_numpy(np.ascontiguousarray(b[s:s + 1])).to(dev)).cpu().numpy()
         assert np.array_equal(x1[0], outs["c128"]["x"][s])
