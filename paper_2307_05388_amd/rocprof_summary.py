@@ -4,6 +4,11 @@
       per-kernel table from `rocprofv3 --kernel-trace --stats --output-format csv`
       (the *_kernel_stats.csv file).
 
+  python -m paper_2307_05388_amd.rocprof_summary mfma COUNTER_CSV --type F64 --workload W --command C > profiles/Z.md
+      matrix-core flops, rate and busy fraction per dispatch from one counter
+      run (SQ_INSTS_VALU_MFMA_MOPS_F64 or _F32, SQ_VALU_MFMA_BUSY_CYCLES,
+      GRBM_GUI_ACTIVE).
+
   python -m paper_2307_05388_amd.rocprof_summary traffic FETCH_CSV WRITE_CSV --copy-mb M --workload W \\
           --command-fetch C1 --command-write C2 > profiles/Y.md
       HBM bytes per dispatch of every kernel from two counter runs
@@ -117,6 +122,46 @@ def traffic(args):
     print("\n".join(out))
 
 
+def _dispatch_rows(path):
+    """{kernel: {dispatch: {counter: [values], "ns": duration}}}."""
+    out = collections.defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        k = _col(r, "Kernel_Name")
+        d = out[k].setdefault(_col(r, "Dispatch_Id"), {"ns": float(_col(r, "End_Timestamp")) -
+                                                        float(_col(r, "Start_Timestamp"))})
+        d.setdefault(_col(r, "Counter_Name"), []).append(float(_col(r, "Counter_Value")))
+    return out
+
+
+def mfma(args):
+    """Matrix-core use per dispatch from one counter run with
+    SQ_INSTS_VALU_MFMA_MOPS_<type> (512 flops per count), SQ_VALU_MFMA_BUSY_CYCLES
+    and GRBM_GUI_ACTIVE: MFMA flops the hardware executed, their rate over the
+    dispatch, and the busy fraction of all SIMDs (busy / (active x SIMDs))."""
+    rows = _dispatch_rows(args.csv)
+    mops = f"SQ_INSTS_VALU_MFMA_MOPS_{args.type}"
+    out = [f"# Matrix-core use per dispatch: {args.workload}", "", "Command (from the repository root, one MI355X):",
+           "", "```", args.command, "```", "",
+           f"MFMA flops = {mops} x 512; busy = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x {args.simds} SIMDs), "
+           f"active cycles = GRBM_GUI_ACTIVE (reported summed over the {args.xcds} XCDs) / {args.xcds}.",
+           "", "| kernel | dispatches | avg us | MFMA GFLOP per dispatch | MFMA TFLOP/s | MFMA busy % |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(rows):
+        if not k.startswith("void fdfd"):
+            continue
+        ds = [d for d in rows[k].values() if mops in d]
+        if not ds:
+            continue
+        fl = sum(sum(d[mops]) * 512 for d in ds) / len(ds)
+        ns = sum(d["ns"] for d in ds) / len(ds)
+        # GRBM_GUI_ACTIVE arrives summed over the XCDs: per-XCD active cycles x XCDs
+        busy = [sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", [0])) /
+                (sum(d.get("GRBM_GUI_ACTIVE", [1])) / args.xcds * args.simds) for d in ds]
+        out.append(f"| {short_name(k)} | {len(ds)} | {ns / 1e3:.1f} | {fl / 1e9:.3f} | {fl / ns / 1e3:.2f} | "
+                   f"{100 * sum(busy) / len(busy):.2f} |")
+    print("\n".join(out))
+
+
 def read_traffic(path):
     """The JSON line of a traffic summary if it was measured on the current kernels, else None."""
     try:
@@ -145,8 +190,15 @@ def main(argv=None):
     t.add_argument("--workload", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    mf = sub.add_parser("mfma")
+    mf.add_argument("csv")
+    mf.add_argument("--type", default="F64")
+    mf.add_argument("--simds", type=int, default=1024)
+    mf.add_argument("--xcds", type=int, default=8)
+    mf.add_argument("--workload", required=True)
+    mf.add_argument("--command", required=True)
     a = ap.parse_args(argv)
-    (kernels if a.cmd == "kernels" else traffic)(a)
+    {"kernels": kernels, "traffic": traffic, "mfma": mfma}[a.cmd](a)
 
 
 if __name__ == "__main__":
