@@ -537,6 +537,64 @@ __device__ void ldl_sub16(C* F, int ld, int o, int b, int m, C* dd, C* invd, C* 
   }
 }
 
+// The same factorisation with all four waves: lane l holds row l, wave w the
+// sub-block columns w, w+4, w+8, w+12.  Each step the owner of pivot column k
+// publishes it to one of two alternating LDS buffers, one barrier, and every
+// wave forms l_k = a_k / d_k itself and updates its own columns (the same
+// operations, in the same order per entry, as ldl_sub16).  colbuf: 2 x 64.
+// Called by the whole workgroup.
+template <typename C>
+__device__ void ldl_sub16_mw(C* F, int ld, int o, int b, int m, C* dd, C* invd, C* colbuf, double thr,
+                             double anorm, int& npert, double& minr, int& nonfin) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool act = l >= o && l < m;
+  C col[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int q = w + 4 * t;
+    col[t] = (act && q < b && o + q <= l) ? F[(o + q) * ld + l] : czero<C>();
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < b) {
+      C* buf = colbuf + (k & 1) * 64;
+      if (w == (k & 3)) buf[l] = col[k >> 2];
+      __syncthreads();
+      int np = 0, nf = 0;
+      double mr = INFINITY;
+      const C d = fix_pivot(buf[o + k], thr, anorm, np, mr, nf);
+      const C inv = cinv(d);
+      if (threadIdx.x == 0) {
+        npert += np;
+        minr = fmin(minr, mr);
+        nonfin |= nf;
+        dd[o + k] = d;
+        invd[o + k] = inv;
+      }
+      const C lk = cmul(buf[l], inv);
+      // Branch-free: lanes l < o + j only touch entries above the diagonal,
+      // which are never published nor stored.
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = w + 4 * t;
+        if (j > k && j < b) col[t] = cfms(col[t], lk, buf[o + j]);
+      }
+      if (w == (k & 3)) {
+        const bool below = l > o + k;
+        col[k >> 2].x = below ? lk.x : col[k >> 2].x;
+        col[k >> 2].y = below ? lk.y : col[k >> 2].y;
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = w + 4 * t;
+      if (q < b && o + q < l) F[(o + q) * ld + l] = col[t];
+    }
+  }
+}
+
 // Rows r in [r0, m) of the sub-block's columns: L_r = F_r L_ss^-T D^-1 by
 // forward substitution, one row per thread.
 template <typename C>
@@ -645,7 +703,7 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scrat
                             int& npert, double& minr, int& nonfin) {
   for (int o = 0; o < p; o += 16) {
     const int b = min(16, p - o);
-    if (threadIdx.x < 64) ldl_sub16(F, ld, o, b, m, dd, invd, scratch, thr, anorm, npert, minr, nonfin);
+    ldl_sub16_mw(F, ld, o, b, m, dd, invd, scratch, thr, anorm, npert, minr, nonfin);
     __syncthreads();
     if (m > 64) {
       trsm_rows16(F, ld, o, b, 64, m, invd);
