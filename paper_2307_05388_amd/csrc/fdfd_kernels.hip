@@ -911,24 +911,17 @@ __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f
   }
   // the parent needs only the update block: release it before the inverse
   publish(q, ep, s * a.nfronts + f);
-  invert_blocked(F, m, p, invd + p);
-  // Stored panel of a small front (p <= 64, one diagonal block): D on the
-  // diagonal, Xinv = L11^-1 strictly below it, and M = L21 Xinv below the
-  // pivot rows, M[r][c] = L21[r][c] + sum_{c < k < p} L21[r][k] Xinv[k][c].
-  // With M the sweeps of the front need no triangular chain: forward
-  // z = Xinv v_p and v_u -= M v_p, backward x_p = Xinv^T y_p - M^T x_u.
+  // Stored panel of a small front (p <= 64): D on the diagonal and the
+  // unit-lower L below it, no inverse.  The sweeps of these fronts solve with
+  // L11 in registers of one wavefront (a chain of p lane broadcasts, far
+  // shorter than a memory round trip), so an inverse would only cost the
+  // factorisation time.
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   for (int c = wave; c < p; c += 4)
     for (int r = lane; r < m; r += 64) {
       C v = czero<C>();
-      if (r >= p) {
-        v = F[c * m + r];
-        for (int k = c + 1; k < p; ++k) v = cadd(v, cmul(F[k * m + r], F[c * m + k]));
-      } else if (r > c) {
-        v = F[c * m + r];
-      } else if (r == c) {
-        v = dd[c];
-      }
+      if (r > c) v = F[c * m + r];
+      else if (r == c) v = dd[c];
       L[(int64_t)c * m + r] = v;
     }
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
@@ -1835,12 +1828,25 @@ __device__ __forceinline__ void trace_wave(const Queue& q, int t, int slot) {
   }
 }
 
-// Forward sweep of one small front by one wave (panel in the form stored by
-// the small-front factorisation: D, Xinv strictly lower, M below).  V =
-// [rhs_p; 0] + the children's update vectors is gathered into the wave's LDS;
-// then every row is one dot product with the original V_p, independent of the
-// others: z_r = V_r + sum_{j<r} Xinv[r][j] V_j for r < p (y_r = z_r / d_r) and
-// V_r - sum_{j<p} M[r][j] V_j for r >= p (the update vector).  Lane = row.
+// Broadcast of lane j's value to the whole wave (j uniform).
+template <typename C> __device__ __forceinline__ C bcast_c(C v, int j) {
+  constexpr int n = sizeof(C) / 4;
+  int w[n];
+  __builtin_memcpy(w, &v, sizeof(C));
+#pragma unroll
+  for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readlane(w[i], j);
+  C o;
+  __builtin_memcpy(&o, w, sizeof(C));
+  return o;
+}
+
+// Forward sweep of one small front by one wave (panel: D on the diagonal, the
+// unit-lower L below).  V = [rhs_p; 0] + the children's update vectors is
+// gathered into the wave's LDS; z = L11^-1 V_p by forward substitution with
+// lane = row: lane i keeps its running value and, at step j, takes z_j from
+// lane j (a register broadcast) times its own L_ij, loaded kWaveBatch columns
+// at a time ahead of use; then V_u -= L21 z (lane = row, all loads
+// independent), y_p = D^-1 z and the update vector is V_u.
 template <typename R>
 __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f, typename Cx<R>::T* V, int ldv) {
   typedef typename Cx<R>::T C;
@@ -1880,31 +1886,52 @@ __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
     }
   }
   wave_sync();
+  const C dl = lane < p ? L[(int64_t)lane * m + lane] : czero<C>();
+  for (int col = 0; col < nrhs; ++col) {
+    C* Vc = V + col * ldv;
+    // z = L11^-1 V_p, lane = row
+    C zi = lane < p ? Vc[lane] : czero<C>();
 #pragma unroll 1
-  for (int r = lane; r < m; r += 64) {
-    const int jmax = min(r, p);
-    const C dr = r < p ? L[(int64_t)r * m + r] : czero<C>();
-    for (int col = 0; col < nrhs; ++col) {
-      const C* Vc = V + col * ldv;
+    for (int j0 = 0; j0 < p; j0 += WB) {
+      C e[WB];
+#pragma unroll
+      for (int t = 0; t < WB; ++t) {
+        const int j = j0 + t;
+        e[t] = j < lane && lane < p ? L[(int64_t)j * m + lane] : czero<C>();
+      }
+#pragma unroll
+      for (int t = 0; t < WB; ++t) {
+        const int j = j0 + t;
+        if (j < p) zi = cfms(zi, e[t], bcast_c(zi, j));
+      }
+    }
+    wave_sync();
+    if (lane < p) Vc[lane] = zi;
+    wave_sync();
+    // V_u -= L21 z: rows p + lane, p + lane + 64, ...
+#pragma unroll 1
+    for (int r = p + lane; r < m; r += 64) {
       C acc = czero<C>();
 #pragma unroll 1
       for (int j0 = 0; j0 < p; j0 += WB) {
         C e[WB];
 #pragma unroll
-        for (int t = 0; t < WB; ++t) e[t] = j0 + t < jmax ? L[(int64_t)(j0 + t) * m + r] : czero<C>();
+        for (int t = 0; t < WB; ++t) e[t] = j0 + t < p ? L[(int64_t)(j0 + t) * m + r] : czero<C>();
 #pragma unroll
-        for (int t = 0; t < WB; ++t) acc = cadd(acc, cmul(e[t], j0 + t < jmax ? Vc[j0 + t] : czero<C>()));
+        for (int t = 0; t < WB; ++t) acc = cadd(acc, cmul(e[t], j0 + t < p ? Vc[j0 + t] : czero<C>()));
       }
-      if (r < p) Y[(int64_t)col * a.N + pb + r] = cmul(cadd(Vc[r], acc), cinv(dr));
-      else st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), csub(Vc[r], acc));
+      st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), csub(Vc[r], acc));
     }
+    if (lane < p) Y[(int64_t)col * a.N + pb + lane] = cmul(zi, cinv(dl));
+    wave_sync();
   }
-  wave_sync();
 }
 
-// Backward sweep of one small front by one wave: X = [y_p; x_u] in LDS, then
-// x_j = y_j + sum_{j<i<p} Xinv[i][j] y_i - sum_{i>=p} M[i][j] x_i, lane = column
-// j walking down its contiguous panel column.
+// Backward sweep of one small front by one wave: X = [y_p; x_u] in LDS;
+// lane = column j: t_j = sum_{i>=p} L[i][j] x_i down the contiguous column,
+// then back substitution x_j = y_j - t_j - sum_{j<i<p} L[i][j] x_i with x_i
+// taken from lane i (a register broadcast) as soon as it is final, the
+// column's L[i][j] loaded kWaveBatch rows at a time ahead of use.
 template <typename R>
 __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f, typename Cx<R>::T* X, int ldv) {
   typedef typename Cx<R>::T C;
@@ -1926,22 +1953,33 @@ __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
     const C* Xc = X + col * ldv;
     C acc = czero<C>();
 #pragma unroll 1
-    for (int i0 = lane + 1; i0 < m; i0 += WB) {
+    for (int i0 = p; i0 < m; i0 += WB) {
       C e[WB];
 #pragma unroll
       for (int t = 0; t < WB; ++t) e[t] = lane < p && i0 + t < m ? Lc[i0 + t] : czero<C>();
 #pragma unroll
+      for (int t = 0; t < WB; ++t) acc = cadd(acc, cmul(e[t], i0 + t < m ? Xc[i0 + t] : czero<C>()));
+    }
+    C xj = lane < p ? csub(Xc[lane], acc) : czero<C>();
+    // rows i = p-1 down to 1: lane i's value is final, lanes j < i take it
+#pragma unroll 1
+    for (int i0 = p - 1; i0 > 0; i0 -= WB) {
+      C e[WB];
+#pragma unroll
       for (int t = 0; t < WB; ++t) {
-        const int i = i0 + t;
-        const C xi = i < m ? Xc[i] : czero<C>();
-        acc = i < p ? cadd(acc, cmul(e[t], xi)) : csub(acc, cmul(e[t], xi));
+        const int i = i0 - t;
+        e[t] = i > lane && lane < p ? Lc[i] : czero<C>();
+      }
+#pragma unroll
+      for (int t = 0; t < WB; ++t) {
+        const int i = i0 - t;
+        if (i > 0) xj = cfms(xj, e[t], bcast_c(xj, i));
       }
     }
     if (lane < p) {
-      const C x = cadd(Xc[lane], acc);
-      st_ag(Y + (int64_t)col * a.N + pb + lane, x);
+      st_ag(Y + (int64_t)col * a.N + pb + lane, xj);
       double2* o = O + (int64_t)col * a.N + a.perm[pb + lane];
-      const double2 xv = to_d2(x);
+      const double2 xv = to_d2(xj);
       *o = w.accumulate ? dadd(*o, xv) : xv;
     }
   }
@@ -1964,7 +2002,7 @@ __device__ __forceinline__ void publish_wave(const Queue& q, int ep, int64_t idx
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 3) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   sweep_status(w);
