@@ -1517,26 +1517,35 @@ __device__ __forceinline__ void sweep_status(const SweepArgs& w) {
 // loop below issues kSweepBatch independent loads before it uses the first.
 constexpr int kSweepBatch = 16;
 
+// The tiled-level sweeps run one kSweepThreads-thread workgroup per front: the
+// few large fronts of those levels are processed one or two at a time, so a
+// front's time is its load rounds, and more waves keep more loads in flight.
+constexpr int kSweepThreads = 512;
+constexpr int kSW = kSweepThreads / 64;   // waves
+constexpr int kRowStep = 64 * kSW / 4;    // rows per step of the below-block update
+constexpr int kNQ = kSW / 4;              // row parts of the backward column sums
+
 // One front of the forward sweep.  V = [rhs_p; 0] + the children's update
 // vectors; then for each kBW-wide pivot block: V_blk <- Xinv V_blk with the
-// inverted unit-lower diagonal block stored in the panel (four waves split the
-// columns, partial sums meet in LDS), and V_below -= L_below,blk V_blk (two
-// rows per thread, all of a row pair's loads in flight together).  Finally
+// inverted unit-lower diagonal block stored in the panel (the waves split the
+// columns, partial sums meet in LDS), and V_below -= L_below,blk V_blk,
+// kRowStep rows per step (wave w: rows 64 (w / 4) + lane of the step, columns
+// w % 4, w % 4 + 4, ...; sixteen loads per thread in flight).  Finally
 // y_p = D^-1 V_p and the update vector is V_u.
 template <typename R>
 __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
-  C* red = reinterpret_cast<C*>(smem);  // nrhs x 4 x 2 kBW partial sums
-  C* V = red + 8 * kBW * nrhs;          // nrhs x m
+  C* red = reinterpret_cast<C*>(smem);  // nrhs x 4 x kRowStep (>= nrhs x kSW x kBW) partial sums
+  C* V = red + 4 * kRowStep * nrhs;     // nrhs x m
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
   const double2* B = w.src + (int64_t)s * nrhs * a.N;
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];
-  for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
     const int col = idx / m, r = idx - col * m;
     // the gather rows of up to two children first, then every value load
     int gr[2];
@@ -1561,74 +1570,72 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cg = wave & 3, rq = wave >> 2;
   for (int k0 = 0; k0 < p; k0 += kBW) {
     const int kn = min(kBW, p - k0), k1 = k0 + kn;
     const C* Xb = L + (int64_t)k0 * m + k0;
     {
-      // V_blk <- Xinv V_blk: lane = row, wave w takes columns w, w+4, ... < lane
-      C xv[16];
+      // V_blk <- Xinv V_blk: lane = row, wave w takes columns w, w + kSW, ... < lane
+      constexpr int NT = kBW / kSW;
+      C xv[NT];
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int j = wave + 4 * t;
+      for (int t = 0; t < NT; ++t) {
+        const int j = wave + kSW * t;
         xv[t] = (lane < kn && j < lane) ? Xb[(int64_t)j * m + lane] : czero<C>();
       }
       for (int col = 0; col < nrhs; ++col) {
         const C* Vb = V + col * m + k0;
         C acc = czero<C>();
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const int j = wave + 4 * t;
+        for (int t = 0; t < NT; ++t) {
+          const int j = wave + kSW * t;
           acc = cadd(acc, cmul(xv[t], j < kn ? Vb[j] : czero<C>()));
         }
-        red[(col * 4 + wave) * kBW + lane] = acc;
+        red[(col * kSW + wave) * kBW + lane] = acc;
       }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
       const int col = idx / kn, j = idx - col * kn;
-      const C* rr = red + col * 4 * kBW + j;
-      V[col * m + k0 + j] =
-          cadd(V[col * m + k0 + j], cadd(cadd(rr[0], rr[kBW]), cadd(rr[2 * kBW], rr[3 * kBW])));
+      const C* rr = red + col * kSW * kBW + j;
+      C acc = czero<C>();
+#pragma unroll
+      for (int q = 0; q < kSW; ++q) acc = cadd(acc, rr[q * kBW]);
+      V[col * m + k0 + j] = cadd(V[col * m + k0 + j], acc);
     }
     __syncthreads();
-    // V_below -= L_below,blk V_blk, 128 rows per step: lane = row of a 64-row
-    // chunk, wave w takes columns w, w+4, ...; all 32 loads of a thread are in
-    // flight together and the four column groups meet in LDS.
-    for (int rc = k1; rc < m; rc += 2 * kBW) {
-      const int i0 = rc + lane, i1 = i0 + kBW;
-      C l0[16], l1[16];
+    for (int rc = k1; rc < m; rc += kRowStep) {
+      const int i = rc + 64 * rq + lane;
+      C l[16];
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        const int j = wave + 4 * t;
+        const int j = cg + 4 * t;
         const C* Lj = L + (int64_t)(k0 + min(j, kn - 1)) * m;
-        l0[t] = j < kn && i0 < m ? Lj[i0] : czero<C>();
-        l1[t] = j < kn && i1 < m ? Lj[i1] : czero<C>();
+        l[t] = j < kn && i < m ? Lj[i] : czero<C>();
       }
       for (int col = 0; col < nrhs; ++col) {
         const C* Vb = V + col * m + k0;
-        C a0 = czero<C>(), a1 = czero<C>();
+        C acc = czero<C>();
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-          const int j = wave + 4 * t;
-          const C z = j < kn ? Vb[j] : czero<C>();
-          a0 = cadd(a0, cmul(l0[t], z));
-          a1 = cadd(a1, cmul(l1[t], z));
+          const int j = cg + 4 * t;
+          acc = cadd(acc, cmul(l[t], j < kn ? Vb[j] : czero<C>()));
         }
-        red[(col * 4 + wave) * 2 * kBW + lane] = a0;
-        red[(col * 4 + wave) * 2 * kBW + kBW + lane] = a1;
+        red[(col * 4 + cg) * kRowStep + 64 * rq + lane] = acc;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < 2 * kBW * nrhs; idx += kThreads) {
-        const int col = idx / (2 * kBW), r = idx - col * 2 * kBW, i = rc + r;
-        if (i < m) {
-          const C* rr = red + col * 8 * kBW + r;
-          V[col * m + i] = csub(V[col * m + i], cadd(cadd(rr[0], rr[2 * kBW]), cadd(rr[4 * kBW], rr[6 * kBW])));
+      for (int idx = threadIdx.x; idx < kRowStep * nrhs; idx += kSweepThreads) {
+        const int col = idx / kRowStep, r = idx - col * kRowStep, ii = rc + r;
+        if (ii < m) {
+          const C* rr = red + col * 4 * kRowStep + r;
+          V[col * m + ii] =
+              csub(V[col * m + ii], cadd(cadd(rr[0], rr[kRowStep]), cadd(rr[2 * kRowStep], rr[3 * kRowStep])));
         }
       }
       __syncthreads();
     }
   }
-  for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
     const int col = idx / m, r = idx - col * m;
     if (r < p) Y[(int64_t)col * a.N + pb + r] = cmul(V[col * m + r], cinv(L[(int64_t)r * m + r]));
     else st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), V[col * m + r]);
@@ -1643,26 +1650,31 @@ template <typename C> __device__ __forceinline__ C wave_sum(C v) {
   return v;
 }
 
-// Column dot products of the backward sweep for NR right-hand sides:
-// lane l of wave w owns column jj = 16 w + (l & 15) of the block and the rows
-// r0 + (l >> 4) + 4 t of [r0, r1): one load instruction covers 16 columns x 4
-// consecutive rows, kSweepBatch loads per thread are in flight per step, and
-// the four row phases of a column meet through two lane exchanges.  Returns
-// the column sums in the lanes with l < 16.
+// Column dot products of the backward sweep for NR right-hand sides: lane l
+// of wave w owns column jj = 16 (w % 4) + (l & 15) of the block and, within
+// the row quarter w / 4 of [r0, r1), the rows q0 + (l >> 4) + 4 t: one load
+// instruction covers 16 columns x 4 consecutive rows, kDotBatch loads per
+// thread are in flight per step, the four row phases of a column meet through
+// two lane exchanges.  Returns the part's column sums in lanes l < 16.
+// loads in flight per thread in bwd_dots (complex64 entries take half the registers)
+template <typename C> constexpr int kDotBatch = sizeof(C) == 16 ? 16 : 32;
+
 template <int NR, typename C>
 __device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, int m, int r0, int r1, C* acc) {
-  const int q = (threadIdx.x & 63) >> 4;
+  const int q = (threadIdx.x & 63) >> 4, rq = (threadIdx.x >> 6) >> 2;
+  const int per = (r1 - r0 + kNQ - 1) / kNQ;
+  const int q0 = r0 + rq * per, q1 = min(r1, q0 + per);
 #pragma unroll
   for (int c = 0; c < NR; ++c) acc[c] = czero<C>();
-  for (int i = r0 + q; i < r1; i += 4 * kSweepBatch) {
-    C l[kSweepBatch];
+  for (int i = q0 + q; i < q1; i += 4 * kDotBatch<C>) {
+    C l[kDotBatch<C>];
 #pragma unroll
-    for (int t = 0; t < kSweepBatch; ++t) l[t] = colok && i + 4 * t < r1 ? Lc[i + 4 * t] : czero<C>();
+    for (int t = 0; t < kDotBatch<C>; ++t) l[t] = colok && i + 4 * t < q1 ? Lc[i + 4 * t] : czero<C>();
 #pragma unroll
     for (int c = 0; c < NR; ++c)
 #pragma unroll
-      for (int t = 0; t < kSweepBatch; ++t)
-        acc[c] = cadd(acc[c], cmul(l[t], i + 4 * t < r1 ? X[c * m + i + 4 * t] : czero<C>()));
+      for (int t = 0; t < kDotBatch<C>; ++t)
+        acc[c] = cadd(acc[c], cmul(l[t], i + 4 * t < q1 ? X[c * m + i + 4 * t] : czero<C>()));
   }
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
@@ -1671,53 +1683,47 @@ __device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, in
   }
 }
 
-// X[col][k0 + jj] (op)= column sums for right-hand sides [c0, c0 + NR); op:
-// subtract (below-block rows) or add into tmp (diagonal block).
+// Column sums of right-hand sides [c0, c0 + NR) over the below-block rows
+// (diag = false) or, for column jj, the rows jj+1 .. kn-1 of the diagonal
+// block's inverse (diag = true), per row part into red[c][part][jj].
 template <int NR, typename C>
-__device__ __forceinline__ void bwd_group(const C* L, C* X, C* tmp, int m, int k0, int kn, int k1, int c0,
+__device__ __forceinline__ void bwd_group(const C* L, const C* X, C* red, int m, int k0, int kn, int k1, int c0,
                                           bool diag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int jj = 16 * wave + (lane & 15);
+  const int jj = 16 * (wave & 3) + (lane & 15), rq = wave >> 2;
   const bool colok = jj < kn;
   C acc[NR];
-  if (!diag) {
-    bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m, colok, X + c0 * m, m, k1, m, acc);
-    if (colok && lane < 16)
+  if (!diag) bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m, colok, X + c0 * m, m, k1, m, acc);
+  else bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m + k0, colok, X + c0 * m + k0, m, jj + 1, kn, acc);
+  if (lane < 16)
 #pragma unroll
-      for (int c = 0; c < NR; ++c) X[(c0 + c) * m + k0 + jj] = csub(X[(c0 + c) * m + k0 + jj], acc[c]);
-  } else {
-    // x_blk[jj] = X_blk[jj] + sum_{jj < i < kn} Xinv[i][jj] X_blk[i]
-    bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m + k0, colok, X + c0 * m + k0, m, jj + 1, kn, acc);
-    if (colok && lane < 16)
-#pragma unroll
-      for (int c = 0; c < NR; ++c) tmp[(c0 + c) * kBW + jj] = cadd(X[(c0 + c) * m + k0 + jj], acc[c]);
-  }
+    for (int c = 0; c < NR; ++c) red[((c0 + c) * kNQ + rq) * kBW + jj] = acc[c];
 }
 
 template <typename C>
-__device__ __forceinline__ void bwd_block(const C* L, C* X, C* tmp, int m, int k0, int kn, int k1, int nrhs,
+__device__ __forceinline__ void bwd_block(const C* L, const C* X, C* red, int m, int k0, int kn, int k1, int nrhs,
                                           bool diag) {
   for (int c0 = 0; c0 < nrhs; c0 += 2) {
-    if (nrhs - c0 >= 2) bwd_group<2>(L, X, tmp, m, k0, kn, k1, c0, diag);
-    else bwd_group<1>(L, X, tmp, m, k0, kn, k1, c0, diag);
+    if (nrhs - c0 >= 2) bwd_group<2>(L, X, red, m, k0, kn, k1, c0, diag);
+    else bwd_group<1>(L, X, red, m, k0, kn, k1, c0, diag);
   }
 }
 
 // One front of the backward sweep.  X = [z_p; x(update rows)]; for kBW-wide
 // blocks from the last: X_blk -= L_below,blk^T X_below, then
-// X_blk <- Xinv^T X_blk (column dot products, bwd_dots).  x_p goes to y and to
-// the grid-order output.
+// X_blk <- Xinv^T X_blk (column dot products, bwd_dots; the row parts meet
+// in LDS).  x_p goes to y and to the grid-order output.
 template <typename R>
 __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
-  C* tmp = reinterpret_cast<C*>(smem);  // nrhs x kBW
-  C* X = tmp + nrhs * kBW;
+  C* red = reinterpret_cast<C*>(smem);  // nrhs x kNQ x kBW
+  C* X = red + kNQ * nrhs * kBW;
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
-  for (int idx = threadIdx.x; idx < m * nrhs; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
     const int col = idx / m, r = idx - col * m;
     X[col * m + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
   }
@@ -1727,20 +1733,34 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     const int k0 = ((k1 - 1) / kBW) * kBW;
     const int kn = k1 - k0;
     if (k1 < m) {
-      bwd_block(L, X, tmp, m, k0, kn, k1, nrhs, false);
+      bwd_block(L, X, red, m, k0, kn, k1, nrhs, false);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+        const int col = idx / kn, j = idx - col * kn;
+        const C* rr = red + col * kNQ * kBW + j;
+        C acc = czero<C>();
+#pragma unroll
+        for (int q = 0; q < kNQ; ++q) acc = cadd(acc, rr[q * kBW]);
+        X[col * m + k0 + j] = csub(X[col * m + k0 + j], acc);
+      }
       __syncthreads();
     }
-    bwd_block(L, X, tmp, m, k0, kn, k1, nrhs, true);
+    bwd_block(L, X, red, m, k0, kn, k1, nrhs, true);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kThreads) {
+    // x_blk = X_blk + the parts' sums (every read of X_blk above is done)
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
       const int col = idx / kn, j = idx - col * kn;
-      X[col * m + k0 + j] = tmp[col * kBW + j];
+      const C* rr = red + col * kNQ * kBW + j;
+      C acc = czero<C>();
+#pragma unroll
+      for (int q = 0; q < kNQ; ++q) acc = cadd(acc, rr[q * kBW]);
+      X[col * m + k0 + j] = cadd(X[col * m + k0 + j], acc);
     }
     __syncthreads();
     k1 = k0;
   }
   double2* O = w.out + (int64_t)s * nrhs * a.N;
-  for (int idx = threadIdx.x; idx < p * nrhs; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < p * nrhs; idx += kSweepThreads) {
     const int col = idx / p, r = idx - col * p;
     const C x = X[col * m + r];
     st_ag(Y + (int64_t)col * a.N + pb + r, x);
@@ -1752,7 +1772,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
 
 // Forward sweep: items in level order (leaves first), each waits for its children.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   if (done(w.flag)) return;
   sweep_status(w);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1779,7 +1799,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Qu
 
 // Backward sweep: items in reverse level order (root first), each waits for its parent.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
@@ -2382,8 +2402,8 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
 }
 
 size_t sweep_lds(const Plan& P, int nrhs) {
-  // forward: nrhs x 8 kBW partial sums + V; backward: nrhs x kBW + X
-  return ((size_t)kBW * 8 * (nrhs > 1 ? nrhs : 1) + (size_t)P.an.max_front * nrhs) * P.csize;
+  // forward: nrhs x 4 kRowStep partial sums + V; backward: nrhs x 4 kBW + X
+  return ((size_t)4 * kRowStep * (nrhs > 1 ? nrhs : 1) + (size_t)P.an.max_front * nrhs) * P.csize;
 }
 
 // LDS of the wave-item sweeps: four waves, each with nrhs x wave_ld entries.
@@ -2391,9 +2411,9 @@ size_t sweep_wave_lds(const Plan& P, int nrhs) { return (size_t)4 * P.wave_ld * 
 
 // Workgroups of a persistent launch: as many as can be resident at once for
 // this kernel and LDS footprint, never more than the work items.
-unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems) {
+unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems, int threads = kThreads) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   int g = P.n_cu * per_cu;
   if (g > nitems) g = nitems;
@@ -2453,7 +2473,8 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
     wh.lev_hi = nlev;
     const int n = nhigh * nsys;
     Prof pr(P, st, KC_FWD_SWEEP, fb_high, 0.0);
-    hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(resident_grid(P, fh, lds, n)), dim3(kThreads), lds, st, a, wh,
+    hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(resident_grid(P, fh, lds, n, kSweepThreads)), dim3(kSweepThreads), lds,
+                       st, a, wh,
                        make_queue(P, n, 1, nlow > 0 ? -1 : 2), lf + nlow);
   }
   // backward: the top levels first
@@ -2464,7 +2485,8 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
     wh.lev_hi = nlev;
     const int n = nhigh * nsys;
     Prof pr(P, st, KC_BWD_SWEEP, fb_high, 0.0);
-    hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(resident_grid(P, bh, lds, n)), dim3(kThreads), lds, st, a, wh,
+    hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(resident_grid(P, bh, lds, n, kSweepThreads)), dim3(kSweepThreads), lds,
+                       st, a, wh,
                        make_queue(P, n, 1, 3), lf + nlow);
   }
   if (nlow > 0) {
