@@ -756,7 +756,10 @@ __device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
 template <typename C>
 __device__ __forceinline__ void invert_offdiag(C* F, int ld, int nb, C* T) {
   const int nsb = (nb + 15) / 16;
-  const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+  // r varies fastest across lanes: the reads of a row-r column are consecutive
+  // entries, the reads of column c are broadcasts (with c fastest, sixteen
+  // lanes would read addresses a whole column apart: 16-way bank conflicts)
+  const int r = threadIdx.x & 15, c = threadIdx.x >> 4;
   for (int jb = 0; jb + 1 < nsb; ++jb) {
     for (int ib = jb + 1; ib < nsb; ++ib) {
       const int ri = 16 * ib, cj = 16 * jb, bi = min(16, nb - ri), bj = min(16, nb - cj);
@@ -780,7 +783,7 @@ __device__ __forceinline__ void invert_offdiag(C* F, int ld, int nb, C* T) {
           }
         }
       }
-      if (r < bi && c < bj) T[r * 16 + c] = acc;
+      if (r < bi && c < bj) T[c * 16 + r] = acc;
       __syncthreads();
       if (r < bi && c < bj) {
         C v = czero<C>();
@@ -790,7 +793,7 @@ __device__ __forceinline__ void invert_offdiag(C* F, int ld, int nb, C* T) {
           C xv;
           xv.x = q < r ? xl.x : (q == r ? 1 : 0);
           xv.y = q < r ? xl.y : 0;
-          if (q < bi) v = cadd(v, cmul(xv, T[q * 16 + c]));
+          if (q < bi) v = cadd(v, cmul(xv, T[c * 16 + q]));
         }
         v.x = -v.x;
         v.y = -v.y;
