@@ -36,8 +36,21 @@ template <typename C> __device__ __forceinline__ C cfms(C acc, C a, C b) {
   acc.y = acc.y - a.x * b.y - a.y * b.x;
   return acc;
 }
+// 1/a: the hardware reciprocal estimate refined by two Newton steps (each
+// squares the relative error), within a couple of ulp of the rounded quotient
+// for the normal, finite a the pivots have; half the dependent operations of
+// an IEEE division, which sits on the serial chain of every pivot step.
+__device__ __forceinline__ double rcp_nr(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return fma(r, fma(-a, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_nr(float a) {
+  const float r = __builtin_amdgcn_rcpf(a);
+  return fmaf(r, fmaf(-a, r, 1.0f), r);
+}
 template <typename C> __device__ __forceinline__ C cinv(C d) {
-  const auto r = 1 / (d.x * d.x + d.y * d.y);
+  const auto r = rcp_nr(d.x * d.x + d.y * d.y);
   C o;
   o.x = d.x * r;
   o.y = -d.y * r;
@@ -455,7 +468,11 @@ __device__ __forceinline__ void publish(const Queue& q, int ep, int64_t idx) {
 // Matrix-core instructions used on LDS-resident operands: 16x16x4 products in
 // the factor precision.  Operand lanes: A row l%16 / B column l%16 at
 // k = l/16; the result row of register r differs between the f64 and f32
-// instructions (row()); its column is l%16.
+// instructions (row()); its column is l%16.  The tile routines below put the
+// output-column operand in the A slot, so each register holds the transposed
+// product: the output row varies with l%16, and a store of sixteen lanes to a
+// column-major LDS block covers consecutive entries (the other way round the
+// sixteen lanes would hit one bank, a whole column apart).
 template <typename R> struct Mfma;
 template <> struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
@@ -675,14 +692,14 @@ __device__ __forceinline__ void trail_mfma(C* F, int o, int b, int c0, int p, co
       const int q = 4 * ks + kq;
       const C av = F[(o + q) * kBW + 16 * BI + i];
       const C bv = Bt[q * kBW + 16 * BJ + i];
-      re = Mfma<R>::op(av.x, bv.x, re);
-      im = Mfma<R>::op(av.x, bv.y, im);
-      re = Mfma<R>::op(-av.y, bv.y, re);
-      im = Mfma<R>::op(av.y, bv.x, im);
+      re = Mfma<R>::op(bv.x, av.x, re);
+      im = Mfma<R>::op(bv.y, av.x, im);
+      re = Mfma<R>::op(bv.y, -av.y, re);
+      im = Mfma<R>::op(bv.x, av.y, im);
     }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      C* dst = F + (16 * BJ + i) * kBW + 16 * BI + Mfma<R>::row(l, rr);
+      C* dst = F + (16 * BJ + Mfma<R>::row(l, rr)) * kBW + 16 * BI + i;
       C v = *dst;
       v.x -= re[rr];
       v.y -= im[rr];
@@ -1007,7 +1024,8 @@ __device__ __forceinline__ void wait_at_least(const int32_t* p, int v, DevStatus
   }
 }
 
-
+// Address of entry (r, c) of front f: the factor panel for pivot columns, the
+// update block otherwise.
 template <typename C>
 __device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, int u, int m, int r, int c) {
   if (c < p) return (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)c * m + r;
@@ -1189,9 +1207,10 @@ __device__ __forceinline__ void task_trsm(const KArgs& a, int s, int f, int k, i
 // O[c][r] = sum_q A[q][r] B[q][c] (all column major with leading dimension
 // kBW, zero padded).  Wave w owns output rows 16w..16w+15 as four 16 x 16
 // blocks; per block and 4-deep k-step the complex product is four real
-// 16x16x4 MFMAs (re += ar br - ai bi, im += ar bi + ai br).  Operand lanes:
-// A row l%16 / B column l%16 at k = l/16; the result rows per register differ
-// between the f64 and f32 instructions (Mfma::row).  O may alias A or B: the
+// 16x16x4 MFMAs (re += ar br - ai bi, im += ar bi + ai br), with B's column
+// block in the instruction's A slot so that the result is the block's
+// transpose (output row = l%16, output column per register from Mfma::row,
+// conflict-free column-major stores).  O may alias A or B: the
 // products finish (barrier) before O is written, and a barrier follows.
 template <typename R, typename C>
 __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, C* O) {
@@ -1215,13 +1234,13 @@ __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, C* O) {
     // eight independent accumulators per pass, so no MFMA waits on the previous one
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
-      re[bj] = Mfma<R>::op(av.x, bv[bj].x, re[bj]);
-      im[bj] = Mfma<R>::op(av.x, bv[bj].y, im[bj]);
+      re[bj] = Mfma<R>::op(bv[bj].x, av.x, re[bj]);
+      im[bj] = Mfma<R>::op(bv[bj].y, av.x, im[bj]);
     }
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
-      re[bj] = Mfma<R>::op(nai, bv[bj].y, re[bj]);
-      im[bj] = Mfma<R>::op(av.y, bv[bj].x, im[bj]);
+      re[bj] = Mfma<R>::op(bv[bj].y, nai, re[bj]);
+      im[bj] = Mfma<R>::op(bv[bj].x, av.y, im[bj]);
     }
   }
   __syncthreads();
@@ -1232,7 +1251,7 @@ __device__ __forceinline__ void mfma_tile_abt(const C* A, const C* B, C* O) {
       C v;
       v.x = re[bj][r];
       v.y = im[bj][r];
-      O[(16 * bj + i) * kBW + 16 * wave + Mfma<R>::row(l, r)] = v;
+      O[(16 * bj + Mfma<R>::row(l, r)) * kBW + 16 * wave + i] = v;
     }
   __syncthreads();
 }
@@ -1268,10 +1287,10 @@ __device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O
       if (t < nblk) {  // uniform per wave
         const C av = A[q * kBW + 16 * bi[t] + i];
         const C bv = B[q * kBW + 16 * bj[t] + i];
-        re[t] = Mfma<R>::op(av.x, bv.x, re[t]);
-        im[t] = Mfma<R>::op(av.x, bv.y, im[t]);
-        re[t] = Mfma<R>::op(-av.y, bv.y, re[t]);
-        im[t] = Mfma<R>::op(av.y, bv.x, im[t]);
+        re[t] = Mfma<R>::op(bv.x, av.x, re[t]);
+        im[t] = Mfma<R>::op(bv.y, av.x, im[t]);
+        re[t] = Mfma<R>::op(bv.y, -av.y, re[t]);
+        im[t] = Mfma<R>::op(bv.x, av.y, im[t]);
       }
     }
   }
@@ -1284,7 +1303,7 @@ __device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O
         C v;
         v.x = re[t][r];
         v.y = im[t][r];
-        O[(16 * bj[t] + i) * kBW + 16 * bi[t] + Mfma<R>::row(l, r)] = v;
+        O[(16 * bj[t] + Mfma<R>::row(l, r)) * kBW + 16 * bi[t] + i] = v;
       }
     }
   __syncthreads();
