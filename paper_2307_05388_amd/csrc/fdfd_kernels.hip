@@ -558,12 +558,16 @@ __device__ void ldl_sub16(C* F, int ld, int o, int b, int m, C* dd, C* invd, C* 
 // sub-block columns w, w+4, w+8, w+12.  Each step the owner of pivot column k
 // publishes it to one of two alternating LDS buffers, one barrier, and every
 // wave forms l_k = a_k / d_k itself and updates its own columns (the same
-// operations, in the same order per entry, as ldl_sub16).  colbuf: 2 x 64.
-// Called by the whole workgroup.
+// operations, in the same order per entry, as ldl_sub16).  All LDS reads of a
+// step are issued together right after the barrier, before the step's writes
+// (d, 1/d), and the column updates are computed unconditionally and selected
+// (w is scalar), so a step costs one LDS round trip instead of one per read.
+// colbuf: 2 x 64.  Called by the whole workgroup.
 template <typename C>
 __device__ void ldl_sub16_mw(C* F, int ld, int o, int b, int m, C* dd, C* invd, C* colbuf, double thr,
                              double anorm, int& npert, double& minr, int& nonfin) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool act = l >= o && l < m;
   C col[4];
 #pragma unroll
@@ -577,29 +581,35 @@ __device__ void ldl_sub16_mw(C* F, int ld, int o, int b, int m, C* dd, C* invd, 
       C* buf = colbuf + (k & 1) * 64;
       if (w == (k & 3)) buf[l] = col[k >> 2];
       __syncthreads();
+      const C piv = buf[o + k];
+      const C bl = buf[l];
+      C cj[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cj[t] = buf[o + w + 4 * t];
       int np = 0, nf = 0;
       double mr = INFINITY;
-      const C d = fix_pivot(buf[o + k], thr, anorm, np, mr, nf);
+      const C d = fix_pivot(piv, thr, anorm, np, mr, nf);
       const C inv = cinv(d);
+      const C lk = cmul(bl, inv);
+      // Lanes l < o + j only touch entries above the diagonal, which are
+      // never published nor stored.
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = w + 4 * t;
+        const C upd = cfms(col[t], lk, cj[t]);
+        if (j > k && j < b) col[t] = upd;
+      }
+      if (w == (k & 3)) {
+        const bool below = l > o + k;
+        col[k >> 2].x = below ? lk.x : col[k >> 2].x;
+        col[k >> 2].y = below ? lk.y : col[k >> 2].y;
+      }
       if (threadIdx.x == 0) {
         npert += np;
         minr = fmin(minr, mr);
         nonfin |= nf;
         dd[o + k] = d;
         invd[o + k] = inv;
-      }
-      const C lk = cmul(buf[l], inv);
-      // Branch-free: lanes l < o + j only touch entries above the diagonal,
-      // which are never published nor stored.
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = w + 4 * t;
-        if (j > k && j < b) col[t] = cfms(col[t], lk, buf[o + j]);
-      }
-      if (w == (k & 3)) {
-        const bool below = l > o + k;
-        col[k >> 2].x = below ? lk.x : col[k >> 2].x;
-        col[k >> 2].y = below ? lk.y : col[k >> 2].y;
       }
     }
   }
