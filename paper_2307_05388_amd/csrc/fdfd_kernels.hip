@@ -489,6 +489,18 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
+// Broadcast of lane j's value to the whole wave (j uniform).
+template <typename C> __device__ __forceinline__ C bcast_c(C v, int j) {
+  constexpr int n = sizeof(C) / 4;
+  int w[n];
+  __builtin_memcpy(w, &v, sizeof(C));
+#pragma unroll
+  for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readlane(w[i], j);
+  C o;
+  __builtin_memcpy(&o, w, sizeof(C));
+  return o;
+}
+
 template <typename C> __device__ __forceinline__ C shfl_c(C v, int lane) {
   v.x = __shfl(v.x, lane);
   v.y = __shfl(v.y, lane);
@@ -755,20 +767,27 @@ __device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
   const int nsb = (nb + 15) / 16;
   if (wave < nsb) {
     const int o = 16 * wave, b = min(16, nb - o), j = lane;
-    // Branch-free: x[k] = 0 for k < j, so the full sums over k < i give the
-    // column (and 0 above the diagonal); only i < b is tested (uniform).
+    // Right-looking: once x_k is final every later row takes its term
+    // -L_ik x_k, so the dependent chain is one step per column (a row-by-row
+    // form chains all i terms of a row).  Per entry the subtractions and
+    // their order are those of the row-by-row form; x_k = 0 for k < j, so
+    // the sums give the column (and 0 above the diagonal, never stored).
     C x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      C v = czero<C>();
-      if (i < b) {
+      x[i].x = i == j ? 1 : 0;
+      x[i].y = 0;
+    }
 #pragma unroll
-        for (int k = 0; k < i; ++k) v = cfms(v, F[(o + k) * ld + o + i], x[k]);
+    for (int k = 0; k < 15; ++k) {
+      if (k < b) {
+        C lc[16];
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) lc[i] = i < b ? F[(o + k) * ld + o + i] : czero<C>();
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) x[i] = cfms(x[i], lc[i], x[k]);
       }
-      v.x = i == j ? 1 : v.x;
-      v.y = i == j ? 0 : v.y;
-      x[i] = v;
-      // keeps the row's LDS loads from being hoisted across rows (register pressure)
+      // keeps the next column's loads from being hoisted (register pressure)
       __builtin_amdgcn_sched_barrier(0);
     }
     if (j < b) {
@@ -1152,13 +1171,24 @@ __device__ __forceinline__ void trsm_core(C* Xs, const C* Ls, C* Vs, int nb) {
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) v[x][y] = Xs[(j0 + cb + y) * kBW + ra + 32 * x];
-    for (int q = 0; q < j0; ++q) {
-      const C x0 = Xs[q * kBW + ra], x1 = Xs[q * kBW + ra + 32];
-      const C l0 = Ls[q * kBW + j0 + cb], l1 = Ls[q * kBW + j0 + cb + 1];
-      v[0][0] = cfms(v[0][0], x0, l0);
-      v[0][1] = cfms(v[0][1], x0, l1);
-      v[1][0] = cfms(v[1][0], x1, l0);
-      v[1][1] = cfms(v[1][1], x1, l1);
+    // four steps' LDS reads in flight before their products (j0 % 16 == 0)
+    for (int q0 = 0; q0 < j0; q0 += 4) {
+      C x0[4], x1[4], l0[4], l1[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q = q0 + e;
+        x0[e] = Xs[q * kBW + ra];
+        x1[e] = Xs[q * kBW + ra + 32];
+        l0[e] = Ls[q * kBW + j0 + cb];
+        l1[e] = Ls[q * kBW + j0 + cb + 1];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[0][0] = cfms(v[0][0], x0[e], l0[e]);
+        v[0][1] = cfms(v[0][1], x0[e], l1[e]);
+        v[1][0] = cfms(v[1][0], x1[e], l0[e]);
+        v[1][1] = cfms(v[1][1], x1[e], l1[e]);
+      }
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -1880,17 +1910,6 @@ __device__ __forceinline__ void trace_wave(const Queue& q, int t, int slot) {
   }
 }
 
-// Broadcast of lane j's value to the whole wave (j uniform).
-template <typename C> __device__ __forceinline__ C bcast_c(C v, int j) {
-  constexpr int n = sizeof(C) / 4;
-  int w[n];
-  __builtin_memcpy(w, &v, sizeof(C));
-#pragma unroll
-  for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readlane(w[i], j);
-  C o;
-  __builtin_memcpy(&o, w, sizeof(C));
-  return o;
-}
 
 // Forward sweep of one small front by one wave (panel: D on the diagonal, the
 // unit-lower L below).  V = [rhs_p; 0] + the children's update vectors is
