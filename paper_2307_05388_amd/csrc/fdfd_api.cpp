@@ -407,11 +407,35 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
 
   std::vector<int32_t> tasks, tile_base, is_tiled;
   build_schedule(P, small_cap, tasks, tile_base, is_tiled);
-  // the fronts factored one workgroup per front store the single-GEMV panel
-  // form; the sweeps take them one wavefront per front
+  // the fronts factored one workgroup per front (plain L, D) are swept one
+  // wavefront per front
   P.wave_levels = P.small_prefix;
   P.wave_ld = 0;
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
+  // forward sweep items of the levels above: each front's pivot part, then
+  // the update-row chunks of the fronts whose L21 is split
+  std::vector<int32_t> fwd_items, nch(P.an.nfronts, 0), chunk_base(P.an.nfronts, 0);
+  {
+    const int nlow =
+        P.wave_levels > 0 ? P.levels[P.wave_levels - 1].first + P.levels[P.wave_levels - 1].count : 0;
+    int nc_total = 0;
+    for (int k = nlow; k < P.an.nfronts; ++k) {
+      const int f = P.an.level_fronts[k];
+      const int64_t p = P.an.npiv[f], u = P.an.nupd[f];
+      const int nc = u * p * (int64_t)cs >= fdfd::kSplitBytes ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
+      nch[f] = nc;
+      chunk_base[f] = nc_total;
+      fwd_items.push_back(f);
+      fwd_items.push_back(-1);
+      for (int j = 0; j < nc; ++j) {
+        fwd_items.push_back(f);
+        fwd_items.push_back(j);
+      }
+      nc_total += nc;
+    }
+    P.n_fwd_items = (int32_t)(fwd_items.size() / 2);
+    P.nchunk = nc_total;
+  }
   const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
   if (max_solve_lds > lds_dyn) {
     delete h;
@@ -423,9 +447,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   const int64_t sum_u = P.an.upd_ptr.back();
   P.res_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
   const int64_t need = nsys * P.an.fac_total * (int64_t)cs + nsys * P.an.upd_total * (int64_t)cs +
-                       nsys * (int64_t)P.ntiles * 4 + nsys * (int64_t)P.an.nfronts * 4 +
+                       nsys * (int64_t)P.ntiles * 4 + nsys * ((int64_t)P.an.nfronts + P.nchunk) * 4 +
                        nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16 + nsys * 8 + nsys * N * 8 +
-                       nsys * R * N * (int64_t)cs + nsys * R * sum_u * (int64_t)cs + 2 * nsys * R * N * 16 +
+                       2 * nsys * R * N * (int64_t)cs + nsys * R * sum_u * (int64_t)cs + 2 * nsys * R * N * 16 +
                        nsys * R * P.res_blocks * 16 + (int64_t)sizeof(fdfd::DevStatus);
   if (desc->mem_cap_bytes > 0 && need > desc->mem_cap_bytes) {
     delete h;
@@ -457,6 +481,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     P.tile_tasks_host = tasks;
     TRY(upload(P, &P.t.tile_base, tile_base));
     TRY(upload(P, &P.t.is_tiled, is_tiled));
+    TRY(upload(P, &P.t.fwd_items, fwd_items));
+    TRY(upload(P, &P.t.nch, nch));
+    TRY(upload(P, &P.t.chunk_base, chunk_base));
     TRY(upload(P, &P.t.parent, A.parent));
     TRY(upload(P, &P.t.height, A.height));
     TRY(upload(P, &P.t.fac_off, A.fac_off));
@@ -471,14 +498,15 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(alloc(P, (void**)&P.eps, nsys * N * 8));
     TRY(alloc(P, &P.y, nsys * R * N * cs));
     TRY(alloc(P, &P.wv, nsys * R * std::max<int64_t>(1, sum_u) * cs));
+    TRY(alloc(P, &P.zv, nsys * R * N * cs));
     TRY(alloc(P, (void**)&P.xw, nsys * R * N * 16));
     TRY(alloc(P, (void**)&P.res, nsys * R * N * 16));
     TRY(alloc(P, (void**)&P.partial, nsys * R * P.res_blocks * 16));
     TRY(alloc(P, (void**)&P.status, sizeof(fdfd::DevStatus)));
     TRY(alloc(P, (void**)&P.counters, fdfd::kCounterBytes));
-    TRY(alloc(P, (void**)&P.done, nsys * (int64_t)A.nfronts * 4));
+    TRY(alloc(P, (void**)&P.done, nsys * ((int64_t)A.nfronts + P.nchunk) * 4));
     hipError_t e = hipMemset(P.counters, 0, fdfd::kCounterBytes);
-    if (e == hipSuccess) e = hipMemset(P.done, 0, nsys * (int64_t)A.nfronts * 4);
+    if (e == hipSuccess) e = hipMemset(P.done, 0, nsys * ((int64_t)A.nfronts + P.nchunk) * 4);
     if (e == hipSuccess) e = hipMemset(P.status, 0, sizeof(fdfd::DevStatus));
     if (e != hipSuccess) {
       st = hip_fail(&P, e, "hipMemset");

@@ -1540,16 +1540,34 @@ struct SweepArgs {
   int32_t lev_lo, lev_hi;  // the launch's fronts have heights in [lev_lo, lev_hi);
                            // fronts outside finished in an earlier launch
   int32_t wave_ld;         // wave-item launches: LDS entries per wave and RHS
+  // forward launch of the tiled levels: (front, part) items, update-row
+  // chunks per front and their first flag slot, z of split fronts
+  const int32_t* items;
+  const int32_t* nch;
+  const int32_t* chunk_base;
+  void* zv;
+  int32_t nchunk;
 };
+
+// Completion flag of update-row chunk j of front f (after the fronts' flags).
+__device__ __forceinline__ const int32_t* chunk_flag(const Queue& q, const KArgs& a, const SweepArgs& w, int s,
+                                                     int f, int j) {
+  return q.done + (int64_t)a.nsys * a.nfronts + (int64_t)s * w.nchunk + w.chunk_base[f] + j;
+}
 
 // Waits of a sweep launch: only on fronts of the same launch (the others
 // finished before the launch began and carry an older epoch).  Called by one
 // thread, which spins; the caller orders its later loads after it.
+// A child whose update rows are split in chunks (w.nch, forward launch of the
+// tiled levels only) is complete when all its chunks are.
 __device__ __forceinline__ void sweep_wait_children(const Queue& q, int ep, const KArgs& a, const SweepArgs& w,
                                                     int s, int f) {
   for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k) {
     const int c = a.child_list[k];
-    if (a.height[c] >= w.lev_lo) wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + c);
+    if (a.height[c] < w.lev_lo) continue;
+    const int nc = w.nch ? w.nch[c] : 0;
+    if (nc == 0) wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + c);
+    for (int j = 0; j < nc; ++j) wait_flag(q, ep, chunk_flag(q, a, w, s, c, j));
   }
 }
 
@@ -1593,11 +1611,13 @@ constexpr int kNQ = kSW / 4;              // row parts of the backward column su
 // columns, partial sums meet in LDS), and V_below -= L_below,blk V_blk,
 // kRowStep rows per step (wave w: rows 64 (w / 4) + lane of the step, columns
 // w % 4, w % 4 + 4, ...; sixteen loads per thread in flight).  Finally
-// y_p = D^-1 V_p and the update vector is V_u.
+// y_p = D^-1 V_p and the update vector is V_u.  split: only the pivot rows
+// (the update rows are chunk items, fwd_chunk), and z = V_p goes to w.zv.
 template <typename R>
-__device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
+__device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, bool split, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const int p = a.npiv[f], u = a.nupd[f], m = split ? p : p + u, pb = a.pbeg[f];
+  const int ldl = p + u;  // leading dimension of the panel
   const int nrhs = w.nrhs;
   C* red = reinterpret_cast<C*>(smem);  // nrhs x 4 x kRowStep (>= nrhs x kSW x kBW) partial sums
   C* V = red + 4 * kRowStep * nrhs;     // nrhs x m
@@ -1606,7 +1626,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
   const double2* B = w.src + (int64_t)s * nrhs * a.N;
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
-  const int32_t* g = a.gmap + a.gmap_ptr[f];
+  const int32_t* g = a.gmap + a.gmap_ptr[f];  // rows of length ldl per child
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
     const int col = idx / m, r = idx - col * m;
     // the gather rows of up to two children first, then every value load
@@ -1614,7 +1634,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     int64_t base[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      gr[k] = k < nch ? g[k * m + r] : -1;
+      gr[k] = k < nch ? g[k * ldl + r] : -1;
       base[k] = k < nch ? (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] : 0;
     }
     double2 bv = make_double2(0.0, 0.0);
@@ -1625,7 +1645,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     if (r < p && w.scale_src) bv = dmul(bv, sym_scale(a, s, a.perm[pb + r]));
     C v = cadd(from_d2<C>(bv), cadd(cv[0], cv[1]));
     for (int k = 2; k < nch; ++k) {
-      const int gk = g[k * m + r];
+      const int gk = g[k * ldl + r];
       if (gk >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] + gk));
     }
     V[col * m + r] = v;
@@ -1635,7 +1655,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   const int cg = wave & 3, rq = wave >> 2;
   for (int k0 = 0; k0 < p; k0 += kBW) {
     const int kn = min(kBW, p - k0), k1 = k0 + kn;
-    const C* Xb = L + (int64_t)k0 * m + k0;
+    const C* Xb = L + (int64_t)k0 * ldl + k0;
     {
       // V_blk <- Xinv V_blk: lane = row, wave w takes columns w, w + kSW, ... < lane
       constexpr int NT = kBW / kSW;
@@ -1643,7 +1663,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int j = wave + kSW * t;
-        xv[t] = (lane < kn && j < lane) ? Xb[(int64_t)j * m + lane] : czero<C>();
+        xv[t] = (lane < kn && j < lane) ? Xb[(int64_t)j * ldl + lane] : czero<C>();
       }
       for (int col = 0; col < nrhs; ++col) {
         const C* Vb = V + col * m + k0;
@@ -1672,7 +1692,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
         const int j = cg + 4 * t;
-        const C* Lj = L + (int64_t)(k0 + min(j, kn - 1)) * m;
+        const C* Lj = L + (int64_t)(k0 + min(j, kn - 1)) * ldl;
         l[t] = j < kn && i < m ? Lj[i] : czero<C>();
       }
       for (int col = 0; col < nrhs; ++col) {
@@ -1699,8 +1719,86 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   }
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
     const int col = idx / m, r = idx - col * m;
-    if (r < p) Y[(int64_t)col * a.N + pb + r] = cmul(V[col * m + r], cinv(L[(int64_t)r * m + r]));
-    else st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), V[col * m + r]);
+    if (r < p) {
+      Y[(int64_t)col * a.N + pb + r] = cmul(V[col * m + r], cinv(L[(int64_t)r * ldl + r]));
+      if (split) st_ag((C*)w.zv + (int64_t)s * nrhs * a.N + (int64_t)col * a.N + pb + r, V[col * m + r]);
+    } else {
+      st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r - p), V[col * m + r]);
+    }
+  }
+}
+
+// One chunk of kChunkRows update rows R = [r0, r0 + nr) of a split front in
+// the forward sweep: V_R = the children's update-vector entries of those rows
+// (gathered before the front's pivot item is waited for), then
+// V_R -= L[R, 0:p] z_p with z_p from that item, stored as rows R of the
+// front's update vector.  Lane = row, wave w takes the columns w, w + kSW, ...
+// (kSweepBatch loads per thread in flight); the partial sums of the waves
+// accumulate in their own LDS slots and meet at the end.
+template <typename R>
+__device__ void fwd_chunk(const KArgs& a, const SweepArgs& w, const Queue& q, int ep, int s, int f, int j,
+                          unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const int r0 = p + kChunkRows * j, nr = min(kChunkRows, m - r0);
+  const int nrhs = w.nrhs;
+  C* red = reinterpret_cast<C*>(smem);   // nrhs x kSW x kChunkRows partial sums
+  C* V = red + kSW * kChunkRows * nrhs;  // nrhs x nr
+  C* Z = V + nr * nrhs;                  // nrhs x p
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
+  const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
+  const int32_t* g = a.gmap + a.gmap_ptr[f];
+  for (int idx = threadIdx.x; idx < nr * nrhs; idx += kSweepThreads) {
+    const int col = idx / nr, r = idx - col * nr;
+    C v = czero<C>();
+    for (int k = 0; k < nch; ++k) {
+      const int gk = g[k * m + r0 + r];
+      if (gk >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] + gk));
+    }
+    V[col * nr + r] = v;
+  }
+  for (int idx = threadIdx.x; idx < kSW * kChunkRows * nrhs; idx += kSweepThreads) red[idx] = czero<C>();
+  if (threadIdx.x == 0) {
+    wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + f);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  __syncthreads();
+  const C* Zs = (const C*)w.zv + (int64_t)s * nrhs * a.N;
+  for (int idx = threadIdx.x; idx < p * nrhs; idx += kSweepThreads) {
+    const int col = idx / p, r = idx - col * p;
+    Z[col * p + r] = ld_ag(Zs + (int64_t)col * a.N + pb + r);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool rowok = lane < nr;
+  const C* Li = L + r0 + (rowok ? lane : 0);
+  for (int t0 = wave; t0 < p; t0 += kSweepBatch * kSW) {
+    C l[kSweepBatch];
+#pragma unroll
+    for (int t = 0; t < kSweepBatch; ++t) {
+      const int c = t0 + kSW * t;
+      l[t] = rowok && c < p ? Li[(int64_t)c * m] : czero<C>();
+    }
+    for (int col = 0; col < nrhs; ++col) {
+      C* acc = red + (col * kSW + wave) * kChunkRows + lane;
+      C v = *acc;
+#pragma unroll
+      for (int t = 0; t < kSweepBatch; ++t) {
+        const int c = t0 + kSW * t;
+        v = cadd(v, cmul(l[t], c < p ? Z[col * p + c] : czero<C>()));
+      }
+      *acc = v;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nr * nrhs; idx += kSweepThreads) {
+    const int col = idx / nr, r = idx - col * nr;
+    const C* rr = red + col * kSW * kChunkRows + r;
+    C acc = czero<C>();
+#pragma unroll
+    for (int q2 = 0; q2 < kSW; ++q2) acc = cadd(acc, rr[q2 * kChunkRows]);
+    st_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[f] + (r0 - p) + r, csub(V[col * nr + r], acc));
   }
 }
 
@@ -1832,9 +1930,10 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
   }
 }
 
-// Forward sweep: items in level order (leaves first), each waits for its children.
+// Forward sweep: items (front, part) in level order (leaves first), a front's
+// pivot part before its update-row chunks; each waits for the children.
 template <typename R>
-__global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* items) {
   if (done(w.flag)) return;
   sweep_status(w);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1843,7 +1942,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs 
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
-    const int f = order[t / a.nsys], s = t % a.nsys;
+    const int it = t / a.nsys, s = t % a.nsys;
+    const int f = items[2 * it], part = items[2 * it + 1];
     if (q.wait) {
       if (threadIdx.x == 0) {
         sweep_wait_children(q, ep, a, w, s, f);
@@ -1852,8 +1952,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs 
       __syncthreads();
     }
     trace_mark(q, t, 1);
-    fwd_front<R>(a, w, s, f, smem_raw);
-    publish(q, ep, (int64_t)s * a.nfronts + f);
+    if (part < 0) {
+      fwd_front<R>(a, w, s, f, w.nch[f] > 0, smem_raw);
+      publish(q, ep, (int64_t)s * a.nfronts + f);
+    } else {
+      fwd_chunk<R>(a, w, q, ep, s, f, part, smem_raw);
+      publish(q, ep, (int64_t)a.nsys * a.nfronts + (int64_t)s * w.nchunk + w.chunk_base[f] + part);
+    }
     trace_mark(q, t, 2);
   }
   leave(q, ep);
@@ -2491,6 +2596,11 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   w.st = P.status;
   w.status_mode = status_mode;
   w.wave_ld = P.wave_ld;
+  w.items = P.t.fwd_items;
+  w.nch = P.t.nch;
+  w.chunk_base = P.t.chunk_base;
+  w.zv = P.zv;
+  w.nchunk = P.nchunk;
   const int32_t* lf = P.t.level_fronts;
   const int nlev = (int)P.levels.size();
   const int lw = P.wave_levels;
@@ -2522,11 +2632,11 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
     SweepArgs wh = w;
     wh.lev_lo = lw;
     wh.lev_hi = nlev;
-    const int n = nhigh * nsys;
+    const int n = P.n_fwd_items * nsys;
     Prof pr(P, st, KC_FWD_SWEEP, fb_high, 0.0);
     hipLaunchKernelGGL((k_fwd_sweep<R>), dim3(resident_grid(P, fh, lds, n, kSweepThreads)), dim3(kSweepThreads), lds,
                        st, a, wh,
-                       make_queue(P, n, 1, nlow > 0 ? -1 : 2), lf + nlow);
+                       make_queue(P, n, 1, nlow > 0 || P.nchunk > 0 ? -1 : 2), P.t.fwd_items);
   }
   // backward: the top levels first
   if (nhigh > 0) {

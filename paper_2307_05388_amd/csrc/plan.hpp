@@ -38,6 +38,7 @@ struct DevTables {
   int32_t *level_fronts = nullptr;
   int32_t *parent = nullptr, *height = nullptr;
   int32_t *tile_tasks = nullptr, *tile_base = nullptr, *is_tiled = nullptr;
+  int32_t *fwd_items = nullptr, *nch = nullptr, *chunk_base = nullptr;
   int64_t *fac_off = nullptr, *upd_off = nullptr, *gmap_ptr = nullptr;
 };
 
@@ -87,6 +88,11 @@ struct Plan {
   size_t lds_limit = 65536;
   int32_t wave_levels = 0;      // bottom levels swept one wavefront per front
   int32_t wave_ld = 0;          // largest front (rows) among them
+  // Forward sweep of the tiled levels: work items (front, part) in claim
+  // order, part -1 the pivot rows, part j >= 0 the j-th kChunkRows update
+  // rows of a front whose L21 is split over several workgroups.
+  int32_t n_fwd_items = 0;
+  int32_t nchunk = 0;           // update-row chunks of all split fronts (one system)
 
   // arenas (device)
   void* fac = nullptr;         // nsys * fac_total scalars
@@ -96,6 +102,7 @@ struct Plan {
   double* eps = nullptr;       // nsys * N (copy taken at refactor)
   void* y = nullptr;           // nsys * max_rhs * N scalars (elimination order)
   void* wv = nullptr;          // nsys * max_rhs * sum(u) scalars (update vectors)
+  void* zv = nullptr;          // nsys * max_rhs * N scalars: z = L11^-1 v of split fronts
   double2* xw = nullptr;       // nsys * max_rhs * N (adjoint work solution)
   double2* res = nullptr;      // nsys * max_rhs * N (FP64 residual)
   double* partial = nullptr;   // nsys * max_rhs * res_blocks * 2
@@ -103,7 +110,7 @@ struct Plan {
   DevStatus* status = nullptr;
   int32_t* counters = nullptr;  // [0..1] persistent-queue counters, [2] residual blocks,
                                 // [kEpochSlot] epoch of the last persistent launch
-  int32_t* done = nullptr;      // [nsys][nfronts] completion epochs
+  int32_t* done = nullptr;      // [nsys][nfronts] completion epochs, then [nsys][nchunk]
   int32_t* tile_state = nullptr;  // [nsys][ntiles] tile versions
   int32_t* tile_done = nullptr;   // [nsys][nfronts] finished update tiles
   DevStatus* status_host = nullptr;  // pinned
@@ -145,6 +152,10 @@ struct Plan {
 // The epoch of the last persistent launch sits in its own 128-byte line of
 // the counters array, apart from the counters that take atomics.
 constexpr int kEpochSlot = 32;
+// Forward sweep: a front whose L21 holds at least kSplitBytes is swept as its
+// pivot rows plus chunks of kChunkRows update rows, one workgroup each.
+constexpr int kChunkRows = 64;
+constexpr int64_t kSplitBytes = 256 << 10;
 constexpr size_t kCounterBytes = 256;
 
 // Kernel launchers (fdfd_kernels.hip).  Each returns hipSuccess or the first
