@@ -414,7 +414,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
   // forward sweep items of the levels above: each front's pivot part, then
   // the update-row chunks of the fronts whose L21 is split
-  std::vector<int32_t> fwd_items, nch(P.an.nfronts, 0), chunk_base(P.an.nfronts, 0);
+  std::vector<int32_t> fwd_items, bwd_items, nch(P.an.nfronts, 0), chunk_base(P.an.nfronts, 0);
+  std::vector<int64_t> part_base(P.an.nfronts, 0);
   {
     const int nlow =
         P.wave_levels > 0 ? P.levels[P.wave_levels - 1].first + P.levels[P.wave_levels - 1].count : 0;
@@ -435,6 +436,21 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     }
     P.n_fwd_items = (int32_t)(fwd_items.size() / 2);
     P.nchunk = nc_total;
+    // backward: root first, a front's chunks (partial column sums of its
+    // update rows) before its pivot part
+    int64_t pt = 0;
+    for (int k = P.an.nfronts - 1; k >= nlow; --k) {
+      const int f = P.an.level_fronts[k];
+      for (int j = 0; j < nch[f]; ++j) {
+        bwd_items.push_back(f);
+        bwd_items.push_back(j);
+      }
+      bwd_items.push_back(f);
+      bwd_items.push_back(-1);
+      part_base[f] = pt;
+      pt += (int64_t)nch[f] * P.an.npiv[f];
+    }
+    P.part_total = pt;
   }
   const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
   if (max_solve_lds > lds_dyn) {
@@ -449,7 +465,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   const int64_t need = nsys * P.an.fac_total * (int64_t)cs + nsys * P.an.upd_total * (int64_t)cs +
                        nsys * (int64_t)P.ntiles * 4 + nsys * ((int64_t)P.an.nfronts + P.nchunk) * 4 +
                        nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16 + nsys * 8 + nsys * N * 8 +
-                       2 * nsys * R * N * (int64_t)cs + nsys * R * sum_u * (int64_t)cs + 2 * nsys * R * N * 16 +
+                       2 * nsys * R * N * (int64_t)cs + nsys * R * (sum_u + P.part_total) * (int64_t)cs +
+                       2 * nsys * R * N * 16 +
                        nsys * R * P.res_blocks * 16 + (int64_t)sizeof(fdfd::DevStatus);
   if (desc->mem_cap_bytes > 0 && need > desc->mem_cap_bytes) {
     delete h;
@@ -482,6 +499,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(upload(P, &P.t.tile_base, tile_base));
     TRY(upload(P, &P.t.is_tiled, is_tiled));
     TRY(upload(P, &P.t.fwd_items, fwd_items));
+    TRY(upload(P, &P.t.bwd_items, bwd_items));
+    TRY(upload(P, &P.t.part_base, part_base));
     TRY(upload(P, &P.t.nch, nch));
     TRY(upload(P, &P.t.chunk_base, chunk_base));
     TRY(upload(P, &P.t.parent, A.parent));
@@ -499,6 +518,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(alloc(P, &P.y, nsys * R * N * cs));
     TRY(alloc(P, &P.wv, nsys * R * std::max<int64_t>(1, sum_u) * cs));
     TRY(alloc(P, &P.zv, nsys * R * N * cs));
+    TRY(alloc(P, &P.pv, nsys * R * std::max<int64_t>(1, P.part_total) * cs));
     TRY(alloc(P, (void**)&P.xw, nsys * R * N * 16));
     TRY(alloc(P, (void**)&P.res, nsys * R * N * 16));
     TRY(alloc(P, (void**)&P.partial, nsys * R * P.res_blocks * 16));

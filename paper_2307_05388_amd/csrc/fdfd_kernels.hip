@@ -1547,6 +1547,10 @@ struct SweepArgs {
   const int32_t* chunk_base;
   void* zv;
   int32_t nchunk;
+  // backward launch of the tiled levels: partial column sums of the chunks
+  const int64_t* part_base;
+  void* pv;
+  int64_t part_total;
 };
 
 // Completion flag of update-row chunk j of front f (after the fronts' flags).
@@ -1847,45 +1851,57 @@ __device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, in
 // (diag = false) or, for column jj, the rows jj+1 .. kn-1 of the diagonal
 // block's inverse (diag = true), per row part into red[c][part][jj].
 template <int NR, typename C>
-__device__ __forceinline__ void bwd_group(const C* L, const C* X, C* red, int m, int k0, int kn, int k1, int c0,
-                                          bool diag) {
+__device__ __forceinline__ void bwd_group(const C* L, int ldl, const C* X, C* red, int m, int k0, int kn, int k1,
+                                          int c0, bool diag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int jj = 16 * (wave & 3) + (lane & 15), rq = wave >> 2;
   const bool colok = jj < kn;
   C acc[NR];
-  if (!diag) bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m, colok, X + c0 * m, m, k1, m, acc);
-  else bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * m + k0, colok, X + c0 * m + k0, m, jj + 1, kn, acc);
+  if (!diag) bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * ldl, colok, X + c0 * m, m, k1, m, acc);
+  else bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * ldl + k0, colok, X + c0 * m + k0, m, jj + 1, kn, acc);
   if (lane < 16)
 #pragma unroll
     for (int c = 0; c < NR; ++c) red[((c0 + c) * kNQ + rq) * kBW + jj] = acc[c];
 }
 
+// L: the panel (leading dimension ldl); X: nrhs x m, rows [k1, m) summed.
 template <typename C>
-__device__ __forceinline__ void bwd_block(const C* L, const C* X, C* red, int m, int k0, int kn, int k1, int nrhs,
-                                          bool diag) {
+__device__ __forceinline__ void bwd_block(const C* L, int ldl, const C* X, C* red, int m, int k0, int kn, int k1,
+                                          int nrhs, bool diag) {
   for (int c0 = 0; c0 < nrhs; c0 += 2) {
-    if (nrhs - c0 >= 2) bwd_group<2>(L, X, red, m, k0, kn, k1, c0, diag);
-    else bwd_group<1>(L, X, red, m, k0, kn, k1, c0, diag);
+    if (nrhs - c0 >= 2) bwd_group<2>(L, ldl, X, red, m, k0, kn, k1, c0, diag);
+    else bwd_group<1>(L, ldl, X, red, m, k0, kn, k1, c0, diag);
   }
 }
 
 // One front of the backward sweep.  X = [z_p; x(update rows)]; for kBW-wide
 // blocks from the last: X_blk -= L_below,blk^T X_below, then
 // X_blk <- Xinv^T X_blk (column dot products, bwd_dots; the row parts meet
-// in LDS).  x_p goes to y and to the grid-order output.
+// in LDS).  x_p goes to y and to the grid-order output.  Split fronts (nc
+// chunks): the update rows' part of X_p -= L21^T x_u comes from the chunk
+// items (bwd_chunk, summed in chunk order) and only the pivot rows remain.
 template <typename R>
-__device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsigned char* smem) {
+__device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, int nc, unsigned char* smem) {
   typedef typename Cx<R>::T C;
-  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  const bool split = nc > 0;
+  const int p = a.npiv[f], u = a.nupd[f], m = split ? p : p + u, pb = a.pbeg[f];
+  const int ldl = p + u;  // leading dimension of the panel
   const int nrhs = w.nrhs;
   C* red = reinterpret_cast<C*>(smem);  // nrhs x kNQ x kBW
   C* X = red + kNQ * nrhs * kBW;
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
+  const C* PB = (const C*)w.pv + (int64_t)s * nrhs * w.part_total + (split ? w.part_base[f] : 0);
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
     const int col = idx / m, r = idx - col * m;
-    X[col * m + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
+    C v = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
+    if (split) {
+      C acc = czero<C>();
+      for (int j = 0; j < nc; ++j) acc = cadd(acc, ld_ag(PB + (int64_t)col * w.part_total + (int64_t)j * p + r));
+      v = csub(v, acc);
+    }
+    X[col * m + r] = v;
   }
   __syncthreads();
   int k1 = p;
@@ -1893,7 +1909,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     const int k0 = ((k1 - 1) / kBW) * kBW;
     const int kn = k1 - k0;
     if (k1 < m) {
-      bwd_block(L, X, red, m, k0, kn, k1, nrhs, false);
+      bwd_block(L, ldl, X, red, m, k0, kn, k1, nrhs, false);
       __syncthreads();
       for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
         const int col = idx / kn, j = idx - col * kn;
@@ -1905,7 +1921,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
       }
       __syncthreads();
     }
-    bwd_block(L, X, red, m, k0, kn, k1, nrhs, true);
+    bwd_block(L, ldl, X, red, m, k0, kn, k1, nrhs, true);
     __syncthreads();
     // x_blk = X_blk + the parts' sums (every read of X_blk above is done)
     for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
@@ -1927,6 +1943,51 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, unsi
     double2* o = O + (int64_t)col * a.N + a.perm[pb + r];
     const double2 xv = to_d2(x);
     *o = w.accumulate ? dadd(*o, xv) : xv;
+  }
+}
+
+// One chunk of kChunkRows update rows R = [r0, r0 + nr) of a split front in
+// the backward sweep: the partial column sums P_j[c] = sum_{r in R} L[r][c]
+// x_r for all pivot columns c, x_r from the solution of the ancestors (in y),
+// stored for the front's pivot item.  Lanes are 16 columns x 4 row phases
+// (16 cache lines per load instruction), 16 loads per thread in flight, the
+// waves take 16-column groups; the row phases meet through lane exchanges.
+template <typename R>
+__device__ void bwd_chunk(const KArgs& a, const SweepArgs& w, int s, int f, int j, unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  static_assert(kChunkRows == 64, "four row phases of sixteen rows");
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u;
+  const int r0 = p + kChunkRows * j, nr = min(kChunkRows, m - r0);
+  const int nrhs = w.nrhs;
+  C* X = reinterpret_cast<C*>(smem);  // nrhs x kChunkRows
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  const C* Y = (const C*)w.y + (int64_t)s * nrhs * a.N;
+  const int32_t* ui = a.upd_idx + a.upd_ptr[f];
+  for (int idx = threadIdx.x; idx < kChunkRows * nrhs; idx += kSweepThreads) {
+    const int col = idx / kChunkRows, r = idx - col * kChunkRows;
+    X[idx] = r < nr ? ld_ag(Y + (int64_t)col * a.N + ui[r0 - p + r]) : czero<C>();
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q4 = lane >> 4;
+  C* PB = (C*)w.pv + (int64_t)s * nrhs * w.part_total + w.part_base[f] + (int64_t)j * p;
+  for (int c0 = 16 * wave; c0 < p; c0 += 16 * kSW) {
+    const int c = c0 + (lane & 15);
+    const bool cok = c < p;
+    const C* Lc = L + (int64_t)(cok ? c : 0) * m + r0;
+    C l[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int r = q4 + 4 * t;
+      l[t] = cok && r < nr ? Lc[r] : czero<C>();
+    }
+    for (int col = 0; col < nrhs; ++col) {
+      C acc = czero<C>();
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc = cadd(acc, cmul(l[t], X[col * kChunkRows + q4 + 4 * t]));
+      acc = cadd(acc, shfl_xor_c(acc, 16));
+      acc = cadd(acc, shfl_xor_c(acc, 32));
+      if (lane < 16 && cok) st_ag(PB + (int64_t)col * w.part_total + c, acc);
+    }
   }
 }
 
@@ -1964,9 +2025,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs 
   leave(q, ep);
 }
 
-// Backward sweep: items in reverse level order (root first), each waits for its parent.
+// Backward sweep: items (front, part) in reverse level order (root first), a
+// front's update-row chunks before its pivot part.  Chunks and unsplit fronts
+// wait for the parent; the pivot part of a split front waits for its chunks.
 template <typename R>
-__global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs w, Queue q, const int32_t* items) {
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
@@ -1975,17 +2038,28 @@ __global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs 
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
-    const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
+    const int it = t / a.nsys, s = t % a.nsys;
+    const int f = items[2 * it], part = items[2 * it + 1];
+    const int nc = w.nch[f];
     if (q.wait) {
       if (threadIdx.x == 0) {
-        sweep_wait_parent(q, ep, a, w, s, f);
+        if (part >= 0 || nc == 0) {
+          sweep_wait_parent(q, ep, a, w, s, f);
+        } else {
+          for (int j = 0; j < nc; ++j) wait_flag(q, ep, chunk_flag(q, a, w, s, f, j));
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
       __syncthreads();
     }
     trace_mark(q, t, 1);
-    bwd_front<R>(a, w, s, f, smem_raw);
-    publish(q, ep, (int64_t)s * F + f);
+    if (part < 0) {
+      bwd_front<R>(a, w, s, f, nc, smem_raw);
+      publish(q, ep, (int64_t)s * F + f);
+    } else {
+      bwd_chunk<R>(a, w, s, f, part, smem_raw);
+      publish(q, ep, (int64_t)a.nsys * F + (int64_t)s * w.nchunk + w.chunk_base[f] + part);
+    }
     trace_mark(q, t, 2);
   }
   leave(q, ep);
@@ -2601,6 +2675,9 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   w.chunk_base = P.t.chunk_base;
   w.zv = P.zv;
   w.nchunk = P.nchunk;
+  w.part_base = P.t.part_base;
+  w.pv = P.pv;
+  w.part_total = P.part_total;
   const int32_t* lf = P.t.level_fronts;
   const int nlev = (int)P.levels.size();
   const int lw = P.wave_levels;
@@ -2644,11 +2721,11 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
     wh.status_mode = -1;
     wh.lev_lo = lw;
     wh.lev_hi = nlev;
-    const int n = nhigh * nsys;
+    const int n = P.n_fwd_items * nsys;
     Prof pr(P, st, KC_BWD_SWEEP, fb_high, 0.0);
     hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(resident_grid(P, bh, lds, n, kSweepThreads)), dim3(kSweepThreads), lds,
                        st, a, wh,
-                       make_queue(P, n, 1, 3), lf + nlow);
+                       make_queue(P, n, 1, P.nchunk > 0 ? -1 : 3), P.t.bwd_items);
   }
   if (nlow > 0) {
     SweepArgs wl = w;

@@ -38,7 +38,8 @@ struct DevTables {
   int32_t *level_fronts = nullptr;
   int32_t *parent = nullptr, *height = nullptr;
   int32_t *tile_tasks = nullptr, *tile_base = nullptr, *is_tiled = nullptr;
-  int32_t *fwd_items = nullptr, *nch = nullptr, *chunk_base = nullptr;
+  int32_t *fwd_items = nullptr, *bwd_items = nullptr, *nch = nullptr, *chunk_base = nullptr;
+  int64_t *part_base = nullptr;
   int64_t *fac_off = nullptr, *upd_off = nullptr, *gmap_ptr = nullptr;
 };
 
@@ -93,6 +94,7 @@ struct Plan {
   // rows of a front whose L21 is split over several workgroups.
   int32_t n_fwd_items = 0;
   int32_t nchunk = 0;           // update-row chunks of all split fronts (one system)
+  int64_t part_total = 0;       // backward: sum over split fronts of chunks x pivots
 
   // arenas (device)
   void* fac = nullptr;         // nsys * fac_total scalars
@@ -103,6 +105,7 @@ struct Plan {
   void* y = nullptr;           // nsys * max_rhs * N scalars (elimination order)
   void* wv = nullptr;          // nsys * max_rhs * sum(u) scalars (update vectors)
   void* zv = nullptr;          // nsys * max_rhs * N scalars: z = L11^-1 v of split fronts
+  void* pv = nullptr;          // nsys * max_rhs * part_total scalars: backward chunk sums
   double2* xw = nullptr;       // nsys * max_rhs * N (adjoint work solution)
   double2* res = nullptr;      // nsys * max_rhs * N (FP64 residual)
   double* partial = nullptr;   // nsys * max_rhs * res_blocks * 2
@@ -152,8 +155,9 @@ struct Plan {
 // The epoch of the last persistent launch sits in its own 128-byte line of
 // the counters array, apart from the counters that take atomics.
 constexpr int kEpochSlot = 32;
-// Forward sweep: a front whose L21 holds at least kSplitBytes is swept as its
-// pivot rows plus chunks of kChunkRows update rows, one workgroup each.
+// Sweeps of the tiled levels: a front whose L21 holds at least kSplitBytes is
+// swept as its pivot rows plus chunks of kChunkRows update rows, one
+// workgroup each.
 constexpr int kChunkRows = 64;
 constexpr int64_t kSplitBytes = 256 << 10;
 constexpr size_t kCounterBytes = 256;
