@@ -420,10 +420,12 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     const int nlow =
         P.wave_levels > 0 ? P.levels[P.wave_levels - 1].first + P.levels[P.wave_levels - 1].count : 0;
     int nc_total = 0;
+    // FDFD_SPLIT_KB: the L21 size (KiB) from which a front is split
+    const int64_t split_bytes = (int64_t)env_int("FDFD_SPLIT_KB", (int)(fdfd::kSplitBytes >> 10)) << 10;
     for (int k = nlow; k < P.an.nfronts; ++k) {
       const int f = P.an.level_fronts[k];
       const int64_t p = P.an.npiv[f], u = P.an.nupd[f];
-      const int nc = u * p * (int64_t)cs >= fdfd::kSplitBytes ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
+      const int nc = u > 0 && u * p * (int64_t)cs >= split_bytes ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
       nch[f] = nc;
       chunk_base[f] = nc_total;
       fwd_items.push_back(f);

@@ -159,7 +159,7 @@ constexpr int kEpochSlot = 32;
 // swept as its pivot rows plus chunks of kChunkRows update rows, one
 // workgroup each.
 constexpr int kChunkRows = 64;
-constexpr int64_t kSplitBytes = 256 << 10;
+constexpr int64_t kSplitBytes = 128 << 10;
 constexpr size_t kCounterBytes = 256;
 
 // Kernel launchers (fdfd_kernels.hip).  Each returns hipSuccess or the first
