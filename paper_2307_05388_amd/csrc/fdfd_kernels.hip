@@ -2137,6 +2137,43 @@ __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
   }
   wave_sync();
   const C dl = lane < p ? L[(int64_t)lane * m + lane] : czero<C>();
+  if (m <= 128) {
+    // One right-looking pass over the pivot columns for the pivot and the
+    // update rows together (lane = row, rows lane and lane + 64): at step j,
+    // z_j is final in lane j and every later row takes -L_ij z_j.  The pivot
+    // rows end as z, the update rows as V_u - L21 z.
+    const int r1 = lane + 64;
+    const bool two = m > 64;
+    for (int col = 0; col < nrhs; ++col) {
+      C* Vc = V + col * ldv;
+      C v0 = lane < m ? Vc[lane] : czero<C>();
+      C v1 = two && r1 < m ? Vc[r1] : czero<C>();
+#pragma unroll 1
+      for (int j0 = 0; j0 < p; j0 += WB) {
+        C e0[WB], e1[WB];
+#pragma unroll
+        for (int t = 0; t < WB; ++t) {
+          const int j = j0 + t;
+          e0[t] = j < p && j < lane && lane < m ? L[(int64_t)j * m + lane] : czero<C>();
+          e1[t] = two && j < p && r1 < m ? L[(int64_t)j * m + r1] : czero<C>();
+        }
+#pragma unroll
+        for (int t = 0; t < WB; ++t) {
+          const int j = j0 + t;
+          if (j < p) {
+            const C zj = bcast_c(v0, j);
+            v0 = cfms(v0, e0[t], zj);
+            if (two) v1 = cfms(v1, e1[t], zj);
+          }
+        }
+      }
+      C* Wf = W + (int64_t)col * a.sum_u + a.upd_ptr[f];
+      if (lane < p) Y[(int64_t)col * a.N + pb + lane] = cmul(v0, cinv(dl));
+      else if (lane < m) st_ag(Wf + (lane - p), v0);
+      if (two && r1 < m) st_ag(Wf + (r1 - p), v1);
+    }
+    return;
+  }
   for (int col = 0; col < nrhs; ++col) {
     C* Vc = V + col * ldv;
     // z = L11^-1 V_p, lane = row
