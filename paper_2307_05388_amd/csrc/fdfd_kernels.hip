@@ -1061,6 +1061,21 @@ __device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, in
   return (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f] + (int64_t)(c - p) * u + (r - p);
 }
 
+// The first part of ASM(I,J) on a pivot column chunk: the original operator
+// entries of its columns (stage_columns), which depend on no other task, so
+// the kernel runs it before the task's dependency wait.  A barrier follows in
+// the caller before task_asm reads them.
+template <typename R>
+__device__ __forceinline__ void asm_stage(const KArgs& a, int s, int f, int J, unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int c0 = ch.lo(J), nc = ch.hi(J) - c0;
+  if (c0 < ch.p) {
+    C* sv = reinterpret_cast<C*>(smem);
+    stage_columns(a, s, f, c0, nc, sv, reinterpret_cast<int*>(sv + 5 * kBW));
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
@@ -1068,10 +1083,8 @@ __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, in
   const int r0 = ch.lo(I), r1 = ch.hi(I), c0 = ch.lo(J), c1 = ch.hi(J);
   const int nr = r1 - r0, nc = c1 - c0;
   const bool piv = c0 < ch.p;  // pivot chunks hold original entries
-  C* sv = reinterpret_cast<C*>(smem);
+  C* sv = reinterpret_cast<C*>(smem);  // the pivot columns' stencils, staged by asm_stage
   int* nbv = reinterpret_cast<int*>(sv + 5 * kBW);
-  if (piv) stage_columns(a, s, f, c0, nc, sv, nbv);
-  __syncthreads();
   // lane = row, wave w takes the columns w, w+4, ...: four per batch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = r0 + lane;
@@ -1446,6 +1459,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     const int type = tk[0], f = tk[1], k = tk[2], I = tk[3], J = tk[4];
     const Chunks ch(a.npiv[f], a.nupd[f]);
     int32_t* st = ta.state + (int64_t)s * ta.ntiles + ta.tile_base[f];
+    if (type == T_ASM) asm_stage<R>(a, s, f, J, smem_raw);  // independent of the wait below
     if (threadIdx.x == 0) {
       if (type == T_ASM) {
         for (int c = a.child_ptr[f]; c < a.child_ptr[f + 1]; ++c) {
