@@ -1577,15 +1577,21 @@ __device__ __forceinline__ const int32_t* chunk_flag(const Queue& q, const KArgs
 // finished before the launch began and carry an older epoch).  Called by one
 // thread, which spins; the caller orders its later loads after it.
 // A child whose update rows are split in chunks (w.nch, forward launch of the
-// tiled levels only) is complete when all its chunks are.
+// tiled levels only) is complete when all its chunks are.  The flags are
+// shared out over threads tid of nt (each flag read is a memory round trip,
+// so one thread reading them in turn would chain them); the caller orders its
+// later loads after the waits (fence + barrier).
 __device__ __forceinline__ void sweep_wait_children(const Queue& q, int ep, const KArgs& a, const SweepArgs& w,
-                                                    int s, int f) {
+                                                    int s, int f, int tid, int nt) {
+  int base = 0;  // position of the child's first flag among all the item's flags
   for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k) {
     const int c = a.child_list[k];
     if (a.height[c] < w.lev_lo) continue;
     const int nc = w.nch ? w.nch[c] : 0;
-    if (nc == 0) wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + c);
-    for (int j = 0; j < nc; ++j) wait_flag(q, ep, chunk_flag(q, a, w, s, c, j));
+    const int nf = nc > 0 ? nc : 1;
+    for (int j = tid - base; j < nf; j += nt)
+      if (j >= 0) wait_flag(q, ep, nc > 0 ? chunk_flag(q, a, w, s, c, j) : q.done + (int64_t)s * a.nfronts + c);
+    base += nf;
   }
 }
 
@@ -1911,8 +1917,17 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, int 
     const int col = idx / m, r = idx - col * m;
     C v = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
     if (split) {
+      // eight chunks' sums in flight at a time, added in chunk order
+      const C* pr = PB + (int64_t)col * w.part_total + r;
       C acc = czero<C>();
-      for (int j = 0; j < nc; ++j) acc = cadd(acc, ld_ag(PB + (int64_t)col * w.part_total + (int64_t)j * p + r));
+      for (int j0 = 0; j0 < nc; j0 += 8) {
+        C pj[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) pj[t] = j0 + t < nc ? ld_ag(pr + (int64_t)(j0 + t) * p) : czero<C>();
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (j0 + t < nc) acc = cadd(acc, pj[t]);
+      }
       v = csub(v, acc);
     }
     X[col * m + r] = v;
@@ -2020,10 +2035,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs 
     const int it = t / a.nsys, s = t % a.nsys;
     const int f = items[2 * it], part = items[2 * it + 1];
     if (q.wait) {
-      if (threadIdx.x == 0) {
-        sweep_wait_children(q, ep, a, w, s, f);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      }
+      sweep_wait_children(q, ep, a, w, s, f, threadIdx.x, kSweepThreads);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       __syncthreads();
     }
     trace_mark(q, t, 1);
@@ -2057,13 +2070,12 @@ __global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs 
     const int nc = w.nch[f];
     if (q.wait) {
       if (threadIdx.x == 0) {
-        if (part >= 0 || nc == 0) {
-          sweep_wait_parent(q, ep, a, w, s, f);
-        } else {
-          for (int j = 0; j < nc; ++j) wait_flag(q, ep, chunk_flag(q, a, w, s, f, j));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (part >= 0 || nc == 0) sweep_wait_parent(q, ep, a, w, s, f);
       }
+      // the chunks of a split front, one thread each
+      if (part < 0)
+        for (int j = threadIdx.x; j < nc; j += kSweepThreads) wait_flag(q, ep, chunk_flag(q, a, w, s, f, j));
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       __syncthreads();
     }
     trace_mark(q, t, 1);
@@ -2319,7 +2331,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_sweep_waves(KArgs a, SweepA
     if (t < q.ntasks) {
       trace_wave(q, t, 0);
       const int f = order[t / a.nsys], s = t % a.nsys;
-      if (q.wait && (threadIdx.x & 63) == 0) sweep_wait_children(q, ep, a, w, s, f);
+      if (q.wait) sweep_wait_children(q, ep, a, w, s, f, threadIdx.x & 63, 64);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       trace_wave(q, t, 1);
