@@ -428,12 +428,11 @@ __device__ __forceinline__ void wait_flag(const Queue& q, int ep, const int32_t*
   }
 }
 
+// One thread per child (each flag read is a memory round trip).
 __device__ __forceinline__ void wait_children(const Queue& q, int ep, const KArgs& a, int s, int f) {
-  if (threadIdx.x == 0) {
-    for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k)
-      wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  }
+  for (int k = a.child_ptr[f] + threadIdx.x; k < a.child_ptr[f + 1]; k += blockDim.x)
+    wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   __syncthreads();
 }
 
@@ -1460,29 +1459,34 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     const Chunks ch(a.npiv[f], a.nupd[f]);
     int32_t* st = ta.state + (int64_t)s * ta.ntiles + ta.tile_base[f];
     if (type == T_ASM) asm_stage<R>(a, s, f, J, smem_raw);  // independent of the wait below
-    if (threadIdx.x == 0) {
+    {
+      // the task's dependencies, one thread each (each read is a memory
+      // round trip; one thread reading them in turn would chain them)
+      const int tid = threadIdx.x;
       if (type == T_ASM) {
-        for (int c = a.child_ptr[f]; c < a.child_ptr[f + 1]; ++c) {
+        const int c = a.child_ptr[f] + tid;
+        if (c < a.child_ptr[f + 1]) {
           const int cf = a.child_list[c];
-          if (!ta.is_tiled[cf]) continue;
-          const int nut = (a.nupd[cf] + kBW - 1) / kBW;
-          wait_at_least(ta.done + (int64_t)s * a.nfronts + cf, nut * (nut + 1) / 2, a.st);
+          if (ta.is_tiled[cf]) {
+            const int nut = (a.nupd[cf] + kBW - 1) / kBW;
+            wait_at_least(ta.done + (int64_t)s * a.nfronts + cf, nut * (nut + 1) / 2, a.st);
+          }
         }
       } else if (type == T_DIAG) {
-        wait_value(st + tile_id(k, k), k + 1, a.st);
+        if (tid == 0) wait_value(st + tile_id(k, k), k + 1, a.st);
       } else if (type == T_TRSM) {
-        wait_value(st + tile_id(k, k), k + 2, a.st);
-        wait_value(st + tile_id(I, k), k + 1, a.st);
+        if (tid == 0) wait_value(st + tile_id(k, k), k + 2, a.st);
+        if (tid == 1) wait_value(st + tile_id(I, k), k + 1, a.st);
       } else if (type == T_INV) {
-        for (int i = k + 1; i < ch.nbk + ch.nut; ++i) wait_value(st + tile_id(i, k), k + 2, a.st);
+        for (int i = k + 1 + tid; i < ch.nbk + ch.nut; i += kThreads) wait_value(st + tile_id(i, k), k + 2, a.st);
       } else if (type == T_FUSED) {
-        wait_value(st + tile_id(k - 1, k - 1), k + 1, a.st);
-        wait_value(st + tile_id(k, k - 1), k, a.st);
-        wait_value(st + tile_id(k, k), k, a.st);
+        if (tid == 0) wait_value(st + tile_id(k - 1, k - 1), k + 1, a.st);
+        if (tid == 1) wait_value(st + tile_id(k, k - 1), k, a.st);
+        if (tid == 2) wait_value(st + tile_id(k, k), k, a.st);
       } else {
-        wait_value(st + tile_id(I, k), k + 2, a.st);
-        wait_value(st + tile_id(J, k), k + 2, a.st);
-        wait_value(st + tile_id(I, J), k + 1, a.st);
+        if (tid == 0) wait_value(st + tile_id(I, k), k + 2, a.st);
+        if (tid == 1) wait_value(st + tile_id(J, k), k + 2, a.st);
+        if (tid == 2) wait_value(st + tile_id(I, J), k + 1, a.st);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
