@@ -1425,15 +1425,23 @@ __device__ __forceinline__ void task_fused(const KArgs& a, int s, int f, int k, 
   drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(st + tile_id(k, k - 1), k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  mfma_tile_abt_lower<R>(Xs, Ls, Xs);
-  // tile (k, k) - product, into Ls (lower triangle), then DIAG(k) with its
-  // pivots and scratch in the Xs region
+  // tile (k, k) (final but for this step's update) is loaded before the
+  // product so that the loads overlap it
   C t[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int c = wave + 4 * q;
     const bool keep = c < nb && lane < nb && lane >= c;
-    t[q] = keep ? csub(ld_ag(L + (int64_t)(k0 + c) * m + k0 + lane), Xs[c * kBW + lane]) : czero<C>();
+    t[q] = keep ? ld_ag(L + (int64_t)(k0 + c) * m + k0 + lane) : czero<C>();
+  }
+  mfma_tile_abt_lower<R>(Xs, Ls, Xs);
+  // tile (k, k) - product, into Ls (lower triangle), then DIAG(k) with its
+  // pivots and scratch in the Xs region
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = wave + 4 * q;
+    const bool keep = c < nb && lane < nb && lane >= c;
+    t[q] = keep ? csub(t[q], Xs[c * kBW + lane]) : czero<C>();
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) Ls[(wave + 4 * q) * kBW + lane] = t[q];
