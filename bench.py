@@ -114,8 +114,8 @@ def run_mode(args, p, mode, eps_all, b, c, omegas, profile=False):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
-                                   "note only, so --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; sharding over several GPUs is not "
+                                   "implemented, so --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2307_05388_amd import problems as P
