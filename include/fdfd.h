@@ -121,6 +121,13 @@ typedef struct {
  * Sec. II): nested dissection, separator tree, front layout, index maps and
  * level schedule, then device allocation of every arena.  Host work plus one
  * upload.  *out receives a new plan on success and NULL otherwise.
+ * Read here from the environment, for measurement only (all optional):
+ *   FDFD_SMALL_LDS  LDS budget (bytes) of the one-workgroup front kernel when
+ *                   desc->small_lds is 0;
+ *   FDFD_SPLIT_KB   L21 size (KiB) from which the sweeps split a front into a
+ *                   pivot item and update-row chunks (default 128);
+ *   FDFD_PIVOT_TAU  static pivot threshold relative to the matrix norm;
+ *   FDFD_TRACE      file for per-task timestamps (written by fdfd_query).
  */
 fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out);
 
