@@ -2139,6 +2139,7 @@ template <typename R>
 __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f, typename Cx<R>::T* V, int ldv) {
   typedef typename Cx<R>::T C;
   constexpr int WB = kWaveBatch<R>;
+  constexpr int WB1 = 2 * WB;  // the merged pass: twice the batch
   const int lane = threadIdx.x & 63;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
@@ -2187,16 +2188,16 @@ __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
       C v0 = lane < m ? Vc[lane] : czero<C>();
       C v1 = two && r1 < m ? Vc[r1] : czero<C>();
 #pragma unroll 1
-      for (int j0 = 0; j0 < p; j0 += WB) {
-        C e0[WB], e1[WB];
+      for (int j0 = 0; j0 < p; j0 += WB1) {
+        C e0[WB1], e1[WB1];
 #pragma unroll
-        for (int t = 0; t < WB; ++t) {
+        for (int t = 0; t < WB1; ++t) {
           const int j = j0 + t;
           e0[t] = j < p && j < lane && lane < m ? L[(int64_t)j * m + lane] : czero<C>();
           e1[t] = two && j < p && r1 < m ? L[(int64_t)j * m + r1] : czero<C>();
         }
 #pragma unroll
-        for (int t = 0; t < WB; ++t) {
+        for (int t = 0; t < WB1; ++t) {
           const int j = j0 + t;
           if (j < p) {
             const C zj = bcast_c(v0, j);
@@ -2260,7 +2261,7 @@ __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
 template <typename R>
 __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f, typename Cx<R>::T* X, int ldv) {
   typedef typename Cx<R>::T C;
-  constexpr int WB = kWaveBatch<R>;
+  constexpr int WB = 2 * kWaveBatch<R>;  // two waves per SIMD: twice the batch
   const int lane = threadIdx.x & 63;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   const int nrhs = w.nrhs;
@@ -2327,7 +2328,7 @@ __device__ __forceinline__ void publish_wave(const Queue& q, int ep, int64_t idx
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads, 3) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 2) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   sweep_status(w);
@@ -2356,7 +2357,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_sweep_waves(KArgs a, SweepA
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 2) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
