@@ -6,11 +6,20 @@ with the same factor (+ refinement) + gradient kernel.  Every step uses its own
 permittivity (the design block re-drawn from the seed), all resident in HBM
 before timing starts.
 
-Default workload: the 300 x 300 grid (N = 90,000, 20-cell PML, dx = 40 nm,
-lambda = 1.55 um, 100 x 100 design block), 20 timed iterations, complex128
-factors and complex64 factors + FP64 refinement.  The reported value is the
-fastest form whose fields and gradients stay within 1e-6 (relative) of the
-complex128 GPU solution, checked untimed on the same permittivity.
+Default workload: the 2000 x 2000 grid (N = 4,000,000, 40-cell PML, dx = 40 nm,
+lambda = 1.55 um, 1600 x 1600 design block).  Two forms are timed, each with
+FP64 iterative refinement to the same relative residual (1e-10) inside the
+timed region:
+  * c128 -- complex128 factors (one refinement step is needed at this size);
+  * c64  -- complex64 factors.
+The reported value is the fastest form that passes the untimed gate on the
+last permittivity: device status ok (or pivots perturbed), a final FP64
+relative residual <= 1e-10 for both solves, and fields and gradients within
+1e-6 (relative) of the complex128 form.
+
+--sweep runs the paper's footprint study instead (Sec. V): symbolic analysis,
+device set-up, numerical factorisation and back substitution per footprint,
+and the caching speedup of a cached iteration over one that caches nothing.
 """
 from __future__ import annotations
 
@@ -18,6 +27,7 @@ import argparse
 import json
 import os
 import platform
+import subprocess
 import sys
 import time
 
@@ -28,22 +38,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "design iterations/sec (refactor+fwd+adj solve) at rel err<=1e-6 vs FP64 GPU"
+GATE_RESIDUAL = 1e-10
+GATE_REL_ERR = 1e-6
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="plain300")
+    ap.add_argument("--config", default="large2000")
     ap.add_argument("--modes", default="c128,c64")
-    ap.add_argument("--graph", default="both", choices=["off", "on", "both"],
+    ap.add_argument("--graph", default="off", choices=["off", "on", "both"],
                     help="replay each call's launch chain from a HIP graph recorded by the library")
-    ap.add_argument("--max-ir", type=int, default=4)
-    ap.add_argument("--ir-tol", type=float, default=1e-10)
+    ap.add_argument("--max-ir-c128", type=int, default=2)
+    ap.add_argument("--max-ir-c64", type=int, default=16)
+    ap.add_argument("--ir-tol", type=float, default=GATE_RESIDUAL)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle worker processes (0: all host cores, <= 16)")
     ap.add_argument("--no-caching", action="store_true", help="skip the no-caching comparison")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
+    ap.add_argument("--sweep", action="store_true", help="run the footprint sweep (Sec. V) instead")
+    ap.add_argument("--sweep-sides", default="240,400,560,880,1200,1680,2160,2800,3480")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a plain device fill and copy of this many MiB, the reference "
@@ -59,6 +76,10 @@ def log(args, *a):
 PEAKS = {"hbm": 8000.0, "c128": 78.6, "c64": 157.3}   # GB/s; dense FP64 / FP32 TFLOP/s
 
 
+def form_ir(args, prec):
+    return (args.max_ir_c64 if prec == "c64" else args.max_ir_c128), args.ir_tol
+
+
 def run_mode(args, p, mode, eps_all, b, c, omegas, profile=False):
     """mode: "c128" or "c64", with "+graph" for library-recorded HIP graphs."""
     import torch
@@ -68,8 +89,7 @@ def run_mode(args, p, mode, eps_all, b, c, omegas, profile=False):
     graph = mode.endswith("+graph") and not profile
     plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=args.leaf, profile=profile,
                 graph=graph)
-    max_ir = args.max_ir if prec == "c64" else 0
-    tol = args.ir_tol
+    max_ir, tol = form_ir(args, prec)
     # the design loop writes each new permittivity into one buffer; every
     # vector the calls see keeps its address from step to step
     e_in = torch.empty_like(eps_all[0])
@@ -111,15 +131,38 @@ def run_mode(args, p, mode, eps_all, b, c, omegas, profile=False):
     return plan, step, ms, wall, info, grad
 
 
+def host_info():
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        nproc = os.cpu_count()
+    return {"lscpu_model": model or platform.processor() or platform.machine(), "nproc": nproc,
+            "os_cpu_count": os.cpu_count(), "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "the solver runs on one GPU; sharding over several GPUs is not "
                                    "implemented, so --gpus must be 1"}))
         sys.exit(2)
+    # the CPU baseline forks its worker processes before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.sweep:
+        cpu = cpu_baseline(args)
     import torch
+    if args.sweep:
+        print(json.dumps(footprint_sweep(args)))
+        return
     from paper_2307_05388_amd import problems as P
-    from paper_2307_05388_amd.fdfd import FDFD_GRAD_SUM_SYSTEMS
 
     dev = torch.device("cuda:0")
     if args.copy_mb > 0:
@@ -141,30 +184,44 @@ def main():
         modes = [m + s for m in modes for s in (("", "+graph") if args.graph == "both" else ("+graph",))]
 
     results = {}
-    for prec in modes:
-        plan, step, ms, wall, info, grad = run_mode(args, p, prec, eps_all, b, c, omegas)
+    for mode in modes:
+        plan, step, ms, wall, info, grad = run_mode(args, p, mode, eps_all, b, c, omegas)
         # untimed accuracy check on the last permittivity
         x = step(T - 1)
         g = grad.clone()
         torch.cuda.synchronize()
-        results[prec] = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / args.steps,
-                         "it_per_s": 1e3 / ms, "x": x.clone(), "grad": g, "info": plan.query()}
+        max_ir, tol = form_ir(args, mode.split("+")[0])
+        results[mode] = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / args.steps,
+                         "it_per_s": 1e3 / ms, "x": x.clone(), "grad": g, "info": plan.query(),
+                         "max_ir": max_ir, "ir_tol": tol}
         plan.close()
 
     ref = results.get("c128", results.get("c128+graph"))
-    acc = {}
-    for prec, r in results.items():
-        if ref is None or r is ref:
-            continue
-        ex = (torch.linalg.vector_norm(r["x"] - ref["x"]) / torch.linalg.vector_norm(ref["x"])).item()
-        eg = (torch.linalg.vector_norm(r["grad"] - ref["grad"]) / torch.linalg.vector_norm(ref["grad"])).item()
-        acc[prec] = {"rel_field_err_vs_c128": ex, "rel_grad_err_vs_c128": eg}
-
-    ok = {m: True for m in results}
-    for m, a in acc.items():
-        ok[m] = a["rel_field_err_vs_c128"] <= 1e-6 and a["rel_grad_err_vs_c128"] <= 1e-6
-    best = max((m for m in results if ok[m]), key=lambda m: results[m]["it_per_s"])
+    gate = {}
+    for mode, r in results.items():
+        inf = r["info"]
+        g = {"status": inf["status_str"],
+             "status_ok": inf["status_str"] in ("ok", "pivots perturbed"),
+             "rel_residual_fwd": inf["rel_residual_solve"], "rel_residual_adj": inf["rel_residual_adjoint"]}
+        g["residual_ok"] = (0 <= inf["rel_residual_solve"] <= GATE_RESIDUAL
+                            and 0 <= inf["rel_residual_adjoint"] <= GATE_RESIDUAL)
+        if ref is not None and r is not ref:
+            g["rel_field_err_vs_c128"] = (torch.linalg.vector_norm(r["x"] - ref["x"])
+                                          / torch.linalg.vector_norm(ref["x"])).item()
+            g["rel_grad_err_vs_c128"] = (torch.linalg.vector_norm(r["grad"] - ref["grad"])
+                                         / torch.linalg.vector_norm(ref["grad"])).item()
+            g["agree_ok"] = g["rel_field_err_vs_c128"] <= GATE_REL_ERR and g["rel_grad_err_vs_c128"] <= GATE_REL_ERR
+        else:
+            g["agree_ok"] = True
+        g["pass"] = g["status_ok"] and g["residual_ok"] and g["agree_ok"]
+        gate[mode] = g
+    passing = [m for m in results if gate[m]["pass"]]
+    if not passing:
+        print(json.dumps({"error": "no form passed the accuracy gate", "gate": gate}))
+        sys.exit(3)
+    best = max(passing, key=lambda m: results[m]["it_per_s"])
     rb = results[best]
+    prec_best = best.split("+")[0]
 
     out = {
         "metric": METRIC,
@@ -177,36 +234,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+f64-refinement" if best.startswith("c64") else "c128",
+        "dtype": "c64+f64-refinement" if prec_best == "c64" else "c128+f64-refinement",
         "data": "synthetic",
         "config": {"workload": f"{p.name}: {p.description}", "nx": p.nx, "ny": p.ny,
                    "npml": p.npml, "nsys": p.nsys, "nrhs": p.nrhs, "iterations": args.steps,
-                   "form": best, "graph": best.endswith("+graph"), "max_ir": args.max_ir,
-                   "ir_tol": args.ir_tol},
+                   "form": best, "graph": best.endswith("+graph"), "max_ir": rb["max_ir"],
+                   "ir_tol": rb["ir_tol"]},
         "modes": {m: {"it_per_s": r["it_per_s"], "ms_per_step": r["ms_per_step"],
-                      "wall_ms_per_step": r["wall_ms_per_step"],
+                      "wall_ms_per_step": r["wall_ms_per_step"], "max_ir": r["max_ir"], "ir_tol": r["ir_tol"],
                       "ir_steps_fwd": r["info"]["ir_steps_solve"], "ir_steps_adj": r["info"]["ir_steps_adjoint"],
-                      "rel_residual_fwd": r["info"]["rel_residual_solve"],
-                      "rel_residual_adj": r["info"]["rel_residual_adjoint"],
-                      "n_perturbed": r["info"]["n_perturbed"], **acc.get(m, {})}
+                      "n_perturbed": r["info"]["n_perturbed"], "gate": gate[m]}
                   for m, r in results.items()},
-        "analysis": {k: results[best]["info"][k] for k in ("nfronts", "nlevels", "nnz_factor", "refactor_flops",
-                                                          "factor_bytes", "leaf", "small_levels")},
+        "analysis": {k: rb["info"][k] for k in ("nfronts", "nlevels", "nnz_factor", "refactor_flops",
+                                                "factor_bytes", "leaf", "small_levels")},
     }
     if not args.no_caching:
-        out["caching"] = caching_speedup(args, p, best, eps_all, b, c, omegas, rb["ms_per_step"])
-    # roofline of the dominant kernel, from an event-timed pass of the same steps
-    prof_plan, _, prof_ms, _, prof_info, _ = run_mode(args, p, best, eps_all, b, c, omegas, profile=True)
-    prof_plan.close()
-    from paper_2307_05388_amd.rocprof_summary import read_traffic
-    traffic = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{p.name}_{best.split('+')[0]}.md"))
-    out["roofline"] = roofline(prof_info["kernels"], best.split("+")[0], args.steps, traffic)
-    out["kernels"] = {k: {"launches": v["launches"], "ms_per_step": v["total_ms"] / args.steps,
-                          "avg_us": 1e3 * v["total_ms"] / max(1, v["launches"])}
-                      for k, v in prof_info["kernels"].items() if v["launches"]}
-    out["profiled_ms_per_step"] = prof_ms
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        out["caching"] = caching_split(args, p, best, eps_all, b, c, omegas, rb["ms_per_step"])
+    if not args.no_profile:
+        # roofline of the dominant kernel, from an event-timed pass of the same steps
+        prof_plan, _, prof_ms, _, prof_info, _ = run_mode(args, p, best, eps_all, b, c, omegas, profile=True)
+        prof_plan.close()
+        from paper_2307_05388_amd.rocprof_summary import read_traffic
+        traffic = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{p.name}_{prec_best}.md"))
+        out["roofline"] = roofline(prof_info["kernels"], prec_best, args.steps, traffic)
+        out["kernels"] = {k: {"launches": v["launches"], "ms_per_step": v["total_ms"] / args.steps,
+                              "avg_us": 1e3 * v["total_ms"] / max(1, v["launches"])}
+                          for k, v in prof_info["kernels"].items() if v["launches"]}
+        out["profiled_ms_per_step"] = prof_ms
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
@@ -241,63 +297,130 @@ PAPER_CONTEXT = {
     "hardware": "2.4 GHz Intel Xeon Gold, 8 cores, Intel oneMKL PARDISO (precision not stated)",
     "duplexer_10wl": {"no_cache_s": 833, "cached_s": 179, "speedup": 4.7, "iterations": 164},
     "mode_mux_6wl_3modes": {"no_cache_s": 6076, "cached_s": 712, "speedup": 8.5, "iterations": 333},
-    "footprint_sweep_max_speedup": 9.2,
+    "footprint_sweep": {"duplexer": "above 4.7x below 10x10 um, about 3.1x at 85x85 um",
+                        "mux": "9.2x at small footprints, 7.3x at 85x85 um"},
 }
 
 
-def caching_speedup(args, p, mode, eps_all, b, c, omegas, cached_ms, reps=3):
-    """The paper's comparison on this GPU: an iteration that caches nothing
-    (for the forward and for the adjoint solve alike: symbolic analysis, device
-    set-up, numeric factorisation, solve) against the cached iteration measured
-    above.  Wall-clock, synchronised, median of reps."""
+def phase_times(p, prec, max_ir, tol, eps, b, c, omegas, leaf=0, reps=3):
+    """Median wall-clock milliseconds of the paper's phases on this GPU, each
+    synchronised: SF (symbolic analysis, host), device set-up (arena
+    allocation, table upload), NF (numerical factorisation) and BS (forward
+    solve, objective and adjoint solve with gradient, refinement included)."""
     import torch
     from paper_2307_05388_amd.fdfd import Plan, FDFD_GRAD_SUM_SYSTEMS
-    prec = mode.split("+")[0]
-    max_ir = args.max_ir if prec == "c64" else 0
-    kw = dict(nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=args.leaf)
+    kw = dict(nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=leaf)
     cc = c.conj()
-    sf, nocache = [], []
+    sf, full, nf, bs = [], [], [], []
     for r in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = Plan(p.nx, p.ny, p.npml, host_only=True, **kw)
         sf.append(time.perf_counter() - t0)
         h.close()
-        eps = eps_all[r % len(eps_all)]
         t0 = time.perf_counter()
         plan = Plan(p.nx, p.ny, p.npml, **kw)
-        plan.refactor(eps, omegas)
-        x = plan.solve(b, max_ir=max_ir, tol=args.ir_tol)
-        ov = torch.matmul(x, cc)
-        g = (cc[None, None, :] * ov.conj()[..., None]).contiguous()
         torch.cuda.synchronize()
+        full.append(time.perf_counter() - t0)
+        for rep in range(2):   # the first refactor of a fresh plan is not timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.refactor(eps, omegas)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x = plan.solve(b, max_ir=max_ir, tol=tol)
+            ov = torch.matmul(x, cc)
+            g = (cc[None, None, :] * ov.conj()[..., None]).contiguous()
+            plan.adjoint_grad(x, g, flags=FDFD_GRAD_SUM_SYSTEMS, max_ir=max_ir, tol=tol)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        nf.append(t1 - t0)
+        bs.append(t2 - t1)
         plan.close()
-        plan = Plan(p.nx, p.ny, p.npml, **kw)
-        plan.refactor(eps, omegas)
-        plan.adjoint_grad(x, g, flags=FDFD_GRAD_SUM_SYSTEMS, max_ir=max_ir, tol=args.ir_tol)
-        torch.cuda.synchronize()
-        plan.close()
-        nocache.append(time.perf_counter() - t0)
-    t_nc = 1e3 * float(np.median(nocache))
-    return {"symbolic_analysis_ms": 1e3 * float(np.median(sf)), "no_cache_ms_per_iter": t_nc,
-            "cached_ms_per_iter": cached_ms, "speedup": t_nc / cached_ms, "paper": PAPER_CONTEXT}
+    med = lambda v: 1e3 * float(np.median(v))
+    return {"sf_ms": med(sf), "setup_ms": med(full) - med(sf), "nf_ms": med(nf), "bs_ms": med(bs)}
 
 
-def cpu_baseline(p):
-    """The CPU oracle (plain-C banded LU, complex128, 1 thread) timed on one
-    full design iteration of the same workload: factor + forward + adjoint."""
+def caching_split(args, p, mode, eps_all, b, c, omegas, cached_ms):
+    """The paper's comparison (Sec. II, Sec. V) on this GPU.  Without caching,
+    the forward and the adjoint solve each redo the symbolic and the numerical
+    factorisation (2 SF + 2 NF + the solves); with caching an iteration is one
+    NF plus the solves.  Device arena set-up is a GPU cost the paper's SF does
+    not have: it is reported, and the speedup is given with and without it."""
+    prec = mode.split("+")[0]
+    max_ir, tol = form_ir(args, prec)
+    ph = phase_times(p, prec, max_ir, tol, eps_all[0], b, c, omegas, leaf=args.leaf)
+    no_cache = 2 * ph["sf_ms"] + 2 * ph["nf_ms"] + ph["bs_ms"]
+    no_cache_setup = no_cache + 2 * ph["setup_ms"]
+    return {**ph, "no_cache_ms_per_iter": no_cache, "no_cache_with_setup_ms_per_iter": no_cache_setup,
+            "cached_ms_per_iter": cached_ms, "speedup": no_cache / cached_ms,
+            "speedup_with_setup": no_cache_setup / cached_ms, "paper": PAPER_CONTEXT}
+
+
+def footprint_sweep(args):
+    """Sec. V: square footprints at 25 nm (1 um margins included in the side),
+    each timed phase by phase, then the caching speedup per footprint."""
+    import torch
+    from paper_2307_05388_amd import problems as P
+    dev = torch.device("cuda:0")
+    rows = []
+    for side in [int(s) for s in args.sweep_sides.split(",") if s.strip()]:
+        p = P.footprint_problem(side)
+        om = P.omegas(p)
+        eps = torch.from_numpy(P.design_eps(p, 0)).to(dev)
+        b = torch.from_numpy(P.sources(p)).to(dev)
+        c = torch.from_numpy(P.objective_vector(p)).to(dev)
+        row = {"side_cells": side, "footprint_um": side * p.dx_nm / 1000.0, "N": p.N}
+        for prec in [m.strip() for m in args.modes.split(",") if m.strip()]:
+            max_ir, tol = form_ir(args, prec)
+            ph = phase_times(p, prec, max_ir, tol, eps, b, c, om, reps=2)
+            cached = ph["nf_ms"] + ph["bs_ms"]
+            no_cache = 2 * ph["sf_ms"] + 2 * ph["nf_ms"] + ph["bs_ms"]
+            row[prec] = {**ph, "cached_ms_per_iter": cached, "no_cache_ms_per_iter": no_cache,
+                         "speedup": no_cache / cached,
+                         "speedup_with_setup": (no_cache + 2 * ph["setup_ms"]) / cached}
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
+        del eps, b, c
+        torch.cuda.empty_cache()
+    return {"footprint_sweep": rows, "dx_nm": 25.0, "paper": PAPER_CONTEXT}
+
+
+def _oracle_worker(t):
+    """One full oracle design iteration of the 300 x 300 workload (design drawn
+    for iteration t): complex128 banded LU, forward and adjoint solves."""
     from oracle import fdfd_oracle as oracle
     from paper_2307_05388_amd import problems as P
-    eps = P.design_eps(p, 0)
+    p = P.make_problem("plain300")
+    eps = P.design_eps(p, t)
     b = P.sources(p)
     c = P.objective_vector(p)
     t0 = time.perf_counter()
     oracle.design_iteration(p.nx, p.ny, p.npml, P.omegas(p), eps, b, c=c)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "it/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 design iteration of {p.name} (factor + forward + adjoint + gradient, "
-                      f"complex128 banded LU, kl=ku={p.nx}), {dt:.1f} s",
-            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(args):
+    """The CPU oracle (plain-C banded LU, complex128) timed on the host cores:
+    one worker process per core, each running one full design iteration of the
+    300 x 300 workload (the banded oracle cannot hold the 2000 x 2000 system:
+    its band storage alone would be about 384 GB).  Throughput = iterations /
+    wall time over all workers."""
+    import multiprocessing as mp
+    hi = host_info()
+    n = args.cpu_workers or max(1, min(16, hi["nproc"] or 1))
+    from oracle import fdfd_oracle as oracle
+    oracle.build_oracle()
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(n) as pool:
+        per = pool.map(_oracle_worker, range(n))
+    wall = time.perf_counter() - t0
+    return {"value": n / wall, "unit": "it/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} design iterations of plain300 (300x300, N=90,000; factor + forward + adjoint + "
+                      f"gradient, complex128 banded LU, kl=ku=300), one per worker process in parallel, "
+                      f"{wall:.1f} s wall, {float(np.median(per)):.1f} s median per iteration",
+            "workload": "plain300", **hi}
 
 
 if __name__ == "__main__":

@@ -185,12 +185,20 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info);
  *   FDFD_TABLE_PERM    int32 [N]        elimination position -> grid index
  *   FDFD_TABLE_FRONTS  int32 [nfronts][4] (first position, pivots, update rows, parent)
  *   FDFD_TABLE_UPDATE  int32 [sum of update rows] update rows (positions), front by front
+ *   FDFD_TABLE_TASKS   int32 [ntasks][5] the tile task graph of one system, in
+ *                      claim order: (type, front, k, I, J) with type 0 assembly,
+ *                      1 pivot-block LDL^T, 2 panel solve, 3 update of a pivot-
+ *                      column tile by block k, 4 inverse completion, 5 fused
+ *                      chain step, 6 Schur-complement tile over the blocks
+ *                      [k & 0xffff, k >> 16); preceded by one int32 holding
+ *                      ntasks (so the table has 1 + 5 ntasks entries)
  * count is the capacity of out in int32 elements.  Returns FDFD_ERR_ARG if it
  * is too small.  Works for host-only plans.
  */
 #define FDFD_TABLE_PERM 0
 #define FDFD_TABLE_FRONTS 1
 #define FDFD_TABLE_UPDATE 2
+#define FDFD_TABLE_TASKS 3
 fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t count);
 
 /*

@@ -221,14 +221,16 @@ def gradient(omega, x, lam):
 # One design iteration
 # ----------------------------------------------------------------------------
 
-def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None):
+def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None, npml_y=None):
     """Factor once per system, solve forward for every RHS, solve the adjoint
     with the same factors, and form the permittivity gradient.
 
     eps: (ny, nx) or (nsys, ny, nx);  b: (nsys, nrhs, N);  c: (N,) objective
-    vector, or g: (nsys, nrhs, N) given adjoint sources.  Returns a dict with
+    vector, or g: (nsys, nrhs, N) given adjoint sources.  npml is the PML
+    width along x, npml_y along y (default: npml).  Returns a dict with
     x, lam (nsys, nrhs, N), F (nsys, nrhs) and grad (nsys, N) summed over RHS.
     """
+    npml_y = npml if npml_y is None else npml_y
     omegas = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
     nsys = omegas.size
     b = np.asarray(b, dtype=np.complex128).reshape(nsys, -1, nx * ny)
@@ -239,7 +241,7 @@ def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None):
     grad = np.zeros((nsys, nx * ny))
     for s in range(nsys):
         e = eps if eps.ndim == 2 else eps[s]
-        coef = operator_coefficients(nx, ny, npml, npml, omegas[s], e)
+        coef = operator_coefficients(nx, ny, npml, npml_y, omegas[s], e)
         lu = BandLU(band_matrix(coef))
         x[s] = lu.solve(b[s])
         if g is None:
@@ -252,9 +254,9 @@ def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None):
     return {"x": x, "lam": lam, "F": F, "grad": grad}
 
 
-def relative_residual(nx, ny, npml, omega, eps, x, b):
+def relative_residual(nx, ny, npml, omega, eps, x, b, npml_y=None):
     """||b - A x|| / ||b|| in float64 with the oracle's own operator."""
-    coef = operator_coefficients(nx, ny, npml, npml, omega, eps)
+    coef = operator_coefficients(nx, ny, npml, npml if npml_y is None else npml_y, omega, eps)
     r = np.asarray(b, dtype=np.complex128) - apply_operator(coef, np.asarray(x, dtype=np.complex128))
     return float(np.linalg.norm(r) / np.linalg.norm(b))
 

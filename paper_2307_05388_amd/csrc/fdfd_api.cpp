@@ -134,7 +134,13 @@ void free_all(Plan& P) {
 // Level schedule: the bottom levels whose panels fit the LDS budget run in the
 // one-workgroup-per-front kernel; every level above them runs in the tile task
 // graph, whose task list (topological: level, assembly, then block steps) is
-// built here.
+// built here.  Tiles of a front's pivot columns (J < nbk) are assembled, then
+// updated right-looking one pivot block at a time (UPD), so the pivot-block
+// chain can proceed; the tiles of its Schur complement (I >= J >= nbk) are
+// produced by SYRK tasks, each of which accumulates the products of a group
+// of syrk_group pivot blocks and read-modify-writes its tile once per group
+// (the first group also gathers the children's contributions, which is the
+// assembly of those tiles).
 void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std::vector<int32_t>& tile_base,
                     std::vector<int32_t>& is_tiled) {
   const fdfd::Analysis& A = P.an;
@@ -174,6 +180,7 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
   is_tiled.assign(A.nfronts, 0);
   P.ntiles = 0;
   P.tiled_flops = 0;
+  const int G = std::max(1, P.syrk_group);
   auto push = [&](int type, int f, int k, int I, int J) {
     tasks.push_back(type);
     tasks.push_back(f);
@@ -193,7 +200,7 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       P.tiled_flops += P.front_flops[f];
       kmax = std::max(kmax, nbk);
       for (int I = 0; I < R; ++I)
-        for (int J = 0; J <= I; ++J) push(0, f, 0, I, J);
+        for (int J = 0; J <= I && J < nbk; ++J) push(0, f, 0, I, J);
     }
     // Step k: DIAG(0) (k = 0 only); FUSED(k+1) = TRSM(k+1,k) + UPD(k+1,k+1,k) +
     // DIAG(k+1) while block k+1 is a pivot block; the other TRSM(I,k); the other
@@ -217,9 +224,20 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
         const int f = A.level_fronts[q];
         const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
         if (nbk <= k) continue;
-        for (int J = k + 1; J < R; ++J)
+        for (int J = k + 1; J < R && J < nbk; ++J)
           for (int I = J; I < R; ++I)
             if (!(I == k + 1 && J == k + 1 && k + 1 < nbk)) push(3, f, k, I, J);
+      }
+      // SYRK over the pivot blocks [k0, k + 1) once the group is complete
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int f = A.level_fronts[q];
+        const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
+        if (nbk <= k || R == nbk) continue;
+        const int k1 = k + 1;
+        if (k1 % G != 0 && k1 != nbk) continue;
+        const int k0 = ((k1 - 1) / G) * G;
+        for (int J = nbk; J < R; ++J)
+          for (int I = J; I < R; ++I) push(6, f, k0 | (k1 << 16), I, J);
       }
     }
     // INV(k) after the level's steps: the rest of each pivot block's inverse,
@@ -368,7 +386,16 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     P.factor_lbytes += P.front_lbytes[f];
   }
   P.profile = (desc->flags & FDFD_PROFILE) != 0;
+  // FDFD_SYRK_GROUP: pivot blocks per Schur-complement task (0 = all of them)
+  P.syrk_group = env_int("FDFD_SYRK_GROUP", fdfd::kSyrkGroup);
+  if (P.syrk_group <= 0) P.syrk_group = 1 << 20;
   if (P.host_only) {
+    // the schedule a device plan with the default LDS budgets would run
+    P.csize = P.is_c64 ? 8 : 16;
+    const size_t cap = desc->small_lds > 0 ? (size_t)desc->small_lds : desc->small_lds < 0 ? 0 : 65536;
+    std::vector<int32_t> tasks, tile_base, is_tiled;
+    build_schedule(P, cap, tasks, tile_base, is_tiled);
+    P.tile_tasks_host = tasks;
     *out = h;
     return FDFD_OK;
   }
@@ -774,6 +801,12 @@ fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t 
   if (which == FDFD_TABLE_UPDATE) {
     if (count < (int64_t)A.upd_idx.size()) return fail(&P, FDFD_ERR_ARG, "buffer too small");
     std::copy(A.upd_idx.begin(), A.upd_idx.end(), out);
+    return FDFD_OK;
+  }
+  if (which == FDFD_TABLE_TASKS) {
+    if (count < 1 + (int64_t)P.tile_tasks_host.size()) return fail(&P, FDFD_ERR_ARG, "buffer too small");
+    out[0] = (int32_t)(P.tile_tasks_host.size() / 5);
+    std::copy(P.tile_tasks_host.begin(), P.tile_tasks_host.end(), out + 1);
     return FDFD_OK;
   }
   return fail(&P, FDFD_ERR_ARG, "unknown table");

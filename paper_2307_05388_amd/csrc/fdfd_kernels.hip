@@ -317,6 +317,14 @@ __global__ void k_setup(KArgs a, Omegas om, int npml_x, int npml_y) {
       a.st->n_perturbed = 0;
       a.st->nonfinite = 0;
       a.st->spin_timeout = 0;
+      // the solves before this refactor used the previous factor: their
+      // refinement figures no longer describe the plan
+      a.st->ir_steps_solve = 0;
+      a.st->ir_steps_adj = 0;
+      a.st->rel_solve = -1.0;
+      a.st->rel_adj = -1.0;
+      a.st->ir_failed_solve = 0;
+      a.st->ir_failed_adj = 0;
     }
   }
 }
@@ -1019,7 +1027,7 @@ struct TileArgs {
   int32_t ntiles;
 };
 
-enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3, T_INV = 4, T_FUSED = 5 };
+enum { T_ASM = 0, T_DIAG = 1, T_TRSM = 2, T_UPD = 3, T_INV = 4, T_FUSED = 5, T_SYRK = 6 };
 
 struct Chunks {
   int p, u, m, nbk, nut;
@@ -1392,6 +1400,151 @@ __device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, in
     if (dst[t]) st_ag(dst[t], csub(v[t], As[(wave + 4 * t) * kBW + lane]));
 }
 
+// SYRK(I,J,[k0,k1)): a tile of the front's Schur complement (I >= J >= nbk),
+// T_IJ -= sum_{k0 <= k < k1} L_Ik D_k L_Jk^T, accumulated on the matrix cores
+// over the whole group of pivot blocks before the tile is touched.  Each
+// block's operands are loaded into registers while the previous block's
+// products run (software pipelining, one LDS buffer); the tile is then read
+// (or, for the first group, gathered from the children's update blocks: its
+// assembly) and written once.  The right-looking UPD form instead reads and
+// writes the tile, and pays a task's claim, waits and store drain, once per
+// pivot block.
+template <typename C>
+__device__ __forceinline__ void syrk_load(const C* L, int m, int kb, int kn, int r0, int nr, int c0, int nc,
+                                          C (&va)[16], C (&vb)[16], C& dv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int q = wave + 4 * t;
+    const C* col = L + (int64_t)(kb + min(q, kn - 1)) * m;
+    va[t] = (q < kn && lane < nr) ? ld_ag(col + r0 + lane) : czero<C>();
+    vb[t] = (q < kn && lane < nc) ? ld_ag(col + c0 + lane) : czero<C>();
+  }
+  dv = (int)threadIdx.x < kn ? ld_ag(L + (int64_t)(kb + threadIdx.x) * (m + 1)) : czero<C>();
+}
+
+// O[c][r] += sum_q A[q][r] d_q B[q][c] for LDS-resident 64 x 64 operands
+// (column major, leading dimension kBW) into the caller's accumulators: wave
+// w owns output rows 16w..16w+15 as four 16 x 16 blocks (the layout of
+// mfma_tile_abt); d_q scales the A operand as it is read.
+template <typename R, typename C>
+__device__ __forceinline__ void mfma_acc_adbt(const C* A, const C* B, const C* Dv, typename Mfma<R>::v4 (&re)[4],
+                                              typename Mfma<R>::v4 (&im)[4]) {
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = l & 15, kq = l >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < kBW; k0 += 4) {
+    const int q = k0 + kq;
+    const C av = cmul(A[q * kBW + 16 * wave + i], Dv[q]);
+    const R nai = -av.y;
+    C bv[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) bv[bj] = B[q * kBW + 16 * bj + i];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      re[bj] = Mfma<R>::op(bv[bj].x, av.x, re[bj]);
+      im[bj] = Mfma<R>::op(bv[bj].y, av.x, im[bj]);
+    }
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      re[bj] = Mfma<R>::op(bv[bj].y, nai, re[bj]);
+      im[bj] = Mfma<R>::op(bv[bj].x, av.y, im[bj]);
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void task_syrk(const KArgs& a, int s, int f, int k0, int k1, int I, int J,
+                                          unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  typedef typename Mfma<R>::v4 v4;
+  C* As = reinterpret_cast<C*>(smem);  // As[q][r] = L[r0 + r][kb + q]; at the end the products O[c][r]
+  C* Bs = As + kBW * kBW;              // Bs[q][c] = L[c0 + c][kb + q]
+  C* Ds = Bs + kBW * kBW;              // d of the block's pivots
+  const Chunks ch(a.npiv[f], a.nupd[f]);
+  const int m = ch.m, p = ch.p, u = ch.u;
+  const int r0 = ch.lo(I), nr = ch.hi(I) - r0, c0 = ch.lo(J), nc = ch.hi(J) - c0;
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v4 re[4], im[4];
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    re[bj] = v4{0, 0, 0, 0};
+    im[bj] = v4{0, 0, 0, 0};
+  }
+  C va[16], vb[16], dv;
+  syrk_load(L, m, k0 * kBW, min(kBW, p - k0 * kBW), r0, nr, c0, nc, va, vb, dv);
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();  // the previous block's products have read As, Bs, Ds
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      As[(wave + 4 * t) * kBW + lane] = va[t];
+      Bs[(wave + 4 * t) * kBW + lane] = vb[t];
+    }
+    if (threadIdx.x < kBW) Ds[threadIdx.x] = dv;
+    __syncthreads();
+    if (k + 1 < k1) syrk_load(L, m, (k + 1) * kBW, min(kBW, p - (k + 1) * kBW), r0, nr, c0, nc, va, vb, dv);
+    mfma_acc_adbt<R>(As, Bs, Ds, re, im);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      C v;
+      v.x = re[bj][r];
+      v.y = im[bj][r];
+      As[(16 * bj + Mfma<R>::row(lane, r)) * kBW + 16 * wave + (lane & 15)] = v;
+    }
+  __syncthreads();
+  C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
+  const int rl = r0 - p + lane;  // row of this lane in the update block
+  C v[16];
+  if (k0 == 0) {
+    // the tile's assembly: the children's update-block entries that land on it
+    // (the ordering of update rows keeps every child entry in its lower triangle)
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = czero<C>();
+    const int32_t* g = a.gmap + a.gmap_ptr[f];
+    const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k, g += m) {
+      const int chf = a.child_list[k];
+      const C* Uc = Ub + a.upd_off[chf];
+      const int nu = a.nupd[chf];
+      const int gr = lane < nr ? g[r0 + lane] : -1;
+      int gc[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int c = wv + 4 * t;
+        gc[t] = c < nc ? g[c0 + c] : -1;
+      }
+      C w[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int c = wv + 4 * t;
+        const bool ok = gr >= 0 && gc[t] >= 0 && r0 + lane >= c0 + c;
+        w[t] = ok ? ld_ag(Uc + (int64_t)gc[t] * nu + gr) : czero<C>();
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) v[t] = cadd(v[t], w[t]);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = wave + 4 * t;
+      const bool ok = c < nc && lane < nr && r0 + lane >= c0 + c;
+      v[t] = ok ? ld_ag(U + (int64_t)(c0 - p + c) * u + rl) : czero<C>();
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = wave + 4 * t;
+    if (c < nc && lane < nr && r0 + lane >= c0 + c)
+      st_ag(U + (int64_t)(c0 - p + c) * u + rl, csub(v[t], As[c * kBW + lane]));
+  }
+}
+
 // FUSED(k): the critical chain of one pivot step in one workgroup,
 // TRSM(k, k-1) -> UPD(k, k, k-1) -> DIAG(k), with the intermediate tiles kept
 // in LDS.  L_{k,k-1} = X D^-1 is written out (and its version published
@@ -1491,6 +1644,23 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
         if (tid == 0) wait_value(st + tile_id(k - 1, k - 1), k + 1, a.st);
         if (tid == 1) wait_value(st + tile_id(k, k - 1), k, a.st);
         if (tid == 2) wait_value(st + tile_id(k, k), k, a.st);
+      } else if (type == T_SYRK) {
+        // rows I and J of the panel final up to block k1 - 1 (their TRSM), the
+        // previous group's result, and for the first group the children
+        const int k0 = k & 0xffff, k1 = k >> 16;
+        if (tid == 0) wait_value(st + tile_id(I, k1 - 1), k1 + 1, a.st);
+        if (tid == 1) wait_value(st + tile_id(J, k1 - 1), k1 + 1, a.st);
+        if (tid == 2 && k0 > 0) wait_value(st + tile_id(I, J), k0, a.st);
+        if (k0 == 0 && tid >= 64) {
+          const int c = a.child_ptr[f] + tid - 64;
+          if (c < a.child_ptr[f + 1]) {
+            const int cf = a.child_list[c];
+            if (ta.is_tiled[cf]) {
+              const int nut = (a.nupd[cf] + kBW - 1) / kBW;
+              wait_at_least(ta.done + (int64_t)s * a.nfronts + cf, nut * (nut + 1) / 2, a.st);
+            }
+          }
+        }
       } else {
         if (tid == 0) wait_value(st + tile_id(I, k), k + 2, a.st);
         if (tid == 1) wait_value(st + tile_id(J, k), k + 2, a.st);
@@ -1518,6 +1688,10 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
       task_fused<R>(a, s, f, k, k == ch.nbk + ch.nut - 1 ? kDiagFull : kDiagPart, st, smem_raw);
       tile = tile_id(k, k);
       ver = k + 2;
+    } else if (type == T_SYRK) {
+      task_syrk<R>(a, s, f, k & 0xffff, k >> 16, I, J, smem_raw);
+      tile = tile_id(I, J);
+      ver = k >> 16;
     } else {
       task_upd<R>(a, s, f, k, I, J, smem_raw);
       tile = tile_id(I, J);
@@ -1527,7 +1701,8 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     __syncthreads();
     if (threadIdx.x == 0 && tile >= 0) {
       __hip_atomic_store(st + tile, ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (type == T_UPD && J >= ch.nbk && k == ch.nbk - 1)
+      // a front's update tile is final after its last Schur-complement group
+      if (type == T_SYRK && (k >> 16) == ch.nbk)
         __hip_atomic_fetch_add(ta.done + (int64_t)s * a.nfronts + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     trace_mark(q, t, 2);
@@ -2552,16 +2727,6 @@ __global__ __launch_bounds__(kThreads) void k_gradient_sum(KArgs a, const double
   }
 }
 
-__global__ void k_status_reset(DevStatus* st) {
-  st->ir_flag = 0;
-  st->ir_steps_solve = 0;
-  st->ir_steps_adj = 0;
-  st->rel_solve = -1.0;
-  st->rel_adj = -1.0;
-  st->ir_failed_solve = 0;
-  st->ir_failed_adj = 0;
-}
-
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -2911,9 +3076,5 @@ hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, in
   return hipGetLastError();
 }
 
-hipError_t launch_status_reset(Plan& P, hipStream_t st) {
-  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, st, P.status);
-  return hipGetLastError();
-}
 
 }  // namespace fdfd

@@ -84,6 +84,7 @@ struct Plan {
   double tiled_flops = 0;      // partial-LDL^T flops of the tiled fronts (one system)
   size_t solve_lds_max = 0;
   int32_t small_prefix = 0;    // leading levels run by one persistent small-front launch
+  int32_t syrk_group = 8;      // pivot blocks accumulated per Schur-complement tile task
   size_t small_lds_prefix = 0;
   int32_t n_cu = 256;
   size_t lds_limit = 65536;
@@ -161,6 +162,9 @@ constexpr int kEpochSlot = 32;
 constexpr int kChunkRows = 64;
 constexpr int64_t kSplitBytes = 128 << 10;
 constexpr size_t kCounterBytes = 256;
+// Pivot blocks whose products one Schur-complement tile task accumulates
+// before it writes the tile (FDFD_SYRK_GROUP overrides it at analysis).
+constexpr int kSyrkGroup = 8;
 
 // Kernel launchers (fdfd_kernels.hip).  Each returns hipSuccess or the first
 // launch error.
@@ -172,7 +176,6 @@ hipError_t launch_solve(Plan& P, int mode, const double2* rhs, double2* x_out, i
                         int32_t max_ir, double tol, hipStream_t st);
 hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, int32_t nrhs,
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st);
-hipError_t launch_status_reset(Plan& P, hipStream_t st);
 size_t solve_lds_bytes(const Plan& P, int nrhs);
 
 // Complex entries of LDS the tile-graph tasks need: the TRSM task's 64 x 64

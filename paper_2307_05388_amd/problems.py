@@ -128,6 +128,25 @@ def make_problem(name: str) -> Problem:
     raise ValueError(f"unknown problem {name!r}")
 
 
+def footprint_problem(side: int) -> Problem:
+    """One point of the footprint sweep (Sec. V): a square domain of side
+    cells at dx = 25 nm whose outer 1 um (40 cells) on each side is margin,
+    20 cells of it PML; the design block is the footprint inside the margins
+    (side - 80 cells, e.g. 240 cells = a 4 x 4 um footprint, 3480 = 85 x 85
+    um), with a 0.5 um silicon input and output guide centred in y through
+    the margins.  lambda = 1.55 um."""
+    if side < 100:
+        raise ValueError("side must be at least 100 cells")
+    margin, npml = 40, 20
+    r = _centred_rows(side, 20)
+    return Problem(f"footprint{side}", side, side, npml, 25.0, (1.55,),
+                   strips=((0, margin) + r, (side - margin, side) + r),
+                   design=(margin, side - margin, margin, side - margin),
+                   src_col=npml + 5, src_profiles=("gauss",), obj_col=side - npml - 6,
+                   width_cells=10.0, iterations=1,
+                   description=f"{side}x{side} at 25nm: {(side - 2 * margin) * 0.025:g} um footprint + 1 um margins")
+
+
 def custom_problem(nx: int, ny: int, npml: int, dx_nm: float = 50.0,
                    wavelengths_um=(1.55,), design=None, src_profiles=("line",),
                    name: str = "custom") -> Problem:

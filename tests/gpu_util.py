@@ -60,3 +60,30 @@ def rel(a, b):
 def say(*args):
     print(*args, flush=True)
     sys.stdout.flush()
+
+
+def entry_err(a, b, floor=1e-6):
+    """Largest per-entry error relative to the reference entry's own
+    magnitude, floored at floor * max|b|: unlike the 2-norm it also sees errors
+    confined to low-magnitude regions such as the PML."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = np.maximum(np.abs(b), floor * np.abs(b).max())
+    return float((np.abs(a - b) / scale).max())
+
+
+def leaf_first_pivot_cell(plan, nx, ny, npml):
+    """A grid cell (i, j) outside the PML that is the first pivot of a leaf
+    front (a front no other front names as parent), from the analysis tables."""
+    from paper_2307_05388_amd.fdfd import FDFD_TABLE_FRONTS, FDFD_TABLE_PERM
+    fr = plan.table(FDFD_TABLE_FRONTS).reshape(-1, 4)
+    perm = plan.table(FDFD_TABLE_PERM)
+    parents = set(int(v) for v in fr[:, 3] if v >= 0)
+    for f in range(fr.shape[0]):
+        if f in parents:
+            continue
+        n = int(perm[fr[f, 0]])
+        i, j = n % nx, n // nx
+        if npml <= i <= nx - npml - 1 and npml <= j <= ny - npml - 1:
+            return i, j
+    raise AssertionError("no leaf starts outside the PML")

@@ -8,13 +8,14 @@ captured buffer) and eager work between the replays:
   - the caller records refactor + solve + objective + adjoint/gradient into one
     torch CUDA graph.
 The kernels and launch shapes are the same in every form, so results must be
-bitwise equal.
+bitwise equal.  The first replay of each form is also compared with the CPU
+oracle, element by element.
 """
 import numpy as np
 import pytest
 
 from paper_2307_05388_amd import problems as P
-from gpu_util import say, torch_cuda
+from gpu_util import entry_err, rel, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +42,19 @@ def _iteration(plan, p, eps, b, cc, x, g, grad, max_ir, tol):
     plan.adjoint_grad(x, g, grad=grad, max_ir=max_ir, tol=tol)
 
 
+def _vs_oracle(oracle, p, eps_t, x, grad, prec):
+    eps = eps_t.cpu().numpy()
+    ref = oracle.design_iteration(p.nx, p.ny, p.npml, P.omegas(p), eps, P.sources(p), c=P.objective_vector(p))
+    xn, gn = x.cpu().numpy(), grad.cpu().numpy()
+    bar = 1e-10 if prec == "c128" else 1e-8
+    say(f"  vs oracle: x {rel(xn, ref['x']):.2e} entry {entry_err(xn, ref['x']):.2e} grad {rel(gn, ref['grad']):.2e}")
+    assert rel(xn, ref["x"]) < bar
+    assert entry_err(xn, ref["x"]) < 1e3 * bar
+    assert rel(gn, ref["grad"]) < 10 * bar
+
+
 @pytest.mark.parametrize("prec,max_ir,tol", CASES)
-def test_library_graph_replay_matches_plain_launches(prec, max_ir, tol):
+def test_library_graph_replay_matches_plain_launches(oracle, prec, max_ir, tol):
     torch = torch_cuda()
     from paper_2307_05388_amd.fdfd import Plan
     p, eps, b, c = _setup(torch)
@@ -65,12 +77,14 @@ def test_library_graph_replay_matches_plain_launches(prec, max_ir, tol):
             assert out["graph"][2][key] == out["plain"][2][key], key
         assert torch.equal(out["graph"][0], out["plain"][0]), f"x differs at step {t}"
         assert torch.equal(out["graph"][1], out["plain"][1]), f"gradient differs at step {t}"
+        if t == 1:
+            _vs_oracle(oracle, p, eps[t], out["graph"][0], out["graph"][1], prec)
     for plan in plans.values():
         plan.close()
 
 
 @pytest.mark.parametrize("prec,max_ir,tol", CASES)
-def test_caller_captured_design_iteration(prec, max_ir, tol):
+def test_caller_captured_design_iteration(oracle, prec, max_ir, tol):
     torch = torch_cuda()
     from paper_2307_05388_amd.fdfd import Plan
     p, eps, b, c = _setup(torch)
@@ -105,6 +119,8 @@ def test_caller_captured_design_iteration(prec, max_ir, tol):
         assert torch.equal(x, rx), f"x differs at replay {t}"
         assert torch.equal(grad, rgrad), f"gradient differs at replay {t}"
         say(f"  replay {t}: bitwise equal, ir steps {info['ir_steps_solve']}/{info['ir_steps_adjoint']}")
+        if t == 1:
+            _vs_oracle(oracle, p, eps[t], x, grad, prec)
     del graph
     ref_plan.close()
     cap_plan.close()

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from paper_2307_05388_amd import problems as P
-from gpu_util import gpu_iteration, make_plan, rel, say, torch_cuda
+from gpu_util import entry_err, gpu_iteration, make_plan, rel, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -188,3 +188,29 @@ def test_state_errors_on_device():
     with pytest.raises(FDFDError) as e:
         Plan(200, 200, 10, mem_cap_bytes=1 << 20)
     assert e.value.status == FDFD_ERR_NOMEM
+
+
+@pytest.mark.parametrize("group", ["1", "2", "0"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_schur_groups_forced(oracle, monkeypatch, group, prec):
+    """Every level in the tile graph, with the Schur-complement tiles
+    accumulated one, two or all pivot blocks per task (FDFD_SYRK_GROUP, read at
+    analysis): the grouping changes only the order of the sums."""
+    monkeypatch.setenv("FDFD_SYRK_GROUP", group)
+    say(f"case schur group {group} {prec} 150x131")
+    p = P.custom_problem(150, 131, 12, wavelengths_um=(1.52, 1.58), src_profiles=("gauss", "alt_gauss"))
+    eps = np.stack([P.design_eps(p, t=13), P.design_eps(p, t=14)])
+    b = P.sources(p)
+    c = P.objective_vector(p)
+    plan = make_plan(p, prec, small_lds=0)
+    ir = (10, 1e-12) if prec == "c64" else (0, 0.0)
+    out = gpu_iteration(plan, p, eps, b, c=c, max_ir=ir[0], tol=ir[1])
+    ref = _oracle(oracle, p, eps, b, c=c)
+    bar = 1e-10 if prec == "c128" else 1e-8
+    say(f"  x {rel(out['x'], ref['x']):.2e} entry {entry_err(out['x'], ref['x']):.2e} "
+        f"grad {rel(out['grad'], ref['grad']):.2e}", out["info"]["status_str"])
+    assert out["info"]["status"] in (0, 6)
+    assert rel(out["x"], ref["x"]) < bar and rel(out["lam"], ref["lam"]) < bar
+    assert entry_err(out["x"], ref["x"]) < 1e3 * bar
+    assert rel(out["grad"], ref["grad"]) < 10 * bar
+    plan.close()

@@ -7,13 +7,13 @@ at analysis) against one that splits none, on the same factor layout (tile
 graph for every level) and inputs: the splits only reorder the sums of the
 update rows, so fields and gradients agree to rounding.  Two wavelengths x two
 source profiles exercise the per-system / per-RHS offsets of the hand-over
-buffers and chunk flags.
+buffers and chunk flags.  The split form is also compared with the CPU oracle.
 """
 import numpy as np
 import pytest
 
 from paper_2307_05388_amd import problems as P
-from gpu_util import say, torch_cuda
+from gpu_util import entry_err, rel, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +36,7 @@ def _run(monkeypatch, p, prec, split_kb, eps, b, c, max_ir, tol):
 
 
 @pytest.mark.parametrize("prec,max_ir,tol,rtol", [("c128", 0, 0.0, 1e-11), ("c64", 8, 1e-11, 1e-9)])
-def test_split_sweeps_match_unsplit(monkeypatch, prec, max_ir, tol, rtol):
+def test_split_sweeps_match_unsplit(oracle, monkeypatch, prec, max_ir, tol, rtol):
     torch = torch_cuda()
     p = P.custom_problem(150, 131, 12, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss"))
     dev = torch.device("cuda:0")
@@ -51,3 +51,10 @@ def test_split_sweeps_match_unsplit(monkeypatch, prec, max_ir, tol, rtol):
     eg = np.linalg.norm(gs - gu) / np.linalg.norm(gu)
     say(f"  rel diff x {ex:.2e} grad {eg:.2e}")
     assert ex < rtol and eg < rtol
+    ref = oracle.design_iteration(p.nx, p.ny, p.npml, P.omegas(p), eps.cpu().numpy(), P.sources(p),
+                                  c=P.objective_vector(p))
+    bar = 1e-10 if prec == "c128" else 1e-8
+    say(f"  split vs oracle: x {rel(xs, ref['x']):.2e} entry {entry_err(xs, ref['x']):.2e} "
+        f"grad {rel(gs, ref['grad']):.2e}")
+    assert rel(xs, ref["x"]) < bar and rel(gs, ref["grad"]) < 10 * bar
+    assert entry_err(xs, ref["x"]) < 1e3 * bar

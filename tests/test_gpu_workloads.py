@@ -58,7 +58,11 @@ def test_plain300_matches_oracle_both_precisions(oracle):
 def test_diff500_gradient_matches_central_differences(oracle):
     """500 x 500 with in/out guides: the autograd path (forward solve, adjoint
     with the cached factor, gradient kernel) against central differences of F
-    in float64 on 32 seeded design pixels; relative error over them <= 1e-4."""
+    on 32 seeded design pixels; relative error over them <= 1e-4.  The
+    gradient is taken in the workload's stated form, complex64 factors with
+    FP64 refinement (relative residual 1e-12), and in complex128; F+ and F-
+    are computed with complex128 factors refined in FP64, since their
+    difference cancels about eight digits at h = 1e-4."""
     torch = torch_cuda()
     from paper_2307_05388_amd.autograd import fdfd_fields, mode_overlap
     dev = torch.device("cuda:0")
@@ -69,27 +73,38 @@ def test_diff500_gradient_matches_central_differences(oracle):
     c = torch.from_numpy(P.objective_vector(p)).to(dev)
     i0, i1, j0, j1 = p.design
     vals = P.design_values(p, 0)
-    plan = make_plan(p, "c128")
-    eps_d = torch.from_numpy(vals).to(dev).requires_grad_(True)
-    x = fdfd_fields(eps_d, plan, base, p.design, om, b)
-    F = mode_overlap(x, c)
-    F.backward()
-    g_ad = eps_d.grad.cpu().numpy()
     eps_full = P.base_eps(p)
     eps_full[j0:j1, i0:i1] = vals
-    res = oracle.relative_residual(p.nx, p.ny, p.npml, om[0], eps_full, x.detach()[0, 0].cpu().numpy(),
-                                   P.sources(p)[0, 0])
-    assert res < 1e-10
+    grads = {}
+    for prec in ("c64", "c128"):
+        plan = make_plan(p, prec)
+        eps_d = torch.from_numpy(vals).to(dev).requires_grad_(True)
+        # complex64 plans refine in FP64 by default (at most 10 steps, 1e-12)
+        x = fdfd_fields(eps_d, plan, base, p.design, om, b)
+        F = mode_overlap(x, c)
+        F.backward()
+        grads[prec] = eps_d.grad.cpu().numpy()
+        info = plan.query()
+        res = oracle.relative_residual(p.nx, p.ny, p.npml, om[0], eps_full, x.detach()[0, 0].cpu().numpy(),
+                                       P.sources(p)[0, 0])
+        say(f"diff500 {prec}: residual {res:.2e}, refinement steps {info['ir_steps_solve']}/"
+            f"{info['ir_steps_adjoint']}", info["status_str"])
+        assert res < 1e-10
+        if prec == "c64":
+            assert info["ir_steps_solve"] >= 1 and info["ir_steps_adjoint"] >= 1
+        plan.close()
+
+    plan = make_plan(p, "c128")
 
     def F_at(v):
         e = base.clone()
         e[j0:j1, i0:i1] = torch.from_numpy(v).to(dev)
         plan.refactor(e, om)
-        return float(mode_overlap(plan.solve(b), c).item())
+        return float(mode_overlap(plan.solve(b, max_ir=2, tol=1e-14), c).item())
 
     h = 1e-4
     px = P.fd_pixels(p, 32)
-    g_fd, g_px = [], []
+    g_fd, g_px = [], {k: [] for k in grads}
     for n in px:
         j, i = divmod(int(n), p.nx)
         v = vals.copy()
@@ -98,11 +113,14 @@ def test_diff500_gradient_matches_central_differences(oracle):
         v[j - j0, i - i0] -= 2 * h
         fm = F_at(v)
         g_fd.append((fp - fm) / (2 * h))
-        g_px.append(g_ad[j - j0, i - i0])
-    g_fd, g_px = np.array(g_fd), np.array(g_px)
-    e = np.linalg.norm(g_px - g_fd) / np.linalg.norm(g_fd)
-    say(f"diff500: residual {res:.2e}, gradient vs central differences {e:.2e} over {len(px)} pixels")
-    assert e <= 1e-4
+        for k in grads:
+            g_px[k].append(grads[k][j - j0, i - i0])
+    g_fd = np.array(g_fd)
+    for k in grads:
+        e = np.linalg.norm(np.array(g_px[k]) - g_fd) / np.linalg.norm(g_fd)
+        say(f"diff500 {k}: gradient vs central differences {e:.2e} over {len(px)} pixels")
+        assert e <= 1e-4
+    assert rel(grads["c64"], grads["c128"]) < 1e-6
     plan.close()
 
 
@@ -154,23 +172,43 @@ def test_mux400_batched_wavelengths_and_sources(oracle):
 
 
 def test_large2000_full_size(oracle):
-    """2000 x 2000 (N = 4,000,000, 40-cell PML): complex128 factorisation and
-    both solves at full size, first unrefined, then with float64 refinement
-    (the <= 1e-10 residual bar); oracle residual and adjoint identity."""
+    """2000 x 2000 (N = 4,000,000, 40-cell PML) in the benchmark's launch
+    configuration.  complex128: unrefined, then refined in FP64 (the <= 1e-10
+    residual bar).  complex64 + FP64 refinement: the same bar, and fields and
+    gradients within 1e-6 of the refined complex128 ones.  Each form is run
+    with the benchmark's refinement tolerance (a device residual of 1e-10) and
+    with a tighter one.  complex64 needs several steps at this size: its
+    unpivoted LDL^T meets pivots down to about 1e-7 ||SA||, and the static
+    perturbation that keeps it stable slows the refinement (a smaller
+    threshold makes the refinement diverge).  Oracle residual
+    (the oracle's own operator, float64) and adjoint identity throughout."""
     p = P.make_problem("large2000")
     eps = P.design_eps(p)
     b = P.sources(p)
     c = P.objective_vector(p)
-    plan = make_plan(p, "c128")
-    for max_ir, tol, bar in ((0, 0.0, 1e-9), (2, 1e-12, 1e-10)):
-        out = gpu_iteration(plan, p, eps, b, c=c, max_ir=max_ir, tol=tol)
-        res = oracle.relative_residual(p.nx, p.ny, p.npml, P.omegas(p)[0], eps, out["x"][0, 0], b[0, 0])
-        adj = _adjoint_identity(out, b)
-        info = out["info"]
-        say(f"large2000 max_ir={max_ir}: residual {res:.2e}, adjoint identity {adj:.2e}, "
-            f"refinement steps {info['ir_steps_solve']}/{info['ir_steps_adjoint']}, fronts {info['nfronts']}, "
-            f"factor {info['factor_bytes'] / 2**30:.2f} GiB", info["status_str"])
-        assert res < bar
-        assert adj < 1e-10
-        assert np.all(np.isfinite(out["grad"]))
-    plan.close()
+    om = P.omegas(p)[0]
+    outs = {}
+    for prec, runs in (("c128", ((0, 0.0, 1e-9), (2, 1e-10, 1e-10), (2, 1e-12, 1e-10))),
+                       ("c64", ((20, 1e-10, 1e-10), (20, 1e-12, 1e-10)))):
+        plan = make_plan(p, prec)
+        for max_ir, tol, bar in runs:
+            say(f"case large2000 {prec} max_ir={max_ir} tol={tol}")
+            out = gpu_iteration(plan, p, eps, b, c=c, max_ir=max_ir, tol=tol)
+            res = oracle.relative_residual(p.nx, p.ny, p.npml, om, eps, out["x"][0, 0], b[0, 0])
+            adj = _adjoint_identity(out, b)
+            info = out["info"]
+            say(f"  residual {res:.2e} (device {info['rel_residual_solve']:.2e}/{info['rel_residual_adjoint']:.2e}),"
+                f" adjoint identity {adj:.2e}, refinement steps {info['ir_steps_solve']}/"
+                f"{info['ir_steps_adjoint']}, perturbed {info['n_perturbed']}, fronts {info['nfronts']}, "
+                f"factor {info['factor_bytes'] / 2**30:.2f} GiB", info["status_str"])
+            assert info["status"] in (0, 6)
+            assert res < bar
+            assert adj < 1e-10
+            assert np.all(np.isfinite(out["grad"]))
+            outs[(prec, max_ir, tol)] = out
+        plan.close()
+    ref = outs[("c128", 2, 1e-12)]
+    for key in (("c128", 2, 1e-10), ("c64", 20, 1e-10), ("c64", 20, 1e-12)):
+        ex, eg = rel(outs[key]["x"], ref["x"]), rel(outs[key]["grad"], ref["grad"])
+        say(f"large2000 {key} vs refined complex128: x {ex:.2e} grad {eg:.2e}")
+        assert ex < 1e-6 and eg < 1e-6
