@@ -154,6 +154,28 @@ fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t n
                        int32_t max_ir, double ir_tol, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory during the solve (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fdfd_solve with the same arguments, results and errors, whose
+ * work vectors (elimination-order and update vectors, split-front hand-over
+ * buffers, FP64 residual and partial norms, residual counter) live in one
+ * file-scope device array of FDFD_NOALLOC_SCRATCH_BYTES (64 MiB) instead of
+ * the plan's arenas.  It calls no hipMalloc, hipFree or other allocating
+ * routine (the plan, made earlier by fdfd_analyze, is an input); it starts
+ * with a fill kernel that clears the residual counter.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents: calls that
+ * overlap on one GPU (other streams, other plans, other threads) race, and the
+ * caller must serialise them.  Returns FDFD_ERR_ARG, enqueuing nothing, when
+ * nsys x nrhs columns of this plan need more than the array holds (about
+ * 64 bytes per cell and column in complex128, plus the update vectors: one
+ * column of a 500 x 500 grid fits, 2000 x 2000 does not), and FDFD_ERR_STATE
+ * for plans made with FDFD_PROFILE.
+ */
+#define FDFD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+fdfd_status fdfd_solve_noalloc(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t nrhs,
+                               int32_t max_ir, double ir_tol, void* hip_stream);
+
+/*
  * Adjoint solve A^T lam = g (Eq. 4 and Eq. 6) with the same cached factor
  * (S A is symmetric, so lam = S (SA)^-1 g needs no second factorisation),
  * then the gradient of Eq. (3): grad_n = -2 w_s^2 Re(lam_n x_n), summed over

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -53,6 +54,13 @@ struct fdfd_plan_s {
   fdfd::Plan p;
 };
 
+// Work vectors of fdfd_solve_noalloc: one file-scope device array, which every
+// GPU the library runs on holds (at its own address) until the process ends.
+// Host code must not use the array's name as a device address: its address
+// on each device comes from hipGetSymbolAddress (scratch_address below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 using fdfd::Plan;
@@ -78,6 +86,57 @@ fdfd_status fail(Plan* P, fdfd_status s, const std::string& msg) {
 
 fdfd_status hip_fail(Plan* P, hipError_t e, const char* what) {
   return fail(P, FDFD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device address of the scratch array on device dev (which must be current),
+// resolved once per device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Carves one solve's work vectors (nsys x nrhs columns) from base, each
+// region 256-byte aligned; returns the bytes used (base may be null to size).
+size_t carve_solve_work(const Plan& P, int nrhs, unsigned char* base, fdfd::SolveWork* w) {
+  const size_t cols = (size_t)P.desc.nsys * nrhs, cs = P.csize, N = (size_t)P.an.N;
+  const size_t sum_u = std::max<size_t>(1, (size_t)P.an.upd_ptr.back());
+  const size_t parts = std::max<size_t>(1, (size_t)P.part_total);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~size_t(255);
+    return base ? base + at : nullptr;
+  };
+  unsigned char* y = take(cols * N * cs);
+  unsigned char* wv = take(cols * sum_u * cs);
+  unsigned char* zv = take(cols * N * cs);
+  unsigned char* pv = take(cols * parts * cs);
+  unsigned char* res = take(cols * N * 16);
+  unsigned char* partial = take(cols * (size_t)P.res_blocks * 16);
+  unsigned char* counter = take(sizeof(int32_t));
+  if (w) {
+    w->y = y;
+    w->wv = wv;
+    w->zv = zv;
+    w->pv = pv;
+    w->res = reinterpret_cast<double2*>(res);
+    w->partial = reinterpret_cast<double*>(partial);
+    w->res_counter = reinterpret_cast<int32_t*>(counter);
+    w->clear_counter = true;
+  }
+  return off;
 }
 
 int env_int(const char* name, int dflt) {
@@ -412,6 +471,15 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   }
   P.device = dev;
   DeviceGuard guard(dev);
+  {
+    // the allocation-free solve's work array: its address on this device
+    void* sp = nullptr;
+    const hipError_t e = scratch_address(dev, &sp);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(nullptr, FDFD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+  }
   int lds_limit = 65536;
   (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   int ncu = 0;
@@ -649,6 +717,35 @@ fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t n
         return fdfd::launch_solve(P, 0, (const double2*)b_dev, (double2*)x_dev, nrhs, max_ir, ir_tol, s);
       });
   if (r != FDFD_OK) return r;
+  P.last_stream = st;
+  return FDFD_OK;
+}
+
+fdfd_status fdfd_solve_noalloc(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t nrhs, int32_t max_ir,
+                               double ir_tol, void* hip_stream) {
+  if (!plan) return fail(nullptr, FDFD_ERR_ARG, "plan is NULL");
+  Plan& P = plan->p;
+  if (P.host_only) return fail(&P, FDFD_ERR_STATE, "host-only plan cannot solve");
+  if (!P.factored) return fail(&P, FDFD_ERR_STATE, "solve before refactor");
+  if (P.profile) return fail(&P, FDFD_ERR_STATE, "fdfd_solve_noalloc does not run on FDFD_PROFILE plans");
+  if (!b_dev || !x_dev) return fail(&P, FDFD_ERR_ARG, "b_dev and x_dev must be non-NULL");
+  if (nrhs < 1 || nrhs > P.desc.max_rhs) return fail(&P, FDFD_ERR_ARG, "nrhs must be in [1, max_rhs]");
+  if (max_ir < 0 || max_ir > 100) return fail(&P, FDFD_ERR_ARG, "max_ir must be in [0, 100]");
+  if (!(ir_tol > 0.0)) ir_tol = 1e-12;
+  const size_t need = carve_solve_work(P, nrhs, nullptr, nullptr);
+  if (need > kScratchBytes)
+    return fail(&P, FDFD_ERR_ARG,
+                "fdfd_solve_noalloc needs " + std::to_string(need) + " bytes of work space for this plan and nrhs; "
+                "the limit is " + std::to_string(kScratchBytes) + " (use fdfd_solve)");
+  DeviceGuard guard(P.device);
+  void* base = nullptr;
+  hipError_t e = scratch_address(P.device, &base);
+  if (e != hipSuccess) return hip_fail(&P, e, "hipGetSymbolAddress(scratch)");
+  fdfd::SolveWork w;
+  carve_solve_work(P, nrhs, static_cast<unsigned char*>(base), &w);
+  hipStream_t st = (hipStream_t)hip_stream;
+  e = fdfd::launch_solve(P, 0, (const double2*)b_dev, (double2*)x_dev, nrhs, max_ir, ir_tol, st, &w);
+  if (e != hipSuccess) return hip_fail(&P, e, "solve launch");
   P.last_stream = st;
   return FDFD_OK;
 }

@@ -2895,15 +2895,15 @@ unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems, in
 // bottom P.wave_levels levels run in the wave-item kernels (forward first,
 // backward last), the levels above in the workgroup-per-front kernels.
 template <typename R>
-void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
+void sweep(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
            int accumulate, const int* flag, hipStream_t st, int status_mode = -1) {
   const int nsys = P.desc.nsys;
   const size_t lds = sweep_lds(P, nrhs), wlds = sweep_wave_lds(P, nrhs);
   SweepArgs w;
   w.src = src;
   w.out = dst;
-  w.y = P.y;
-  w.wv = P.wv;
+  w.y = wk.y;
+  w.wv = wk.wv;
   w.flag = flag;
   w.nrhs = nrhs;
   w.scale_src = scale_in;
@@ -2914,10 +2914,10 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   w.items = P.t.fwd_items;
   w.nch = P.t.nch;
   w.chunk_base = P.t.chunk_base;
-  w.zv = P.zv;
+  w.zv = wk.zv;
   w.nchunk = P.nchunk;
   w.part_base = P.t.part_base;
-  w.pv = P.pv;
+  w.pv = wk.pv;
   w.part_total = P.part_total;
   const int32_t* lf = P.t.level_fronts;
   const int nlev = (int)P.levels.size();
@@ -2980,27 +2980,45 @@ void sweep(Plan& P, const KArgs& a, const double2* src, double2* dst, int nrhs, 
   }
 }
 
+__global__ void k_clear_i32(int32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 template <typename R>
 hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int nrhs, int max_ir,
-                      double tol, hipStream_t st) {
+                      double tol, hipStream_t st, const SolveWork* work) {
   const KArgs a = make_args(P);
+  SolveWork wk;
+  if (work) {
+    wk = *work;
+  } else {
+    wk.y = P.y;
+    wk.wv = P.wv;
+    wk.zv = P.zv;
+    wk.pv = P.pv;
+    wk.res = P.res;
+    wk.partial = P.partial;
+    wk.res_counter = P.counters + 2;
+  }
+  // a fill kernel rather than a memset, so a caller may capture the call
+  if (wk.clear_counter) hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, st, wk.res_counter, 1);
   const int ncols = P.desc.nsys * nrhs;
   double2* xdst = mode == 0 ? x_out : P.xw;
   const int scale = mode == 0 ? 1 : 0;
   const int* flag = &P.status->ir_flag;
   if (max_ir <= 0) {
     // no refinement: the forward sweep records the solve's status itself
-    sweep<R>(P, a, rhs, xdst, nrhs, scale, 0, nullptr, st, mode);
+    sweep<R>(P, wk, a, rhs, xdst, nrhs, scale, 0, nullptr, st, mode);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_ir_begin, dim3(1), dim3(1), 0, st, P.status);
-  sweep<R>(P, a, rhs, xdst, nrhs, scale, 0, nullptr, st);
+  sweep<R>(P, wk, a, rhs, xdst, nrhs, scale, 0, nullptr, st);
   ResArgs ra;
   ra.rhs = rhs;
   ra.x = xdst;
-  ra.res = P.res;
-  ra.partial = P.partial;
-  ra.counter = P.counters + 2;
+  ra.res = wk.res;
+  ra.partial = wk.partial;
+  ra.counter = wk.res_counter;
   ra.flag = flag;
   ra.tol = tol;
   ra.nrhs = nrhs;
@@ -3014,7 +3032,7 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
       Prof pr(P, st, KC_RESIDUAL, rbytes, 0.0);
       hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
     }
-    sweep<R>(P, a, P.res, xdst, nrhs, 0, 1, flag, st);
+    sweep<R>(P, wk, a, wk.res, xdst, nrhs, 0, 1, flag, st);
   }
   if (max_ir > 0) {
     ra.step = max_ir;
@@ -3056,9 +3074,9 @@ hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipSt
 }
 
 hipError_t launch_solve(Plan& P, int mode, const double2* rhs, double2* x_out, int32_t nrhs,
-                        int32_t max_ir, double tol, hipStream_t st) {
-  return P.is_c64 ? solve_impl<float>(P, mode, rhs, x_out, nrhs, max_ir, tol, st)
-                  : solve_impl<double>(P, mode, rhs, x_out, nrhs, max_ir, tol, st);
+                        int32_t max_ir, double tol, hipStream_t st, const SolveWork* work) {
+  return P.is_c64 ? solve_impl<float>(P, mode, rhs, x_out, nrhs, max_ir, tol, st, work)
+                  : solve_impl<double>(P, mode, rhs, x_out, nrhs, max_ir, tol, st, work);
 }
 
 hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, int32_t nrhs,

@@ -166,6 +166,23 @@ constexpr size_t kCounterBytes = 256;
 // before it writes the tile (FDFD_SYRK_GROUP overrides it at analysis).
 constexpr int kSyrkGroup = 8;
 
+// Work vectors of one solve call: the elimination-order vector y, the update
+// vectors wv, the split fronts' hand-over buffers zv / pv, the FP64 residual,
+// the residual's per-block partial norms and its last-block counter (which
+// must be 0 when the call starts; the residual kernel leaves it at 0).  The
+// plan's arenas by default; fdfd_solve_noalloc carves them from a static
+// device array.
+struct SolveWork {
+  void* y = nullptr;
+  void* wv = nullptr;
+  void* zv = nullptr;
+  void* pv = nullptr;
+  double2* res = nullptr;
+  double* partial = nullptr;
+  int32_t* res_counter = nullptr;
+  bool clear_counter = false;  // zero res_counter (fill kernel) before the solve
+};
+
 // Kernel launchers (fdfd_kernels.hip).  Each returns hipSuccess or the first
 // launch error.
 hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st);
@@ -173,7 +190,7 @@ hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipSt
 // forward (rhs = S b, result into x_out, overwritten); mode 1: adjoint
 // (rhs = g, lam' into P.xw, then lam = S lam' into lam_out if not null).
 hipError_t launch_solve(Plan& P, int mode, const double2* rhs, double2* x_out, int32_t nrhs,
-                        int32_t max_ir, double tol, hipStream_t st);
+                        int32_t max_ir, double tol, hipStream_t st, const SolveWork* work = nullptr);
 hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, int32_t nrhs,
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st);
 size_t solve_lds_bytes(const Plan& P, int nrhs);

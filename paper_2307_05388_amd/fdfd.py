@@ -23,7 +23,7 @@ FDFD_GRAPH = 4
 FDFD_GRAD_ACCUMULATE, FDFD_GRAD_SUM_SYSTEMS = 1, 2
 FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE, FDFD_TABLE_TASKS = 0, 1, 2, 3
 
-EXPORTED = ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_adjoint_grad", "fdfd_query",
+EXPORTED = ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_solve_noalloc", "fdfd_adjoint_grad", "fdfd_query",
             "fdfd_kernel_stats", "fdfd_get_table", "fdfd_status_str", "fdfd_last_error", "fdfd_destroy"]
 
 
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdfd_analyze.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     lib.fdfd_refactor.argtypes = [vp, vp, i64, ctypes.POINTER(dbl), vp]
     lib.fdfd_solve.argtypes = [vp, vp, vp, i32, i32, dbl, vp]
+    lib.fdfd_solve_noalloc.argtypes = [vp, vp, vp, i32, i32, dbl, vp]
     lib.fdfd_adjoint_grad.argtypes = [vp, vp, vp, i32, i32, dbl, vp, vp, i32, vp]
     lib.fdfd_query.argtypes = [vp, ctypes.POINTER(Info)]
     lib.fdfd_get_table.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), i64]
@@ -91,7 +92,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdfd_last_error.restype = ctypes.c_char_p
     lib.fdfd_destroy.argtypes = [vp]
     lib.fdfd_destroy.restype = None
-    for name in ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_adjoint_grad",
+    for name in ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_solve_noalloc", "fdfd_adjoint_grad",
                  "fdfd_query", "fdfd_get_table", "fdfd_kernel_stats"]:
         getattr(lib, name).restype = i32
     _lib = lib
@@ -187,6 +188,17 @@ class Plan:
             x = torch.empty_like(b)
         self._check(self._lib.fdfd_solve(self._h, _ptr(b), _ptr(x), nrhs, max_ir, tol,
                                          _stream_handle(stream)))
+        return x
+
+    def solve_noalloc(self, b, x, max_ir=0, tol=0.0, stream=None):
+        """fdfd_solve_noalloc: the forward solve with its work vectors in the
+        library's static device array (x must be given; nothing is allocated)."""
+        import torch
+        assert b.is_cuda and b.dtype == torch.complex128 and b.is_contiguous()
+        assert x.shape == b.shape and x.dtype == b.dtype and x.is_contiguous()
+        nrhs = b.shape[-2] if b.dim() >= 2 else 1
+        self._check(self._lib.fdfd_solve_noalloc(self._h, _ptr(b), _ptr(x), nrhs, max_ir, tol,
+                                                 _stream_handle(stream)))
         return x
 
     def adjoint_grad(self, x, g, lam=None, grad=None, flags=0, max_ir=0, tol=0.0, stream=None):
