@@ -194,12 +194,13 @@ void free_all(Plan& P) {
 // one-workgroup-per-front kernel; every level above them runs in the tile task
 // graph, whose task list (topological: level, assembly, then block steps) is
 // built here.  Tiles of a front's pivot columns (J < nbk) are assembled, then
-// updated right-looking one pivot block at a time (UPD), so the pivot-block
-// chain can proceed; the tiles of its Schur complement (I >= J >= nbk) are
-// produced by SYRK tasks, each of which accumulates the products of a group
-// of syrk_group pivot blocks and read-modify-writes its tile once per group
-// (the first group also gathers the children's contributions, which is the
-// assembly of those tiles).
+// updated right-looking (UPD): one pivot block at a time in the rows of pivot
+// blocks, so the pivot-block chain can proceed, and syrk_group blocks at a
+// time in the update rows; the tiles of its Schur complement (I >= J >= nbk)
+// are produced by SYRK tasks, each of which accumulates the products of a
+// group of syrk_group pivot blocks and read-modify-writes its tile once per
+// group (the first group also gathers the children's contributions, which is
+// the assembly of those tiles).
 void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std::vector<int32_t>& tile_base,
                     std::vector<int32_t>& is_tiled) {
   const fdfd::Analysis& A = P.an;
@@ -283,9 +284,17 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
         const int f = A.level_fronts[q];
         const int nbk = (A.npiv[f] + T - 1) / T, R = nbk + (A.nupd[f] + T - 1) / T;
         if (nbk <= k) continue;
-        for (int J = k + 1; J < R && J < nbk; ++J)
-          for (int I = J; I < R; ++I)
-            if (!(I == k + 1 && J == k + 1 && k + 1 < nbk)) push(3, f, k, I, J);
+        const int k1 = k + 1;
+        for (int J = k1; J < nbk; ++J) {
+          // rows of pivot blocks: one block at a time (the chain waits on them)
+          for (int I = J; I < nbk; ++I)
+            if (!(I == k1 && J == k1)) push(3, f, k | (k1 << 16), I, J);
+          // update rows: a group of blocks at a time, the last group ending at J
+          if (k1 == J || k1 % G == 0) {
+            const int k0 = ((k1 - 1) / G) * G;
+            for (int I = nbk; I < R; ++I) push(3, f, k0 | (k1 << 16), I, J);
+          }
+        }
       }
       // SYRK over the pivot blocks [k0, k + 1) once the group is complete
       for (int q = L.first; q < L.first + L.count; ++q) {

@@ -1011,7 +1011,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, c
 //   ASM(I,J)     assemble tile (I,J): original entries + children's blocks
 //   DIAG(k)      LDL^T of pivot block k, inverse of its unit-lower part
 //   TRSM(k,I)    tile (I,k) <- F_Ik Xinv_k^T D_k^-1
-//   UPD(k,I,J)   tile (I,J) -= L_Ik D_k L_Jk^T       (k < J <= I)
+//   UPD(I,J,[k0,k1))  tile (I,J) -= sum_k L_Ik D_k L_Jk^T  (k0 <= k < k1 <= J, J < nbk)
+//   SYRK(I,J,[k0,k1)) the same for the Schur-complement tiles (I >= J >= nbk)
 // Each tile carries a version (1 after ASM, +1 per modification); a task
 // waits for the exact versions it reads and writes, and publishes the next.
 // A front's update tiles count their final versions in done[], which the
@@ -1083,6 +1084,12 @@ __device__ __forceinline__ void asm_stage(const KArgs& a, int s, int f, int J, u
   }
 }
 
+// ASM(I,J): the tile's original entries (pivot columns only, from the
+// stencils asm_stage placed in LDS) plus the children's update-block entries
+// that land on it.  Lane = row, wave w takes the columns w, w+4, ...; per
+// child one round of gather-index loads (the row's, and the sixteen columns'
+// which are the same across the wave) is followed by one round of all sixteen
+// value loads, so a tile costs two memory round trips per child.
 template <typename R>
 __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
@@ -1092,27 +1099,41 @@ __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, in
   const bool piv = c0 < ch.p;  // pivot chunks hold original entries
   C* sv = reinterpret_cast<C*>(smem);  // the pivot columns' stencils, staged by asm_stage
   int* nbv = reinterpret_cast<int*>(sv + 5 * kBW);
-  // lane = row, wave w takes the columns w, w+4, ...: four per batch
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = r0 + lane;
-#pragma unroll 1
-  for (int tb = 0; tb < 16; tb += 4) {
-    int rr[4], cc[4];
-    C v[4];
+  C v[16];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int t = wave + 4 * (tb + e), c = c0 + t;
-      const bool ok = lane < nr && t < nc && r >= c;
-      rr[e] = ok ? r : -1;
-      cc[e] = c;
-      v[e] = (ok && piv) ? staged_entry(sv, nbv, t, r, c) : czero<C>();
-    }
-    add_children<C, 4>(a, s, f, ch.m, rr, cc, v);
+  for (int t = 0; t < 16; ++t) {
+    const int tt = wave + 4 * t, c = c0 + tt;
+    const bool ok = lane < nr && tt < nc && r >= c;
+    v[t] = (ok && piv) ? staged_entry(sv, nbv, tt, r, c) : czero<C>();
+  }
+  const int32_t* g = a.gmap + a.gmap_ptr[f];
+  const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
+  for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k, g += ch.m) {
+    const int chf = a.child_list[k];
+    const C* Uc = Ub + a.upd_off[chf];
+    const int nu = a.nupd[chf];
+    const int gr = lane < nr ? g[r] : -1;
+    int gc[16];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int t = wave + 4 * (tb + e), c = c0 + t;
-      if (lane < nr && t < nc && (r >= c || piv)) st_ag(front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c), v[e]);
+    for (int t = 0; t < 16; ++t) {
+      const int tt = wave + 4 * t;
+      gc[t] = tt < nc ? g[c0 + tt] : -1;
     }
+    C w[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const bool ok = gr >= 0 && gc[t] >= 0 && r >= c0 + wave + 4 * t;
+      w[t] = ok ? ld_ag(Uc + (int64_t)gc[t] * nu + gr) : czero<C>();
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = cadd(v[t], w[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int tt = wave + 4 * t, c = c0 + tt;
+    if (lane < nr && tt < nc && (r >= c || piv)) st_ag(front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c), v[t]);
   }
 }
 
@@ -1369,46 +1390,22 @@ __device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O
   __syncthreads();
 }
 
-// UPD(I,J,k): tile (I,J) -= L_Ik D_k L_Jk^T.  L_Ik and L_Jk D_k are staged in
-// LDS, multiplied on the matrix cores, and the product is subtracted from the
-// tile with all of a thread's loads in flight together (coalesced columns).
-template <typename R>
-__device__ __forceinline__ void task_upd(const KArgs& a, int s, int f, int k, int I, int J, unsigned char* smem) {
-  typedef typename Cx<R>::T C;
-  C* As = reinterpret_cast<C*>(smem);  // As[q][r] = L[r0 + r][k0 + q]; then the product
-  C* Bs = As + kBW * kBW;              // Bs[q][c] = L[c0 + c][k0 + q] d_q
-  const Chunks ch(a.npiv[f], a.nupd[f]);
-  const int m = ch.m, k0 = k * kBW, nb = min(kBW, ch.p - k0);
-  const int r0 = ch.lo(I), nr = ch.hi(I) - r0, c0 = ch.lo(J), nc = ch.hi(J) - c0;
-  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)k0 * m;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  stage_block(As, L + r0, m, nr, nb, kAll);
-  stage_block(Bs, L + c0, m, nc, nb, kAll, L + k0, m + 1);
-  __syncthreads();
-  mfma_tile_abt<R>(As, Bs, As);
-  C* dst[16];
-  C v[16];
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int c = wave + 4 * t;
-    const bool ok = c < nc && lane < nr && r0 + lane >= c0 + c;
-    dst[t] = ok ? front_elem<C>(a, s, f, ch.p, ch.u, m, r0 + lane, c0 + c) : nullptr;
-    v[t] = ok ? ld_ag(dst[t]) : czero<C>();
-  }
-#pragma unroll
-  for (int t = 0; t < 16; ++t)
-    if (dst[t]) st_ag(dst[t], csub(v[t], As[(wave + 4 * t) * kBW + lane]));
-}
 
-// SYRK(I,J,[k0,k1)): a tile of the front's Schur complement (I >= J >= nbk),
-// T_IJ -= sum_{k0 <= k < k1} L_Ik D_k L_Jk^T, accumulated on the matrix cores
-// over the whole group of pivot blocks before the tile is touched.  Each
-// block's operands are loaded into registers while the previous block's
-// products run (software pipelining, one LDS buffer); the tile is then read
-// (or, for the first group, gathered from the children's update blocks: its
-// assembly) and written once.  The right-looking UPD form instead reads and
-// writes the tile, and pays a task's claim, waits and store drain, once per
-// pivot block.
+// Tile update over a group of pivot blocks:
+//   T_IJ -= sum_{k0 <= k < k1} L_Ik D_k L_Jk^T,
+// accumulated on the matrix cores over the whole group before the tile is
+// touched.  Each block's operands are loaded into registers while the
+// previous block's products run (software pipelining, one LDS buffer); the
+// tile is then read and written once.  Used by
+//   SYRK(I,J,[k0,k1))  tiles of the front's Schur complement (I >= J >= nbk);
+//                      the first group gathers the children's update-block
+//                      entries instead of reading the tile (its assembly);
+//   UPD(I,J,[k0,k1))   tiles of the pivot columns (J < nbk), assembled by ASM:
+//                      one block at a time for the rows of pivot blocks (the
+//                      chain of the front waits for them), a group at a time
+//                      for the update rows.
+// The one-block-per-task form instead reads and writes the tile, and pays a
+// task's claim, waits and store drain, once per pivot block.
 template <typename C>
 __device__ __forceinline__ void syrk_load(const C* L, int m, int kb, int kn, int r0, int nr, int c0, int nc,
                                           C (&va)[16], C (&vb)[16], C& dv) {
@@ -1426,20 +1423,33 @@ __device__ __forceinline__ void syrk_load(const C* L, int m, int kb, int kn, int
 // O[c][r] += sum_q A[q][r] d_q B[q][c] for LDS-resident 64 x 64 operands
 // (column major, leading dimension kBW) into the caller's accumulators: wave
 // w owns output rows 16w..16w+15 as four 16 x 16 blocks (the layout of
-// mfma_tile_abt); d_q scales the A operand as it is read.
+// mfma_tile_abt); d_q scales the A operand as it is read.  The LDS reads of
+// the next 4-deep step are issued before this step's products (one wave per
+// SIMD: a wait on LDS between the products would leave the matrix core idle).
 template <typename R, typename C>
 __device__ __forceinline__ void mfma_acc_adbt(const C* A, const C* B, const C* Dv, typename Mfma<R>::v4 (&re)[4],
                                               typename Mfma<R>::v4 (&im)[4]) {
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = l & 15, kq = l >> 4;
-#pragma unroll 4
+  C an = A[kq * kBW + 16 * wave + i], dn = Dv[kq];
+  C bn[4];
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) bn[bj] = B[kq * kBW + 16 * bj + i];
+#pragma unroll 2
   for (int k0 = 0; k0 < kBW; k0 += 4) {
-    const int q = k0 + kq;
-    const C av = cmul(A[q * kBW + 16 * wave + i], Dv[q]);
-    const R nai = -av.y;
+    const C a0 = an, d0 = dn;
     C bv[4];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) bv[bj] = B[q * kBW + 16 * bj + i];
+    for (int bj = 0; bj < 4; ++bj) bv[bj] = bn[bj];
+    if (k0 + 4 < kBW) {
+      const int q = k0 + 4 + kq;
+      an = A[q * kBW + 16 * wave + i];
+      dn = Dv[q];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) bn[bj] = B[q * kBW + 16 * bj + i];
+    }
+    const C av = cmul(a0, d0);
+    const R nai = -av.y;
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
       re[bj] = Mfma<R>::op(bv[bj].x, av.x, re[bj]);
@@ -1454,8 +1464,8 @@ __device__ __forceinline__ void mfma_acc_adbt(const C* A, const C* B, const C* D
 }
 
 template <typename R>
-__device__ __forceinline__ void task_syrk(const KArgs& a, int s, int f, int k0, int k1, int I, int J,
-                                          unsigned char* smem) {
+__device__ __forceinline__ void task_tile_update(const KArgs& a, int s, int f, int k0, int k1, int I, int J,
+                                                 unsigned char* smem) {
   typedef typename Cx<R>::T C;
   typedef typename Mfma<R>::v4 v4;
   C* As = reinterpret_cast<C*>(smem);  // As[q][r] = L[r0 + r][kb + q]; at the end the products O[c][r]
@@ -1497,10 +1507,15 @@ __device__ __forceinline__ void task_syrk(const KArgs& a, int s, int f, int k0, 
       As[(16 * bj + Mfma<R>::row(lane, r)) * kBW + 16 * wave + (lane & 15)] = v;
     }
   __syncthreads();
-  C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
-  const int rl = r0 - p + lane;  // row of this lane in the update block
   C v[16];
-  if (k0 == 0) {
+  C* dst[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int c = wave + 4 * t;
+    const bool ok = c < nc && lane < nr && r0 + lane >= c0 + c;
+    dst[t] = ok ? front_elem<C>(a, s, f, p, u, m, r0 + lane, c0 + c) : nullptr;
+  }
+  if (k0 == 0 && J >= ch.nbk) {
     // the tile's assembly: the children's update-block entries that land on it
     // (the ordering of update rows keeps every child entry in its lower triangle)
 #pragma unroll
@@ -1531,18 +1546,11 @@ __device__ __forceinline__ void task_syrk(const KArgs& a, int s, int f, int k0, 
     }
   } else {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int c = wave + 4 * t;
-      const bool ok = c < nc && lane < nr && r0 + lane >= c0 + c;
-      v[t] = ok ? ld_ag(U + (int64_t)(c0 - p + c) * u + rl) : czero<C>();
-    }
+    for (int t = 0; t < 16; ++t) v[t] = dst[t] ? ld_ag(dst[t]) : czero<C>();
   }
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int c = wave + 4 * t;
-    if (c < nc && lane < nr && r0 + lane >= c0 + c)
-      st_ag(U + (int64_t)(c0 - p + c) * u + rl, csub(v[t], As[c * kBW + lane]));
-  }
+  for (int t = 0; t < 16; ++t)
+    if (dst[t]) st_ag(dst[t], csub(v[t], As[(wave + 4 * t) * kBW + lane]));
 }
 
 // FUSED(k): the critical chain of one pivot step in one workgroup,
@@ -1662,9 +1670,12 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
           }
         }
       } else {
-        if (tid == 0) wait_value(st + tile_id(I, k), k + 2, a.st);
-        if (tid == 1) wait_value(st + tile_id(J, k), k + 2, a.st);
-        if (tid == 2) wait_value(st + tile_id(I, J), k + 1, a.st);
+        // UPD over the blocks [k0, k1): rows I and J final up to block k1 - 1,
+        // the tile updated by every block before k0
+        const int k0 = k & 0xffff, k1 = k >> 16;
+        if (tid == 0) wait_value(st + tile_id(I, k1 - 1), k1 + 1, a.st);
+        if (tid == 1) wait_value(st + tile_id(J, k1 - 1), k1 + 1, a.st);
+        if (tid == 2) wait_value(st + tile_id(I, J), k0 + 1, a.st);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
@@ -1689,13 +1700,13 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
       tile = tile_id(k, k);
       ver = k + 2;
     } else if (type == T_SYRK) {
-      task_syrk<R>(a, s, f, k & 0xffff, k >> 16, I, J, smem_raw);
+      task_tile_update<R>(a, s, f, k & 0xffff, k >> 16, I, J, smem_raw);
       tile = tile_id(I, J);
       ver = k >> 16;
     } else {
-      task_upd<R>(a, s, f, k, I, J, smem_raw);
+      task_tile_update<R>(a, s, f, k & 0xffff, k >> 16, I, J, smem_raw);
       tile = tile_id(I, J);
-      ver = k + 2;
+      ver = (k >> 16) + 1;
     }
     drain_stores();
     __syncthreads();

@@ -56,10 +56,11 @@ def replay(tasks, fronts):
             assert v(k, k) == k + 2 and v(I, k) == k + 1, where
             state[(f, I, k)] = k + 2
         elif ty == UPD:
-            assert J < nbk, where
-            assert v(I, k) == k + 2 and v(J, k) == k + 2 and v(I, J) == k + 1, where
-            state[(f, I, J)] = k + 2
-            applied[(f, I, J)].append(k)
+            k0, k1 = k & 0xFFFF, k >> 16
+            assert J < nbk and 0 <= k0 < k1 <= J <= I, where
+            assert v(I, k1 - 1) == k1 + 1 and v(J, k1 - 1) == k1 + 1 and v(I, J) == k0 + 1, where
+            state[(f, I, J)] = k1 + 1
+            applied[(f, I, J)].extend(range(k0, k1))
         elif ty == INV:
             for i in range(k + 1, R):
                 assert v(i, k) == k + 2, where
