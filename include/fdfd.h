@@ -243,6 +243,50 @@ typedef struct {
 fdfd_status fdfd_kernel_stats(fdfd_plan plan, fdfd_kernel_stat* out, int32_t max_entries,
                               int32_t* n_out);
 
+/*
+ * Design parametrisation (Sec. III, Sec. IV): the map from the optimiser's
+ * variables theta in [0, 1], one per design pixel, to the permittivity of the
+ * design block, and its backward pass.  Stateless; the work runs on the
+ * current HIP device, enqueued on hip_stream.
+ *   filter      rho_i = sum_j w(d_ij) theta_j / S_i,  S_i = sum_j w(d_ij),
+ *               with the conic weights w(d) = max(0, 1 - d / radius) of the
+ *               distance d (cells) between pixel centres, over the block only
+ *               (the paper's smoothing filter of 200 nm radius is radius =
+ *               200 nm / dx cells);
+ *   projection  P(x) = (tanh(beta eta) + tanh(beta (x - eta)))
+ *                    / (tanh(beta eta) + tanh(beta (1 - eta)))
+ *               (the paper's sigmoid-like projection towards two materials);
+ *   material    eps = eps_min + P(rho) (eps_max - eps_min).
+ * Layouts: theta, rho, work and dF/dtheta are float64 [h][w] device arrays;
+ * eps and dF/deps are float64 [ny][nx] maps with the block at (i0, j0)
+ * (nx = w, ny = h, i0 = j0 = 0 for a compact block).  Caller-owned.
+ * Errors: FDFD_ERR_ARG (enqueues nothing; text from fdfd_param_last_error),
+ * FDFD_ERR_HIP on a launch failure.
+ */
+typedef struct {
+  int32_t w, h;          /* design block, cells along x and y (>= 1)           */
+  int32_t i0, j0;        /* its corner in the eps map                          */
+  int32_t nx, ny;        /* the eps map                                         */
+  double radius;         /* filter radius in cells, (0, 12]                     */
+  double beta, eta;      /* projection steepness (> 0) and threshold (0 < eta < 1) */
+  double eps_min, eps_max;
+} fdfd_param_desc;
+
+/* Forward: rho_dev <- filtered theta (kept for the backward pass); the block
+ * of eps_dev <- eps_min + P(rho) (eps_max - eps_min); the rest of eps_dev is
+ * not touched. */
+fdfd_status fdfd_param_forward(const fdfd_param_desc* desc, const double* theta_dev, double* rho_dev,
+                               double* eps_dev, void* hip_stream);
+
+/* Backward: grad_theta_dev <- dF/dtheta from dF/deps (the block of
+ * grad_eps_dev is read) and rho from the forward pass.  work_dev: h * w
+ * doubles of scratch. */
+fdfd_status fdfd_param_backward(const fdfd_param_desc* desc, const double* rho_dev, const double* grad_eps_dev,
+                                double* work_dev, double* grad_theta_dev, void* hip_stream);
+
+/* Text of the calling thread's last fdfd_param_* error. */
+const char* fdfd_param_last_error(void);
+
 /* Static text of a status code. */
 const char* fdfd_status_str(fdfd_status s);
 

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import torch
 
-from .fdfd import FDFD_ERR_NUMERIC, FDFD_GRAD_SUM_SYSTEMS, FDFDError
+from .fdfd import FDFD_ERR_NUMERIC, FDFD_GRAD_SUM_SYSTEMS, FDFDError, param_backward, param_desc, param_forward
 
 # Refinement used when the caller leaves max_ir at None: none for complex128
 # factors, FP64 refinement to a relative residual of 1e-12 for complex64.
@@ -98,3 +98,36 @@ def mode_overlap(x, c):
     """F = sum over systems and right-hand sides of |c^H x|^2 (torch, on device)."""
     ov = torch.matmul(x, c.conj())
     return (ov.real ** 2 + ov.imag ** 2).sum()
+
+
+class DesignMap(torch.autograd.Function):
+    """theta (h, w) in [0, 1] -> permittivity of the design block (h, w): the
+    smoothing filter and the projection of Sec. III / IV, both in the
+    library's kernels (fdfd_param_forward / fdfd_param_backward)."""
+
+    @staticmethod
+    def forward(ctx, theta, desc):
+        theta = theta.detach().contiguous()
+        rho = torch.empty_like(theta)
+        eps = torch.empty_like(theta)
+        param_forward(desc, theta, rho, eps)
+        ctx.desc = desc
+        ctx.save_for_backward(rho)
+        return eps
+
+    @staticmethod
+    def backward(ctx, grad_eps):
+        (rho,) = ctx.saved_tensors
+        work = torch.empty_like(rho)
+        grad_theta = torch.empty_like(rho)
+        param_backward(ctx.desc, rho, grad_eps.contiguous(), work, grad_theta)
+        return grad_theta, None
+
+
+def design_map(theta, radius, beta, eta=0.5, eps_min=2.085, eps_max=12.11):
+    """Differentiable eps of the design block from theta (float64, (h, w),
+    on the GPU); radius in cells (the paper's 200 nm over dx)."""
+    if theta.dim() != 2 or theta.dtype != torch.float64 or not theta.is_cuda:
+        raise ValueError("theta must be a float64 (h, w) CUDA tensor")
+    h, w = theta.shape
+    return DesignMap.apply(theta, param_desc(w, h, radius, beta, eta, eps_min, eps_max))

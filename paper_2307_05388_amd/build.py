@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfdfd.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["analysis.cpp", "fdfd_api.cpp", "fdfd_kernels.hip"]
+SOURCES = ["analysis.cpp", "fdfd_api.cpp", "fdfd_kernels.hip", "param.hip"]
 HEADERS = ["analysis.h", "plan.hpp"]
 
 ARCH = os.environ.get("FDFD_OFFLOAD_ARCH", "gfx950")
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
         return obj
 
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [cc, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp]

@@ -24,7 +24,8 @@ FDFD_GRAD_ACCUMULATE, FDFD_GRAD_SUM_SYSTEMS = 1, 2
 FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE, FDFD_TABLE_TASKS = 0, 1, 2, 3
 
 EXPORTED = ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_solve_noalloc", "fdfd_adjoint_grad", "fdfd_query",
-            "fdfd_kernel_stats", "fdfd_get_table", "fdfd_status_str", "fdfd_last_error", "fdfd_destroy"]
+            "fdfd_kernel_stats", "fdfd_get_table", "fdfd_param_forward", "fdfd_param_backward",
+            "fdfd_param_last_error", "fdfd_status_str", "fdfd_last_error", "fdfd_destroy"]
 
 
 class Desc(ctypes.Structure):
@@ -53,6 +54,13 @@ class Info(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("alg_flops", ctypes.c_double)]
+
+
+class ParamDesc(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("i0", ctypes.c_int32), ("j0", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("radius", ctypes.c_double),
+                ("beta", ctypes.c_double), ("eta", ctypes.c_double), ("eps_min", ctypes.c_double),
+                ("eps_max", ctypes.c_double)]
 
 
 class FDFDError(RuntimeError):
@@ -92,8 +100,13 @@ def load_library(path: str = LIB_PATH):
     lib.fdfd_last_error.restype = ctypes.c_char_p
     lib.fdfd_destroy.argtypes = [vp]
     lib.fdfd_destroy.restype = None
+    lib.fdfd_param_forward.argtypes = [ctypes.POINTER(ParamDesc), vp, vp, vp, vp]
+    lib.fdfd_param_backward.argtypes = [ctypes.POINTER(ParamDesc), vp, vp, vp, vp, vp]
+    lib.fdfd_param_last_error.argtypes = []
+    lib.fdfd_param_last_error.restype = ctypes.c_char_p
     for name in ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_solve_noalloc", "fdfd_adjoint_grad",
-                 "fdfd_query", "fdfd_get_table", "fdfd_kernel_stats"]:
+                 "fdfd_query", "fdfd_get_table", "fdfd_kernel_stats", "fdfd_param_forward",
+                 "fdfd_param_backward"]:
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -256,6 +269,29 @@ class Plan:
         st = self._lib.fdfd_get_table(self._h, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out.size)
         self._check(st)
         return out[:n]
+
+
+def param_desc(w, h, radius, beta, eta=0.5, eps_min=2.085, eps_max=12.11, i0=0, j0=0, nx=None, ny=None):
+    """Descriptor of the design parametrisation (a compact block by default)."""
+    return ParamDesc(w=w, h=h, i0=i0, j0=j0, nx=w if nx is None else nx, ny=h if ny is None else ny,
+                     radius=radius, beta=beta, eta=eta, eps_min=eps_min, eps_max=eps_max)
+
+
+def param_forward(desc, theta, rho, eps, stream=None):
+    """fdfd_param_forward on device tensors (float64)."""
+    lib = load_library()
+    st = lib.fdfd_param_forward(ctypes.byref(desc), _ptr(theta), _ptr(rho), _ptr(eps), _stream_handle(stream))
+    if st != FDFD_OK:
+        raise FDFDError(st, lib.fdfd_param_last_error().decode())
+
+
+def param_backward(desc, rho, grad_eps, work, grad_theta, stream=None):
+    """fdfd_param_backward on device tensors (float64)."""
+    lib = load_library()
+    st = lib.fdfd_param_backward(ctypes.byref(desc), _ptr(rho), _ptr(grad_eps), _ptr(work), _ptr(grad_theta),
+                                 _stream_handle(stream))
+    if st != FDFD_OK:
+        raise FDFDError(st, lib.fdfd_param_last_error().decode())
 
 
 def status_str(code: int) -> str:
