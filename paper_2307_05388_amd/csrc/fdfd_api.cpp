@@ -219,9 +219,11 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       L.max_p = std::max(L.max_p, A.npiv[f]);
       L.max_u = std::max(L.max_u, A.nupd[f]);
       // panel, d, 1/d, then the dense routines' scratch: 16 x 16 for the inverse
-      // blocks, 16 x (p - 16) for the d-scaled columns of the trailing update
+      // blocks, 16 x (p - 16) for the d-scaled columns of the trailing update;
+      // then the children's gather rows (two rows of m ints)
       const size_t scratch = std::max<size_t>(256, 16 * (size_t)std::max(0, A.npiv[f] - 16));
-      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f] + scratch) * cs);
+      const size_t rows = (8 * (size_t)A.m(f) + 15) & ~size_t(15);
+      need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f] + scratch) * cs + rows);
       L.lbytes += P.front_lbytes[f];
     }
     // the one-workgroup kernel keeps at most 64 pivot columns (16 per wave)
@@ -517,23 +519,42 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.wave_ld = 0;
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
   // forward sweep items of the levels above: each front's pivot part, then
-  // the update-row chunks of the fronts whose L21 is split
+  // the update-row chunks of the fronts whose L21 is split.  The pivot part
+  // of a front with many pivot blocks is itself split, one item per 64-row
+  // pivot block (part -1 - j for block j), whose triangular solves stream the
+  // other blocks' results as they are published; such a front always has
+  // its update rows in chunks.
   std::vector<int32_t> fwd_items, bwd_items, nch(P.an.nfronts, 0), chunk_base(P.an.nfronts, 0);
+  std::vector<int32_t> blk_base(P.an.nfronts, -1);
   std::vector<int64_t> part_base(P.an.nfronts, 0);
   {
     const int nlow =
         P.wave_levels > 0 ? P.levels[P.wave_levels - 1].first + P.levels[P.wave_levels - 1].count : 0;
-    int nc_total = 0;
-    // FDFD_SPLIT_KB: the L21 size (KiB) from which a front is split
+    int nc_total = 0, nb_total = 0;
+    // FDFD_SPLIT_KB: the L21 size (KiB) from which a front is split;
+    // FDFD_BLOCK_SPLIT: pivot blocks from which the pivot part is split (0 = never)
     const int64_t split_bytes = (int64_t)env_int("FDFD_SPLIT_KB", (int)(fdfd::kSplitBytes >> 10)) << 10;
+    const int block_split = env_int("FDFD_BLOCK_SPLIT", fdfd::kBlockSplit);
     for (int k = nlow; k < P.an.nfronts; ++k) {
       const int f = P.an.level_fronts[k];
       const int64_t p = P.an.npiv[f], u = P.an.nupd[f];
-      const int nc = u > 0 && u * p * (int64_t)cs >= split_bytes ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
+      const int nbk = (int)((p + fdfd::kChunkRows - 1) / fdfd::kChunkRows);
+      const bool bsplit = block_split > 0 && nbk >= block_split;
+      const bool split = u > 0 && (bsplit || u * p * (int64_t)cs >= split_bytes);
+      const int nc = split ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
       nch[f] = nc;
       chunk_base[f] = nc_total;
-      fwd_items.push_back(f);
-      fwd_items.push_back(-1);
+      if (bsplit) {
+        blk_base[f] = nb_total;
+        nb_total += nbk;
+        for (int j = 0; j < nbk; ++j) {
+          fwd_items.push_back(f);
+          fwd_items.push_back(-1 - j);
+        }
+      } else {
+        fwd_items.push_back(f);
+        fwd_items.push_back(-1);
+      }
       for (int j = 0; j < nc; ++j) {
         fwd_items.push_back(f);
         fwd_items.push_back(j);
@@ -542,8 +563,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     }
     P.n_fwd_items = (int32_t)(fwd_items.size() / 2);
     P.nchunk = nc_total;
+    P.nblk = nb_total;
     // backward: root first, a front's chunks (partial column sums of its
-    // update rows) before its pivot part
+    // update rows) before its pivot part, the pivot blocks last to first
     int64_t pt = 0;
     for (int k = P.an.nfronts - 1; k >= nlow; --k) {
       const int f = P.an.level_fronts[k];
@@ -551,12 +573,21 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
         bwd_items.push_back(f);
         bwd_items.push_back(j);
       }
-      bwd_items.push_back(f);
-      bwd_items.push_back(-1);
+      if (blk_base[f] >= 0) {
+        const int nbk = (P.an.npiv[f] + fdfd::kChunkRows - 1) / fdfd::kChunkRows;
+        for (int j = nbk - 1; j >= 0; --j) {
+          bwd_items.push_back(f);
+          bwd_items.push_back(-1 - j);
+        }
+      } else {
+        bwd_items.push_back(f);
+        bwd_items.push_back(-1);
+      }
       part_base[f] = pt;
       pt += (int64_t)nch[f] * P.an.npiv[f];
     }
     P.part_total = pt;
+    P.n_bwd_items = (int32_t)(bwd_items.size() / 2);
   }
   const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
   if (max_solve_lds > lds_dyn) {
@@ -569,7 +600,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   const int64_t sum_u = P.an.upd_ptr.back();
   P.res_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
   const int64_t need = nsys * P.an.fac_total * (int64_t)cs + nsys * P.an.upd_total * (int64_t)cs +
-                       nsys * (int64_t)P.ntiles * 4 + nsys * ((int64_t)P.an.nfronts + P.nchunk) * 4 +
+                       nsys * (int64_t)P.ntiles * 4 + nsys * ((int64_t)P.an.nfronts + P.nchunk + P.nblk) * 4 +
                        nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16 + nsys * 8 + nsys * N * 8 +
                        2 * nsys * R * N * (int64_t)cs + nsys * R * (sum_u + P.part_total) * (int64_t)cs +
                        2 * nsys * R * N * 16 +
@@ -609,6 +640,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(upload(P, &P.t.part_base, part_base));
     TRY(upload(P, &P.t.nch, nch));
     TRY(upload(P, &P.t.chunk_base, chunk_base));
+    TRY(upload(P, &P.t.blk_base, blk_base));
     TRY(upload(P, &P.t.parent, A.parent));
     TRY(upload(P, &P.t.height, A.height));
     TRY(upload(P, &P.t.fac_off, A.fac_off));
@@ -630,9 +662,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(alloc(P, (void**)&P.partial, nsys * R * P.res_blocks * 16));
     TRY(alloc(P, (void**)&P.status, sizeof(fdfd::DevStatus)));
     TRY(alloc(P, (void**)&P.counters, fdfd::kCounterBytes));
-    TRY(alloc(P, (void**)&P.done, nsys * ((int64_t)A.nfronts + P.nchunk) * 4));
+    TRY(alloc(P, (void**)&P.done, nsys * ((int64_t)A.nfronts + P.nchunk + P.nblk) * 4));
     hipError_t e = hipMemset(P.counters, 0, fdfd::kCounterBytes);
-    if (e == hipSuccess) e = hipMemset(P.done, 0, nsys * ((int64_t)A.nfronts + P.nchunk) * 4);
+    if (e == hipSuccess) e = hipMemset(P.done, 0, nsys * ((int64_t)A.nfronts + P.nchunk + P.nblk) * 4);
     if (e == hipSuccess) e = hipMemset(P.status, 0, sizeof(fdfd::DevStatus));
     if (e != hipSuccess) {
       st = hip_fail(&P, e, "hipMemset");

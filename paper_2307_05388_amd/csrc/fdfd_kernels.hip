@@ -219,33 +219,6 @@ __device__ __forceinline__ C staged_entry(const C* sv, const int* nb, int t, int
   return v;
 }
 
-// Extend-add, gather form: adds the children's update-matrix entries that map
-// to front entries (rr[e], cc[e]) (rr[e] >= cc[e]; rr[e] < 0 marks an unused
-// slot).  The loads of all NB entries are issued together, child by child.
-template <typename C, int NB>
-__device__ __forceinline__ void add_children(const KArgs& a, int s, int f, int m, const int (&rr)[NB],
-                                             const int (&cc)[NB], C (&val)[NB]) {
-  const int cb = a.child_ptr[f], ce = a.child_ptr[f + 1];
-  const int32_t* g = a.gmap + a.gmap_ptr[f];
-  const C* U = (const C*)a.upd + (int64_t)s * a.upd_total;
-  for (int k = cb; k < ce; ++k, g += m) {
-    const int ch = a.child_list[k];
-    const C* Uc = U + a.upd_off[ch];
-    const int nu = a.nupd[ch];
-    int gr[NB], gc[NB];
-#pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      gr[e] = rr[e] >= 0 ? g[rr[e]] : -1;
-      gc[e] = rr[e] >= 0 ? g[cc[e]] : -1;
-    }
-    C v[NB];
-#pragma unroll
-    for (int e = 0; e < NB; ++e) v[e] = (gr[e] >= 0 && gc[e] >= 0) ? ld_ag(Uc + (int64_t)gc[e] * nu + gr[e]) : czero<C>();
-#pragma unroll
-    for (int e = 0; e < NB; ++e) val[e] = cadd(val[e], v[e]);
-  }
-}
-
 // Static pivot perturbation: |d| < thr becomes d (1 + thr/|d|) (thr if d = 0).
 // The test uses |d|^2 against thr^2, so a square root is taken only when a
 // pivot is perturbed; min2 tracks the smallest |d|^2 seen.
@@ -867,42 +840,110 @@ __device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
 // Small fronts: one workgroup per (front, system), whole panel in LDS.
 // Assembly, partial LDL^T of the pivot columns, Schur update of the u x u
 // block (4 x 4 register tiles) straight into the front's update slot, then the
-// panel with inverted 64-wide diagonal blocks, L below them and D on the
-// diagonal.
+// panel (its lower trapezoid: unit-lower L and D on the diagonal).
+// LDS: F (m x p) | d (p) | 1/d (p) | scratch | the children's gather rows.
+// The stencils of the pivot columns are staged in the d / 1/d / scratch area,
+// which is free until the factorisation starts.
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int small_scratch_entries(int p) { return p - 16 > 16 ? 16 * (p - 16) : 256; }
+
+// The children of a front (at most two: the separator tree is binary), read
+// once per front: the compiler cannot keep these table reads out of a loop
+// that also stores to global memory, and each would cost a dependent memory
+// round trip per batch.
+template <typename C>
+struct Kids {
+  int n;
+  const C* u0;
+  const C* u1;
+  int nu0, nu1;
+};
+
+template <typename C>
+__device__ __forceinline__ Kids<C> kids_of(const KArgs& a, int s, int f) {
+  Kids<C> k;
+  const int cb = a.child_ptr[f];
+  k.n = a.child_ptr[f + 1] - cb;
+  const C* U = (const C*)a.upd + (int64_t)s * a.upd_total;
+  const int ch0 = k.n > 0 ? a.child_list[cb] : 0, ch1 = k.n > 1 ? a.child_list[cb + 1] : 0;
+  k.u0 = U + (k.n > 0 ? a.upd_off[ch0] : 0);
+  k.u1 = U + (k.n > 1 ? a.upd_off[ch1] : 0);
+  k.nu0 = k.n > 0 ? a.nupd[ch0] : 0;
+  k.nu1 = k.n > 1 ? a.nupd[ch1] : 0;
+  return k;
+}
+
+// Children's contributions to NB front entries (rr[e], cc[e]) (rr[e] >= cc[e],
+// rr[e] < 0 marks an unused slot), the children's gather rows staged in LDS
+// (gl: one row of m ints per child).  The loads of both children are issued
+// together: one memory round trip for the batch.
+template <typename C, int NB>
+__device__ __forceinline__ void add_children_lds(const Kids<C>& k, int m, const int* gl, const int (&rr)[NB],
+                                                 const int (&cc)[NB], C (&val)[NB]) {
+  C v0[NB], v1[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const bool use = rr[e] >= 0;
+    const int g0r = use && k.n > 0 ? gl[rr[e]] : -1, g0c = use && k.n > 0 ? gl[cc[e]] : -1;
+    const int g1r = use && k.n > 1 ? gl[m + rr[e]] : -1, g1c = use && k.n > 1 ? gl[m + cc[e]] : -1;
+    v0[e] = (g0r >= 0 && g0c >= 0) ? ld_ag(k.u0 + (int64_t)g0c * k.nu0 + g0r) : czero<C>();
+    v1[e] = (g1r >= 0 && g1c >= 0) ? ld_ag(k.u1 + (int64_t)g1c * k.nu1 + g1r) : czero<C>();
+  }
+#pragma unroll
+  for (int e = 0; e < NB; ++e) val[e] = cadd(cadd(val[e], v0[e]), v1[e]);
+}
+
+// The loads of a small front that depend on no other front: the pivot
+// columns' stencils (into the staging area) and the children's gather rows.
+// Issued before the wait for the children.
 template <typename R>
-__device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f, unsigned char* smem_raw) {
+__device__ __forceinline__ void small_front_stage(const KArgs& a, int s, int f, unsigned char* smem_raw) {
+  typedef typename Cx<R>::T C;
+  C* F = reinterpret_cast<C*>(smem_raw);
+  const int p = a.npiv[f], m = p + a.nupd[f];
+  C* dd = F + (int64_t)m * p;
+  stage_columns(a, s, f, 0, p, dd, reinterpret_cast<int*>(dd + 5 * p));
+  int* gl = reinterpret_cast<int*>(dd + 2 * p + small_scratch_entries(p));
+  const int nch = a.child_ptr[f + 1] - a.child_ptr[f];
+  const int32_t* g = a.gmap + a.gmap_ptr[f];
+  for (int k = threadIdx.x; k < nch * m; k += kThreads) gl[k] = g[k];
+}
+
+template <typename R>
+__device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f, const Kids<typename Cx<R>::T>& kids,
+                            unsigned char* smem_raw) {
   typedef typename Cx<R>::T C;
   C* F = reinterpret_cast<C*>(smem_raw);
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
   C* dd = F + (int64_t)m * p;
-  C* invd = dd + p;  // followed by max(16 x 16, 16 x (p - 16)) entries of scratch
+  C* invd = dd + p;  // followed by small_scratch_entries(p) entries of scratch
+  const int* gl = reinterpret_cast<const int*>(dd + 2 * p + small_scratch_entries(p));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   {
-    // the d / 1/d / scratch area is free until the factorisation starts
-    C* sv = dd;
-    int* nbv = reinterpret_cast<int*>(dd + 5 * p);
-    stage_columns(a, s, f, 0, p, sv, nbv);
-    __syncthreads();
-    // four columns per wave and batch (c, c+4, c+8, c+12), lane = row
+    // the stencils staged by small_front_stage (the barrier after the wait
+    // for the children orders them)
+    const C* sv = dd;
+    const int* nbv = reinterpret_cast<const int*>(dd + 5 * p);
+    // four columns per wave (c, c+4, c+8, c+12) and two rows (lane, lane + 64)
+    // per batch of eight entries
     for (int cb = wave; cb < p; cb += 16)
-      for (int r = lane; r < m; r += 64) {
-        int rr[4], cc[4];
-        C v[4];
+      for (int r0 = lane; r0 < m; r0 += 128) {
+        int rr[8], cc[8];
+        C v[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = cb + 4 * e;
-          const bool ok = c < p && r >= c;
+        for (int e = 0; e < 8; ++e) {
+          const int c = cb + 4 * (e & 3), r = r0 + 64 * (e >> 2);
+          const bool ok = c < p && r < m && r >= c;
           rr[e] = ok ? r : -1;
           cc[e] = c;
           v[e] = ok ? staged_entry(sv, nbv, c, r, c) : czero<C>();
         }
-        add_children<C, 4>(a, s, f, m, rr, cc, v);
+        add_children_lds<C, 8>(kids, m, gl, rr, cc, v);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = cb + 4 * e;
-          if (c < p) F[c * m + r] = v[e];
+        for (int e = 0; e < 8; ++e) {
+          const int c = cb + 4 * (e & 3), r = r0 + 64 * (e >> 2);
+          if (c < p && r < m) F[c * m + r] = v[e];
         }
       }
     __syncthreads();
@@ -943,43 +984,38 @@ __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
       }
-      // children's contributions to the update block, one register column per batch
+      // children's contributions to the update block, two register columns per batch
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        int rr[4], cc[4];
-        C v[4];
+      for (int y0 = 0; y0 < 4; y0 += 2) {
+        int rr[8], cc[8];
+        C v[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = ti + tr + 16 * e, c = tj + tc + 16 * y;
+        for (int e = 0; e < 8; ++e) {
+          const int x = e & 3, y = y0 + (e >> 2);
+          const int r = ti + tr + 16 * x, c = tj + tc + 16 * y;
           rr[e] = (r < u && c < u && r >= c) ? p + r : -1;
           cc[e] = p + c;
           v[e] = czero<C>();
         }
-        add_children<C, 4>(a, s, f, m, rr, cc, v);
+        add_children_lds<C, 8>(kids, m, gl, rr, cc, v);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 8; ++e)
           if (rr[e] >= 0) {
             const int r = rr[e] - p, c = cc[e] - p;
-            st_ag(U + (int64_t)c * u + r, csub(v[e], acc[e][y]));
+            st_ag(U + (int64_t)c * u + r, csub(v[e], acc[e & 3][y0 + (e >> 2)]));
           }
       }
     }
   }
-  // the parent needs only the update block: release it before the inverse
+  // the parent needs only the update block: release it before the panel
   publish(q, ep, s * a.nfronts + f);
   // Stored panel of a small front (p <= 64): D on the diagonal and the
-  // unit-lower L below it, no inverse.  The sweeps of these fronts solve with
-  // L11 in registers of one wavefront (a chain of p lane broadcasts, far
-  // shorter than a memory round trip), so an inverse would only cost the
-  // factorisation time.
+  // unit-lower L below it, no inverse (the sweeps of these fronts solve with
+  // L11 in registers of one wavefront, a chain of p lane broadcasts, far
+  // shorter than a memory round trip).  Nothing reads above the diagonal.
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   for (int c = wave; c < p; c += 4)
-    for (int r = lane; r < m; r += 64) {
-      C v = czero<C>();
-      if (r > c) v = F[c * m + r];
-      else if (r == c) v = dd[c];
-      L[(int64_t)c * m + r] = v;
-    }
+    for (int r = c + lane; r < m; r += 64) L[(int64_t)c * m + r] = r > c ? F[c * m + r] : dd[c];
   if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
 }
 
@@ -996,9 +1032,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, c
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
     const int f = order[t / a.nsys], s = t % a.nsys;
+    // independent of the wait below: the stencils, gather rows and children
+    small_front_stage<R>(a, s, f, smem_raw);
+    const Kids<typename Cx<R>::T> kids = kids_of<typename Cx<R>::T>(a, s, f);
     if (q.wait) wait_children(q, ep, a, s, f);
+    else __syncthreads();
     trace_mark(q, t, 1);
-    small_front<R>(a, q, ep, s, f, smem_raw);
+    small_front<R>(a, q, ep, s, f, kids, smem_raw);
     trace_mark(q, t, 2);
   }
   leave(q, ep);
@@ -1763,12 +1803,21 @@ struct SweepArgs {
   const int64_t* part_base;
   void* pv;
   int64_t part_total;
+  // fronts swept as one item per pivot block: first block flag (-1: not split)
+  const int32_t* blk_base;
+  int32_t nblk;
 };
 
 // Completion flag of update-row chunk j of front f (after the fronts' flags).
 __device__ __forceinline__ const int32_t* chunk_flag(const Queue& q, const KArgs& a, const SweepArgs& w, int s,
                                                      int f, int j) {
   return q.done + (int64_t)a.nsys * a.nfronts + (int64_t)s * w.nchunk + w.chunk_base[f] + j;
+}
+
+// Completion flag of pivot block j of a block-split front f (after the chunks' flags).
+__device__ __forceinline__ const int32_t* blk_flag(const Queue& q, const KArgs& a, const SweepArgs& w, int s, int f,
+                                                   int j) {
+  return q.done + (int64_t)a.nsys * (a.nfronts + w.nchunk) + (int64_t)s * w.nblk + w.blk_base[f] + j;
 }
 
 // Waits of a sweep launch: only on fronts of the same launch (the others
@@ -1950,6 +1999,111 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, bool
   }
 }
 
+// Pivot block j of a block-split front in the forward sweep: V_j = the
+// block's right-hand side rows + the children's update-vector entries, then
+// V_j -= L[block j, block j'] z_j' for every earlier block j' as its item
+// publishes z_j' (the block's L entries are loaded before each wait: the
+// factor is final), then z_j = Xinv_j V_j with the stored inverted diagonal
+// block, y_j = D^-1 z_j into y and z_j into zv for the later blocks and the
+// update-row chunks.  Lane = row, wave w takes the columns w, w + kSW, ...
+template <typename R>
+__device__ void fwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q, int ep, int s, int f, int j,
+                              unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  constexpr int NT = kBW / kSW;
+  const int p = a.npiv[f], u = a.nupd[f], ldl = p + u, pb = a.pbeg[f];
+  const int k0 = j * kBW, kn = min(kBW, p - k0);
+  const int nrhs = w.nrhs;
+  C* red = reinterpret_cast<C*>(smem);  // nrhs x kSW x kBW partial sums
+  C* V = red + kSW * kBW * nrhs;        // nrhs x kBW
+  C* Z = V + kBW * nrhs;                // nrhs x kBW: z of the block being applied
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
+  C* Zv = (C*)w.zv + (int64_t)s * nrhs * a.N;
+  const C* W = (const C*)w.wv + (int64_t)s * nrhs * a.sum_u;
+  const double2* B = w.src + (int64_t)s * nrhs * a.N;
+  const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
+  const int32_t* g = a.gmap + a.gmap_ptr[f];
+  for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+    const int col = idx / kn, r = k0 + idx - col * kn;
+    const int n = a.perm[pb + r];
+    double2 bv = B[(int64_t)col * a.N + n];
+    if (w.scale_src) bv = dmul(bv, sym_scale(a, s, n));
+    C v = from_d2<C>(bv);
+    for (int k = 0; k < nch; ++k) {
+      const int gk = g[k * ldl + r];
+      if (gk >= 0) v = cadd(v, ld_ag(W + (int64_t)col * a.sum_u + a.upd_ptr[a.child_list[cb + k]] + gk));
+    }
+    V[col * kBW + (r - k0)] = v;
+  }
+  for (int idx = threadIdx.x; idx < kSW * kBW * nrhs; idx += kSweepThreads) red[idx] = czero<C>();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int jp = 0; jp < j; ++jp) {
+    C l[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = jp * kBW + wave + kSW * t;
+      l[t] = lane < kn ? L[(int64_t)c * ldl + k0 + lane] : czero<C>();
+    }
+    if (threadIdx.x == 0) {
+      wait_flag(q, ep, blk_flag(q, a, w, s, f, jp));
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kBW * nrhs; idx += kSweepThreads) {
+      const int col = idx / kBW, r = idx - col * kBW;
+      Z[idx] = ld_ag(Zv + (int64_t)col * a.N + pb + jp * kBW + r);
+    }
+    __syncthreads();
+    for (int col = 0; col < nrhs; ++col) {
+      C acc = czero<C>();
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc = cadd(acc, cmul(l[t], Z[col * kBW + wave + kSW * t]));
+      C* rp = red + (col * kSW + wave) * kBW + lane;
+      *rp = cadd(*rp, acc);
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+    const int col = idx / kn, r = idx - col * kn;
+    const C* rr = red + col * kSW * kBW + r;
+    C acc = czero<C>();
+#pragma unroll
+    for (int qq = 0; qq < kSW; ++qq) acc = cadd(acc, rr[qq * kBW]);
+    V[col * kBW + r] = csub(V[col * kBW + r], acc);
+  }
+  __syncthreads();
+  {
+    // V <- Xinv V: the stored strictly lower part of the inverted unit-lower block
+    const C* Xb = L + (int64_t)k0 * ldl + k0;
+    C xv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int jj = wave + kSW * t;
+      xv[t] = (lane < kn && jj < lane) ? Xb[(int64_t)jj * ldl + lane] : czero<C>();
+    }
+    for (int col = 0; col < nrhs; ++col) {
+      C acc = czero<C>();
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int jj = wave + kSW * t;
+        acc = cadd(acc, cmul(xv[t], jj < kn ? V[col * kBW + jj] : czero<C>()));
+      }
+      red[(col * kSW + wave) * kBW + lane] = acc;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+    const int col = idx / kn, r = idx - col * kn;
+    const C* rr = red + col * kSW * kBW + r;
+    C z = V[col * kBW + r];
+#pragma unroll
+    for (int qq = 0; qq < kSW; ++qq) z = cadd(z, rr[qq * kBW]);
+    Y[(int64_t)col * a.N + pb + k0 + r] = cmul(z, cinv(L[(int64_t)(k0 + r) * ldl + k0 + r]));
+    st_ag(Zv + (int64_t)col * a.N + pb + k0 + r, z);
+  }
+}
+
 // One chunk of kChunkRows update rows R = [r0, r0 + nr) of a split front in
 // the forward sweep: V_R = the children's update-vector entries of those rows
 // (gathered before the front's pivot item is waited for), then
@@ -1981,20 +2135,53 @@ __device__ void fwd_chunk(const KArgs& a, const SweepArgs& w, const Queue& q, in
     V[col * nr + r] = v;
   }
   for (int idx = threadIdx.x; idx < kSW * kChunkRows * nrhs; idx += kSweepThreads) red[idx] = czero<C>();
+  const C* Zs = (const C*)w.zv + (int64_t)s * nrhs * a.N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool rowok = lane < nr;
+  const C* Li = L + r0 + (rowok ? lane : 0);
+  if (w.blk_base[f] >= 0) {
+    // block-split front: take each pivot block's z as its item publishes it
+    constexpr int NT = kBW / kSW;
+    for (int jp = 0; jp * kBW < p; ++jp) {
+      const int kb = jp * kBW, kn = min(kBW, p - kb);
+      C l[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = wave + kSW * t;
+        l[t] = rowok && c < kn ? Li[(int64_t)(kb + c) * m] : czero<C>();
+      }
+      if (threadIdx.x == 0) {
+        wait_flag(q, ep, blk_flag(q, a, w, s, f, jp));
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+        const int col = idx / kn, r = idx - col * kn;
+        Z[col * p + kb + r] = ld_ag(Zs + (int64_t)col * a.N + pb + kb + r);
+      }
+      __syncthreads();
+      for (int col = 0; col < nrhs; ++col) {
+        C* acc = red + (col * kSW + wave) * kChunkRows + lane;
+        C v = *acc;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int c = wave + kSW * t;
+          v = cadd(v, cmul(l[t], c < kn ? Z[col * p + kb + c] : czero<C>()));
+        }
+        *acc = v;
+      }
+    }
+  } else {
   if (threadIdx.x == 0) {
     wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + f);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
-  const C* Zs = (const C*)w.zv + (int64_t)s * nrhs * a.N;
   for (int idx = threadIdx.x; idx < p * nrhs; idx += kSweepThreads) {
     const int col = idx / p, r = idx - col * p;
     Z[col * p + r] = ld_ag(Zs + (int64_t)col * a.N + pb + r);
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool rowok = lane < nr;
-  const C* Li = L + r0 + (rowok ? lane : 0);
   for (int t0 = wave; t0 < p; t0 += kSweepBatch * kSW) {
     C l[kSweepBatch];
 #pragma unroll
@@ -2012,6 +2199,7 @@ __device__ void fwd_chunk(const KArgs& a, const SweepArgs& w, const Queue& q, in
       }
       *acc = v;
     }
+  }
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < nr * nrhs; idx += kSweepThreads) {
@@ -2070,25 +2258,25 @@ __device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, in
 // block's inverse (diag = true), per row part into red[c][part][jj].
 template <int NR, typename C>
 __device__ __forceinline__ void bwd_group(const C* L, int ldl, const C* X, C* red, int m, int k0, int kn, int k1,
-                                          int c0, bool diag) {
+                                          int r1, int c0, bool diag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int jj = 16 * (wave & 3) + (lane & 15), rq = wave >> 2;
   const bool colok = jj < kn;
   C acc[NR];
-  if (!diag) bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * ldl, colok, X + c0 * m, m, k1, m, acc);
+  if (!diag) bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * ldl, colok, X + c0 * m, m, k1, r1, acc);
   else bwd_dots<NR>(L + (int64_t)(k0 + min(jj, kn - 1)) * ldl + k0, colok, X + c0 * m + k0, m, jj + 1, kn, acc);
   if (lane < 16)
 #pragma unroll
     for (int c = 0; c < NR; ++c) red[((c0 + c) * kNQ + rq) * kBW + jj] = acc[c];
 }
 
-// L: the panel (leading dimension ldl); X: nrhs x m, rows [k1, m) summed.
+// L: the panel (leading dimension ldl); X: nrhs x m, rows [k1, r1) summed.
 template <typename C>
 __device__ __forceinline__ void bwd_block(const C* L, int ldl, const C* X, C* red, int m, int k0, int kn, int k1,
-                                          int nrhs, bool diag) {
+                                          int r1, int nrhs, bool diag) {
   for (int c0 = 0; c0 < nrhs; c0 += 2) {
-    if (nrhs - c0 >= 2) bwd_group<2>(L, ldl, X, red, m, k0, kn, k1, c0, diag);
-    else bwd_group<1>(L, ldl, X, red, m, k0, kn, k1, c0, diag);
+    if (nrhs - c0 >= 2) bwd_group<2>(L, ldl, X, red, m, k0, kn, k1, r1, c0, diag);
+    else bwd_group<1>(L, ldl, X, red, m, k0, kn, k1, r1, c0, diag);
   }
 }
 
@@ -2136,7 +2324,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, int 
     const int k0 = ((k1 - 1) / kBW) * kBW;
     const int kn = k1 - k0;
     if (k1 < m) {
-      bwd_block(L, ldl, X, red, m, k0, kn, k1, nrhs, false);
+      bwd_block(L, ldl, X, red, m, k0, kn, k1, m, nrhs, false);
       __syncthreads();
       for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
         const int col = idx / kn, j = idx - col * kn;
@@ -2148,7 +2336,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, int 
       }
       __syncthreads();
     }
-    bwd_block(L, ldl, X, red, m, k0, kn, k1, nrhs, true);
+    bwd_block(L, ldl, X, red, m, k0, kn, k1, m, nrhs, true);
     __syncthreads();
     // x_blk = X_blk + the parts' sums (every read of X_blk above is done)
     for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
@@ -2168,6 +2356,84 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, int 
     const C x = X[col * m + r];
     st_ag(Y + (int64_t)col * a.N + pb + r, x);
     double2* o = O + (int64_t)col * a.N + a.perm[pb + r];
+    const double2 xv = to_d2(x);
+    *o = w.accumulate ? dadd(*o, xv) : xv;
+  }
+}
+
+// Pivot block j of a block-split front in the backward sweep (every chunk of
+// the front has been waited for): X_j = y_j minus the chunks' partial column
+// sums (in chunk order), then X_j -= L[block j', block j]^T x_j' for every
+// later block j' as its item publishes x_j' (last block first), then
+// x_j = Xinv_j^T X_j; x_j goes to y (for the other blocks and the children)
+// and to the grid-order output.  X holds the front's rows (leading dimension
+// m) as in bwd_front, filled only for block j and the block being applied.
+template <typename R>
+__device__ void bwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q, int ep, int s, int f, int j, int nc,
+                              unsigned char* smem) {
+  typedef typename Cx<R>::T C;
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, ldl = m, pb = a.pbeg[f];
+  const int k0 = j * kBW, kn = min(kBW, p - k0);
+  const int nrhs = w.nrhs;
+  C* red = reinterpret_cast<C*>(smem);  // nrhs x kNQ x kBW
+  C* X = red + kNQ * nrhs * kBW;        // nrhs x m
+  const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+  C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
+  const C* PB = (const C*)w.pv + (int64_t)s * nrhs * w.part_total + (nc > 0 ? w.part_base[f] : 0);
+  for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+    const int col = idx / kn, r = k0 + idx - col * kn;
+    C v = ld_ag(Y + (int64_t)col * a.N + pb + r);
+    if (nc > 0) {
+      const C* pr = PB + (int64_t)col * w.part_total + r;
+      C acc = czero<C>();
+      for (int j0 = 0; j0 < nc; j0 += 8) {
+        C pj[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) pj[t] = j0 + t < nc ? ld_ag(pr + (int64_t)(j0 + t) * p) : czero<C>();
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (j0 + t < nc) acc = cadd(acc, pj[t]);
+      }
+      v = csub(v, acc);
+    }
+    X[col * m + r] = v;
+  }
+  const int nbk = (p + kBW - 1) / kBW;
+  for (int jp = nbk - 1; jp > j; --jp) {
+    const int kb = jp * kBW, kbn = min(kBW, p - kb);
+    if (threadIdx.x == 0) {
+      wait_flag(q, ep, blk_flag(q, a, w, s, f, jp));
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kbn * nrhs; idx += kSweepThreads) {
+      const int col = idx / kbn, r = kb + idx - col * kbn;
+      X[col * m + r] = ld_ag(Y + (int64_t)col * a.N + pb + r);
+    }
+    __syncthreads();
+    bwd_block(L, ldl, X, red, m, k0, kn, kb, kb + kbn, nrhs, false);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+      const int col = idx / kn, jj = idx - col * kn;
+      const C* rr = red + col * kNQ * kBW + jj;
+      C acc = czero<C>();
+#pragma unroll
+      for (int qq = 0; qq < kNQ; ++qq) acc = cadd(acc, rr[qq * kBW]);
+      X[col * m + k0 + jj] = csub(X[col * m + k0 + jj], acc);
+    }
+  }
+  __syncthreads();
+  bwd_block(L, ldl, X, red, m, k0, kn, k0 + kn, m, nrhs, true);
+  __syncthreads();
+  double2* O = w.out + (int64_t)s * nrhs * a.N;
+  for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
+    const int col = idx / kn, jj = idx - col * kn;
+    const C* rr = red + col * kNQ * kBW + jj;
+    C x = X[col * m + k0 + jj];
+#pragma unroll
+    for (int qq = 0; qq < kNQ; ++qq) x = cadd(x, rr[qq * kBW]);
+    st_ag(Y + (int64_t)col * a.N + pb + k0 + jj, x);
+    double2* o = O + (int64_t)col * a.N + a.perm[pb + k0 + jj];
     const double2 xv = to_d2(x);
     *o = w.accumulate ? dadd(*o, xv) : xv;
   }
@@ -2238,7 +2504,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_fwd_sweep(KArgs a, SweepArgs 
       __syncthreads();
     }
     trace_mark(q, t, 1);
-    if (part < 0) {
+    if (part < 0 && w.blk_base[f] >= 0) {
+      const int j = -1 - part;
+      fwd_piv_block<R>(a, w, q, ep, s, f, j, smem_raw);
+      publish(q, ep, (int64_t)a.nsys * (a.nfronts + w.nchunk) + (int64_t)s * w.nblk + w.blk_base[f] + j);
+      // the front's own flag once its last block is done (every earlier block was waited for)
+      if (j == (a.npiv[f] + kBW - 1) / kBW - 1 && threadIdx.x == 0)
+        __hip_atomic_store(q.done + (int64_t)s * a.nfronts + f, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (part < 0) {
       fwd_front<R>(a, w, s, f, w.nch[f] > 0, smem_raw);
       publish(q, ep, (int64_t)s * a.nfronts + f);
     } else {
@@ -2277,7 +2550,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs 
       __syncthreads();
     }
     trace_mark(q, t, 1);
-    if (part < 0) {
+    if (part < 0 && w.blk_base[f] >= 0) {
+      const int j = -1 - part;
+      bwd_piv_block<R>(a, w, q, ep, s, f, j, nc, smem_raw);
+      publish(q, ep, (int64_t)a.nsys * (F + w.nchunk) + (int64_t)s * w.nblk + w.blk_base[f] + j);
+      // block 0 waited for every other block: the front is done
+      if (j == 0 && threadIdx.x == 0)
+        __hip_atomic_store(q.done + (int64_t)s * F + f, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (part < 0) {
       bwd_front<R>(a, w, s, f, nc, smem_raw);
       publish(q, ep, (int64_t)s * F + f);
     } else {
@@ -2930,6 +3210,8 @@ void sweep(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src, dou
   w.part_base = P.t.part_base;
   w.pv = wk.pv;
   w.part_total = P.part_total;
+  w.blk_base = P.t.blk_base;
+  w.nblk = P.nblk;
   const int32_t* lf = P.t.level_fronts;
   const int nlev = (int)P.levels.size();
   const int lw = P.wave_levels;
@@ -2973,7 +3255,7 @@ void sweep(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src, dou
     wh.status_mode = -1;
     wh.lev_lo = lw;
     wh.lev_hi = nlev;
-    const int n = P.n_fwd_items * nsys;
+    const int n = P.n_bwd_items * nsys;
     Prof pr(P, st, KC_BWD_SWEEP, fb_high, 0.0);
     hipLaunchKernelGGL((k_bwd_sweep<R>), dim3(resident_grid(P, bh, lds, n, kSweepThreads)), dim3(kSweepThreads), lds,
                        st, a, wh,

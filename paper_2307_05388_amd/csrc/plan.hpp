@@ -38,7 +38,7 @@ struct DevTables {
   int32_t *level_fronts = nullptr;
   int32_t *parent = nullptr, *height = nullptr;
   int32_t *tile_tasks = nullptr, *tile_base = nullptr, *is_tiled = nullptr;
-  int32_t *fwd_items = nullptr, *bwd_items = nullptr, *nch = nullptr, *chunk_base = nullptr;
+  int32_t *fwd_items = nullptr, *bwd_items = nullptr, *nch = nullptr, *chunk_base = nullptr, *blk_base = nullptr;
   int64_t *part_base = nullptr;
   int64_t *fac_off = nullptr, *upd_off = nullptr, *gmap_ptr = nullptr;
 };
@@ -95,6 +95,8 @@ struct Plan {
   // rows of a front whose L21 is split over several workgroups.
   int32_t n_fwd_items = 0;
   int32_t nchunk = 0;           // update-row chunks of all split fronts (one system)
+  int32_t nblk = 0;             // pivot-block items of all block-split fronts (one system)
+  int32_t n_bwd_items = 0;
   int64_t part_total = 0;       // backward: sum over split fronts of chunks x pivots
 
   // arenas (device)
@@ -114,7 +116,7 @@ struct Plan {
   DevStatus* status = nullptr;
   int32_t* counters = nullptr;  // [0..1] persistent-queue counters, [2] residual blocks,
                                 // [kEpochSlot] epoch of the last persistent launch
-  int32_t* done = nullptr;      // [nsys][nfronts] completion epochs, then [nsys][nchunk]
+  int32_t* done = nullptr;      // [nsys][nfronts] completion epochs, then [nsys][nchunk], then [nsys][nblk]
   int32_t* tile_state = nullptr;  // [nsys][ntiles] tile versions
   int32_t* tile_done = nullptr;   // [nsys][nfronts] finished update tiles
   DevStatus* status_host = nullptr;  // pinned
@@ -161,6 +163,9 @@ constexpr int kEpochSlot = 32;
 // workgroup each.
 constexpr int kChunkRows = 64;
 constexpr int64_t kSplitBytes = 128 << 10;
+// A front with at least kBlockSplit pivot blocks has its pivot part swept as
+// one item per pivot block (FDFD_BLOCK_SPLIT overrides it, 0 = never).
+constexpr int kBlockSplit = 6;
 constexpr size_t kCounterBytes = 256;
 // Pivot blocks whose products one Schur-complement tile task accumulates
 // before it writes the tile (FDFD_SYRK_GROUP overrides it at analysis).

@@ -3,7 +3,9 @@ update-row chunk items (forward: z handed to the chunks; backward: the chunks'
 partial column sums handed to the pivot item).
 
 A plan that splits every tiled front with update rows (FDFD_SPLIT_KB=1, read
-at analysis) against one that splits none, on the same factor layout (tile
+at analysis), and with FDFD_BLOCK_SPLIT=2 also the pivot rows of every tiled
+front with two or more pivot blocks (one item per pivot block, streaming the
+other blocks' results), against one that splits none, on the same factor layout (tile
 graph for every level) and inputs: the splits only reorder the sums of the
 update rows, so fields and gradients agree to rounding.  Two wavelengths x two
 source profiles exercise the per-system / per-RHS offsets of the hand-over
@@ -18,10 +20,11 @@ from gpu_util import entry_err, rel, say, torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-def _run(monkeypatch, p, prec, split_kb, eps, b, c, max_ir, tol):
+def _run(monkeypatch, p, prec, split_kb, eps, b, c, max_ir, tol, block_split=0):
     torch = torch_cuda()
     from paper_2307_05388_amd.fdfd import Plan
     monkeypatch.setenv("FDFD_SPLIT_KB", str(split_kb))
+    monkeypatch.setenv("FDFD_BLOCK_SPLIT", str(block_split))
     plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=36, small_lds=-1)
     plan.refactor(eps, P.omegas(p))
     x = plan.solve(b, max_ir=max_ir, tol=tol)
@@ -35,16 +38,17 @@ def _run(monkeypatch, p, prec, split_kb, eps, b, c, max_ir, tol):
     return x.cpu().numpy(), grad.cpu().numpy(), st
 
 
+@pytest.mark.parametrize("block_split", [0, 2])
 @pytest.mark.parametrize("prec,max_ir,tol,rtol", [("c128", 0, 0.0, 1e-11), ("c64", 8, 1e-11, 1e-9)])
-def test_split_sweeps_match_unsplit(oracle, monkeypatch, prec, max_ir, tol, rtol):
+def test_split_sweeps_match_unsplit(oracle, monkeypatch, prec, max_ir, tol, rtol, block_split):
     torch = torch_cuda()
     p = P.custom_problem(150, 131, 12, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss"))
     dev = torch.device("cuda:0")
     eps = torch.from_numpy(np.stack([P.design_eps(p, t=3 + 5 * s) for s in range(p.nsys)])).to(dev)
     b = torch.from_numpy(P.sources(p)).to(dev)
     c = torch.from_numpy(P.objective_vector(p)).to(dev)
-    say(f"split sweeps {prec} {p.nx}x{p.ny} nsys={p.nsys} nrhs={p.nrhs}")
-    xs, gs, sts = _run(monkeypatch, p, prec, 1, eps, b, c, max_ir, tol)
+    say(f"split sweeps {prec} {p.nx}x{p.ny} nsys={p.nsys} nrhs={p.nrhs} block_split={block_split}")
+    xs, gs, sts = _run(monkeypatch, p, prec, 1, eps, b, c, max_ir, tol, block_split)
     xu, gu, stu = _run(monkeypatch, p, prec, 1 << 30, eps, b, c, max_ir, tol)
     assert sts in ("ok", "pivots perturbed") and stu == sts
     ex = np.linalg.norm(xs - xu) / np.linalg.norm(xu)
