@@ -336,9 +336,12 @@ def phase_times(p, prec, max_ir, tol, eps, b, c, omegas, leaf=0, reps=3):
             t2 = time.perf_counter()
         nf.append(t1 - t0)
         bs.append(t2 - t1)
+        info = plan.query()
         plan.close()
     med = lambda v: 1e3 * float(np.median(v))
-    return {"sf_ms": med(sf), "setup_ms": med(full) - med(sf), "nf_ms": med(nf), "bs_ms": med(bs)}
+    return {"sf_ms": med(sf), "setup_ms": med(full) - med(sf), "nf_ms": med(nf), "bs_ms": med(bs),
+            "ir_steps": [info["ir_steps_solve"], info["ir_steps_adjoint"]], "status": info["status_str"],
+            "n_perturbed": info["n_perturbed"]}
 
 
 def caching_split(args, p, mode, eps_all, b, c, omegas, cached_ms):
@@ -370,7 +373,8 @@ def footprint_sweep(args):
         eps = torch.from_numpy(P.design_eps(p, 0)).to(dev)
         b = torch.from_numpy(P.sources(p)).to(dev)
         c = torch.from_numpy(P.objective_vector(p)).to(dev)
-        row = {"side_cells": side, "footprint_um": side * p.dx_nm / 1000.0, "N": p.N}
+        row = {"side_cells": side, "footprint_um": (side - 80) * p.dx_nm / 1000.0,
+               "domain_um": side * p.dx_nm / 1000.0, "N": p.N}
         for prec in [m.strip() for m in args.modes.split(",") if m.strip()]:
             max_ir, tol = form_ir(args, prec)
             ph = phase_times(p, prec, max_ir, tol, eps, b, c, om, reps=2)

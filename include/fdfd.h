@@ -114,6 +114,9 @@ typedef struct {
   double rel_residual_adjoint; /* max over columns of ||g - SA lam'|| / ||g||      */
   int32_t device_flags;      /* raw device status bits                            */
   int32_t small_levels;      /* bottom tree levels run one workgroup per front    */
+  double refactor_ms;        /* device time of the last fdfd_refactor (HIP events */
+  double solve_ms;           /* around its launches), of the last fdfd_solve and  */
+  double adjoint_ms;         /* of the last fdfd_adjoint_grad; -1 if none yet     */
 } fdfd_info;
 
 /*

@@ -173,6 +173,10 @@ fdfd_status alloc(Plan& P, void** dst, size_t bytes) {
 }
 
 void free_all(Plan& P) {
+  for (hipEvent_t& e : P.phase_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   for (auto& g : P.graphs) (void)hipGraphExecDestroy(g.exec);
   P.graphs.clear();
   if (P.cap_stream) (void)hipStreamDestroy(P.cap_stream);
@@ -688,6 +692,13 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
         goto bad;
       }
     }
+    for (hipEvent_t& ev : P.phase_ev) {
+      if (e == hipSuccess) e = hipEventCreate(&ev);
+    }
+    if (e != hipSuccess) {
+      st = hip_fail(&P, e, "hipEventCreate");
+      goto bad;
+    }
     e = hipHostMalloc((void**)&P.status_host, sizeof(fdfd::DevStatus), hipHostMallocDefault);
     if (e != hipSuccess) {
       st = fail(&P, FDFD_ERR_NOMEM, "pinned host allocation failed");
@@ -731,10 +742,13 @@ fdfd_status fdfd_refactor(fdfd_plan plan, const double* eps_dev, int64_t eps_sys
   hipStream_t st = (hipStream_t)hip_stream;
   std::vector<uint64_t> key = {0, bits(eps_dev), (uint64_t)eps_sys_stride};
   for (double w : om) key.push_back(bits(w));
+  (void)hipEventRecord(P.phase_ev[0], st);
   const fdfd_status r = run_chain(P, std::move(key), st, "refactor launch", [&](hipStream_t s) {
     return fdfd::launch_refactor(P, eps_dev, eps_sys_stride, s);
   });
   if (r != FDFD_OK) return r;
+  (void)hipEventRecord(P.phase_ev[1], st);
+  P.phase_rec[0] = true;
   P.last_stream = st;
   P.factored = true;
   return FDFD_OK;
@@ -752,12 +766,15 @@ fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t n
   if (!(ir_tol > 0.0)) ir_tol = 1e-12;
   DeviceGuard guard(P.device);
   hipStream_t st = (hipStream_t)hip_stream;
+  (void)hipEventRecord(P.phase_ev[2], st);
   const fdfd_status r = run_chain(
       P, {1, bits(b_dev), bits(x_dev), (uint64_t)nrhs, (uint64_t)max_ir, bits(ir_tol)}, st, "solve launch",
       [&](hipStream_t s) {
         return fdfd::launch_solve(P, 0, (const double2*)b_dev, (double2*)x_dev, nrhs, max_ir, ir_tol, s);
       });
   if (r != FDFD_OK) return r;
+  (void)hipEventRecord(P.phase_ev[3], st);
+  P.phase_rec[1] = true;
   P.last_stream = st;
   return FDFD_OK;
 }
@@ -805,6 +822,7 @@ fdfd_status fdfd_adjoint_grad(fdfd_plan plan, const void* x_dev, const void* g_d
   if (!(ir_tol > 0.0)) ir_tol = 1e-12;
   DeviceGuard guard(P.device);
   hipStream_t st = (hipStream_t)hip_stream;
+  (void)hipEventRecord(P.phase_ev[4], st);
   const fdfd_status r = run_chain(
       P,
       {2, bits(x_dev), bits(g_dev), (uint64_t)nrhs, (uint64_t)max_ir, bits(ir_tol), bits(lambda_dev),
@@ -817,6 +835,8 @@ fdfd_status fdfd_adjoint_grad(fdfd_plan plan, const void* x_dev, const void* g_d
         return e;
       });
   if (r != FDFD_OK) return r;
+  (void)hipEventRecord(P.phase_ev[5], st);
+  P.phase_rec[2] = true;
   P.last_stream = st;
   return FDFD_OK;
 }
@@ -842,6 +862,7 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   info->min_pivot_ratio = -1.0;
   info->rel_residual_solve = -1.0;
   info->rel_residual_adjoint = -1.0;
+  info->refactor_ms = info->solve_ms = info->adjoint_ms = -1.0;
   if (P.host_only) return FDFD_OK;
   DeviceGuard guard(P.device);
   hipError_t e = hipMemcpyAsync(P.status_host, P.status, sizeof(fdfd::DevStatus), hipMemcpyDeviceToHost,
@@ -849,6 +870,13 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   if (e == hipSuccess) e = hipStreamSynchronize(P.last_stream);
   if (e != hipSuccess) return hip_fail(&P, e, "status read-back");
   const fdfd::DevStatus& S = *P.status_host;
+  double* phase_ms[3] = {&info->refactor_ms, &info->solve_ms, &info->adjoint_ms};
+  for (int k = 0; k < 3; ++k) {
+    float ms = 0.f;
+    if (P.phase_rec[k] && hipEventSynchronize(P.phase_ev[2 * k + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, P.phase_ev[2 * k], P.phase_ev[2 * k + 1]) == hipSuccess)
+      *phase_ms[k] = ms;
+  }
   info->n_perturbed = S.n_perturbed;
   double mr;
   std::memcpy(&mr, &S.min_ratio_bits, sizeof(double));

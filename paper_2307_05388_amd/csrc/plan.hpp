@@ -149,6 +149,11 @@ struct Plan {
   hipStream_t cap_stream = nullptr;
   int64_t graph_records = 0;         // chains recorded so far (a measurement aid)
 
+  // per-phase device time (fdfd_query): events around the launches of the
+  // last refactor (0, 1), solve (2, 3) and adjoint (4, 5)
+  hipEvent_t phase_ev[6] = {};
+  bool phase_rec[3] = {false, false, false};
+
   hipStream_t last_stream = nullptr;
   std::vector<double> omega_host;
   bool factored = false;

@@ -48,7 +48,8 @@ class Info(ctypes.Structure):
                 ("min_pivot_ratio", ctypes.c_double),
                 ("ir_steps_solve", ctypes.c_int32), ("ir_steps_adjoint", ctypes.c_int32),
                 ("rel_residual_solve", ctypes.c_double), ("rel_residual_adjoint", ctypes.c_double),
-                ("device_flags", ctypes.c_int32), ("small_levels", ctypes.c_int32)]
+                ("device_flags", ctypes.c_int32), ("small_levels", ctypes.c_int32),
+                ("refactor_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
