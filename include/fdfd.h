@@ -117,6 +117,10 @@ typedef struct {
   double refactor_ms;        /* device time of the last fdfd_refactor (HIP events */
   double solve_ms;           /* around its launches), of the last fdfd_solve and  */
   double adjoint_ms;         /* of the last fdfd_adjoint_grad; -1 if none yet     */
+  int32_t rhs_group;         /* right-hand sides per sweep pass at max_rhs: the   */
+                             /* sweeps hold a front's right-hand-side block in   */
+                             /* LDS, so more columns take more passes            */
+  int32_t reserved_info;
 } fdfd_info;
 
 /*
@@ -129,8 +133,17 @@ typedef struct {
  *                   desc->small_lds is 0;
  *   FDFD_SPLIT_KB   L21 size (KiB) from which the sweeps split a front into a
  *                   pivot item and update-row chunks (default 128);
+ *   FDFD_BLOCK_SPLIT pivot blocks from which the sweeps take a front's pivot
+ *                   part one 64-row block per item (default 6, 0 = never);
+ *   FDFD_SYRK_GROUP pivot blocks one Schur-tile task accumulates (default 8);
+ *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
+ *                   passes also never take more than fit the LDS);
  *   FDFD_PIVOT_TAU  static pivot threshold relative to the matrix norm;
  *   FDFD_TRACE      file for per-task timestamps (written by fdfd_query).
+ * max_rhs is not limited by the front sizes: the sweeps hold a front's
+ * right-hand-side block in LDS and take the columns in as many passes as
+ * needed (fdfd_info.rhs_group per pass); a front whose single column does not
+ * fit is refused with FDFD_ERR_ARG.
  */
 fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out);
 

@@ -593,10 +593,12 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     P.part_total = pt;
     P.n_bwd_items = (int32_t)(bwd_items.size() / 2);
   }
-  const size_t max_solve_lds = fdfd::solve_lds_bytes(P, desc->max_rhs);
-  if (max_solve_lds > lds_dyn) {
+  // the sweeps take the right-hand sides in groups that fit the LDS (and at
+  // most FDFD_SWEEP_RHS at a time); one column of the largest front has to
+  P.rhs_cap = std::max(1, env_int("FDFD_SWEEP_RHS", 64));
+  if (fdfd::solve_lds_bytes(P, 1) > lds_dyn) {
     delete h;
-    return fail(nullptr, FDFD_ERR_ARG, "front too large for the solve kernels at this max_rhs");
+    return fail(nullptr, FDFD_ERR_ARG, "front too large for the solve kernels");
   }
 
   // memory plan
@@ -716,7 +718,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     }
   }
 #undef TRY
-  P.solve_lds_max = max_solve_lds;
+  P.solve_lds_max = fdfd::solve_lds_bytes(P, fdfd::solve_rhs_group(P, desc->max_rhs));
+  P.rhs_group = fdfd::solve_rhs_group(P, desc->max_rhs);
   *out = h;
   return FDFD_OK;
 bad:
@@ -863,6 +866,8 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   info->rel_residual_solve = -1.0;
   info->rel_residual_adjoint = -1.0;
   info->refactor_ms = info->solve_ms = info->adjoint_ms = -1.0;
+  info->rhs_group = P.rhs_group;
+  info->reserved_info = 0;
   if (P.host_only) return FDFD_OK;
   DeviceGuard guard(P.device);
   hipError_t e = hipMemcpyAsync(P.status_host, P.status, sizeof(fdfd::DevStatus), hipMemcpyDeviceToHost,

@@ -1786,6 +1786,7 @@ struct SweepArgs {
   void* y;
   void* wv;
   const int* flag;     // refinement converged: skip the launch
+  int64_t io_ld;       // src / out: entries from one system's columns to the next
   int32_t nrhs, scale_src, accumulate;
   DevStatus* st;       // with status_mode >= 0: record "no refinement" for that solve
   int32_t status_mode; // -1, 0 (forward solve) or 1 (adjoint solve)
@@ -1895,7 +1896,7 @@ __device__ void fwd_front(const KArgs& a, const SweepArgs& w, int s, int f, bool
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
-  const double2* B = w.src + (int64_t)s * nrhs * a.N;
+  const double2* B = w.src + (int64_t)s * w.io_ld;
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];  // rows of length ldl per child
   for (int idx = threadIdx.x; idx < m * nrhs; idx += kSweepThreads) {
@@ -2021,7 +2022,7 @@ __device__ void fwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   C* Zv = (C*)w.zv + (int64_t)s * nrhs * a.N;
   const C* W = (const C*)w.wv + (int64_t)s * nrhs * a.sum_u;
-  const double2* B = w.src + (int64_t)s * nrhs * a.N;
+  const double2* B = w.src + (int64_t)s * w.io_ld;
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];
   for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
@@ -2350,7 +2351,7 @@ __device__ void bwd_front(const KArgs& a, const SweepArgs& w, int s, int f, int 
     __syncthreads();
     k1 = k0;
   }
-  double2* O = w.out + (int64_t)s * nrhs * a.N;
+  double2* O = w.out + (int64_t)s * w.io_ld;
   for (int idx = threadIdx.x; idx < p * nrhs; idx += kSweepThreads) {
     const int col = idx / p, r = idx - col * p;
     const C x = X[col * m + r];
@@ -2425,7 +2426,7 @@ __device__ void bwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
   __syncthreads();
   bwd_block(L, ldl, X, red, m, k0, kn, k0 + kn, m, nrhs, true);
   __syncthreads();
-  double2* O = w.out + (int64_t)s * nrhs * a.N;
+  double2* O = w.out + (int64_t)s * w.io_ld;
   for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
     const int col = idx / kn, jj = idx - col * kn;
     const C* rr = red + col * kNQ * kBW + jj;
@@ -2612,7 +2613,7 @@ __device__ void fwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   C* W = (C*)w.wv + (int64_t)s * nrhs * a.sum_u;
-  const double2* B = w.src + (int64_t)s * nrhs * a.N;
+  const double2* B = w.src + (int64_t)s * w.io_ld;
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];
   for (int col = 0; col < nrhs; ++col) {
@@ -2740,7 +2741,7 @@ __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
       X[col * ldv + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
   wave_sync();
   const C* Lc = L + (int64_t)min(lane, max(p - 1, 0)) * m;
-  double2* O = w.out + (int64_t)s * nrhs * a.N;
+  double2* O = w.out + (int64_t)s * w.io_ld;
   for (int col = 0; col < nrhs; ++col) {
     const C* Xc = X + col * ldv;
     C acc = czero<C>();
@@ -3182,17 +3183,43 @@ unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems, in
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src.  The
-// bottom P.wave_levels levels run in the wave-item kernels (forward first,
-// backward last), the levels above in the workgroup-per-front kernels.
+// Right-hand sides one sweep launch takes at once: the most whose LDS blocks
+// fit (a front's right-hand-side block is held whole in LDS).
+int sweep_group(const Plan& P, int nrhs) {
+  const size_t lim = P.lds_limit - 512;
+  int g = std::min(nrhs, P.rhs_cap);
+  while (g > 1 && (sweep_lds(P, g) > lim || sweep_wave_lds(P, g) > lim)) --g;
+  return g;
+}
+
+// One forward + backward sweep: dst (+)= (SA)^-1 (scale ? S : 1) src, over
+// the columns in groups of sweep_group() (each group one forward and one
+// backward pass over the factor, the work vectors laid out for the group).
+// The bottom P.wave_levels levels run in the wave-item kernels (forward
+// first, backward last), the levels above in the workgroup-per-front kernels.
+template <typename R>
+void sweep_cols(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src, double2* dst, int64_t io_ld,
+                int nrhs, int scale_in, int accumulate, const int* flag, hipStream_t st, int status_mode);
+
 template <typename R>
 void sweep(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src, double2* dst, int nrhs, int scale_in,
            int accumulate, const int* flag, hipStream_t st, int status_mode = -1) {
+  const int g = sweep_group(P, nrhs);
+  const int64_t io_ld = (int64_t)nrhs * P.an.N;
+  for (int c0 = 0; c0 < nrhs; c0 += g)
+    sweep_cols<R>(P, wk, a, src + (int64_t)c0 * P.an.N, dst + (int64_t)c0 * P.an.N, io_ld, std::min(g, nrhs - c0),
+                  scale_in, accumulate, flag, st, status_mode);
+}
+
+template <typename R>
+void sweep_cols(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src, double2* dst, int64_t io_ld,
+                int nrhs, int scale_in, int accumulate, const int* flag, hipStream_t st, int status_mode) {
   const int nsys = P.desc.nsys;
   const size_t lds = sweep_lds(P, nrhs), wlds = sweep_wave_lds(P, nrhs);
   SweepArgs w;
   w.src = src;
   w.out = dst;
+  w.io_ld = io_ld;
   w.y = wk.y;
   w.wv = wk.wv;
   w.flag = flag;
@@ -3360,6 +3387,8 @@ hipError_t configure_kernels(Plan& P, int lds_limit) {
 }
 
 size_t solve_lds_bytes(const Plan& P, int nrhs) { return std::max(sweep_lds(P, nrhs), sweep_wave_lds(P, nrhs)); }
+
+int solve_rhs_group(const Plan& P, int nrhs) { return sweep_group(P, nrhs); }
 
 hipError_t launch_refactor(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st) {
   return P.is_c64 ? refactor_impl<float>(P, eps, eps_stride, st)

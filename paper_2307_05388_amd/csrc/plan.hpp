@@ -83,6 +83,8 @@ struct Plan {
   int32_t ntiles = 0;          // packed tiles of the tiled fronts (one system)
   double tiled_flops = 0;      // partial-LDL^T flops of the tiled fronts (one system)
   size_t solve_lds_max = 0;
+  int rhs_group = 1;  // right-hand sides per sweep pass at max_rhs
+  int rhs_cap = 64;   // at most this many per pass (FDFD_SWEEP_RHS)
   int32_t small_prefix = 0;    // leading levels run by one persistent small-front launch
   int32_t syrk_group = 8;      // pivot blocks accumulated per Schur-complement tile task
   size_t small_lds_prefix = 0;
@@ -204,6 +206,8 @@ hipError_t launch_solve(Plan& P, int mode, const double2* rhs, double2* x_out, i
 hipError_t launch_gradient(Plan& P, const double2* x, const double2* lam_sym, int32_t nrhs,
                            double2* lam_out, double* grad, int32_t flags, hipStream_t st);
 size_t solve_lds_bytes(const Plan& P, int nrhs);
+// right-hand sides one sweep pass takes at once (the solves loop over groups)
+int solve_rhs_group(const Plan& P, int nrhs);
 
 // Complex entries of LDS the tile-graph tasks need: the TRSM task's 64 x 64
 // tile, 64 x 64 pivot block and 64 x 16 buffer, the largest of the task types.

@@ -49,7 +49,8 @@ class Info(ctypes.Structure):
                 ("ir_steps_solve", ctypes.c_int32), ("ir_steps_adjoint", ctypes.c_int32),
                 ("rel_residual_solve", ctypes.c_double), ("rel_residual_adjoint", ctypes.c_double),
                 ("device_flags", ctypes.c_int32), ("small_levels", ctypes.c_int32),
-                ("refactor_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double)]
+                ("refactor_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
+                ("rhs_group", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
