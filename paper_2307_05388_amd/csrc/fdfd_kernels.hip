@@ -2227,8 +2227,11 @@ template <typename C> __device__ __forceinline__ C wave_sum(C v) {
 // instruction covers 16 columns x 4 consecutive rows, kDotBatch loads per
 // thread are in flight per step, the four row phases of a column meet through
 // two lane exchanges.  Returns the part's column sums in lanes l < 16.
-// loads in flight per thread in bwd_dots (complex64 entries take half the registers)
-template <typename C> constexpr int kDotBatch = sizeof(C) == 16 ? 16 : 32;
+// loads in flight per thread in bwd_dots: sixteen in both precisions (a
+// deeper batch of complex64 entries, with the two right-hand-side columns'
+// LDS reads it pulls forward, no longer fits the 256 registers a 512-thread
+// workgroup leaves a lane, and spills)
+template <typename C> constexpr int kDotBatch = 16;
 
 template <int NR, typename C>
 __device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, int m, int r0, int r1, C* acc) {
