@@ -596,6 +596,12 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   // the sweeps take the right-hand sides in groups that fit the LDS (and at
   // most FDFD_SWEEP_RHS at a time); one column of the largest front has to
   P.rhs_cap = std::max(1, env_int("FDFD_SWEEP_RHS", 64));
+  // the tile tasks address a pivot block's 64 columns of a front through one
+  // buffer resource of fewer than 2 GiB
+  if (P.an.max_front >= (1 << 20)) {
+    delete h;
+    return fail(nullptr, FDFD_ERR_ARG, "front too large for the tile kernels");
+  }
   if (fdfd::solve_lds_bytes(P, 1) > lds_dyn) {
     delete h;
     return fail(nullptr, FDFD_ERR_ARG, "front too large for the solve kernels");

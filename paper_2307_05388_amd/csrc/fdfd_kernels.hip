@@ -158,6 +158,53 @@ template <typename C> __device__ __forceinline__ void st_ag(C* p, C v) {
   for (int i = 0; i < (int)(sizeof(C) / 8); ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Agent-coherent loads through a buffer resource: the same sc1 loads as
+// ld_ag, but one 16-byte (complex128) or 8-byte (complex64) load per entry,
+// and a load whose byte offset lies outside the resource reads zero, so the
+// rows and columns outside a partial tile are masked by their offsets (one
+// select per row) rather than by a branch around every load.  The resource
+// spans fewer than 2 GiB; kOob is an offset outside every such range.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kOob = 0x80000000u;
+constexpr int kCacheSc1 = 16;  // cache-policy operand of the buffer loads: sc1
+
+// base and bytes must be the same in every lane (the resource lives in
+// scalar registers); they are read from the first lane, so that values the
+// compiler cannot prove uniform (a task's front, read from LDS) do not turn
+// every load into a loop over the distinct descriptors.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, unsigned bytes) {
+  const unsigned long long b = (unsigned long long)base;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  void* p = (void*)(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
+template <typename C> __device__ __forceinline__ C ld_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  C v;
+  if constexpr (sizeof(C) == 16) {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kCacheSc1);
+    __builtin_memcpy(&v, &w, 16);
+  } else {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kCacheSc1);
+    __builtin_memcpy(&v, &w, 8);
+  }
+  return v;
+}
+
+template <typename C> __device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, unsigned off, C v) {
+  if constexpr (sizeof(C) == 16) {
+    u32x4 w;
+    __builtin_memcpy(&w, &v, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, kCacheSc1);
+  } else {
+    u32x2 w;
+    __builtin_memcpy(&w, &v, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, kCacheSc1);
+  }
+}
+
 // Copies a column-major global block (leading dimension ld; rows < nrows,
 // columns < ncols; tri = 0 all, 1 lower with diagonal, 2 strictly lower) into
 // a zero-padded kBW x kBW LDS block.  Lane = row, wave w takes columns w,
@@ -1109,12 +1156,95 @@ __device__ __forceinline__ C* front_elem(const KArgs& a, int s, int f, int p, in
   return (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f] + (int64_t)(c - p) * u + (r - p);
 }
 
+// Tile (rows [r0, r0 + nr), columns [c0, c0 + nc)) of front f in memory, as
+// one buffer: the panel's pivot columns or the update block (a tile lies
+// wholly in one of them), columns >= nc outside it.  Entry (r0 + lane,
+// c0 + wave + 4t) is at byte offset rowoff + t * colstride; rowoff is kOob
+// for lanes >= nr, so their loads read zero and their stores are dropped.
+struct TileMem {
+  __amdgpu_buffer_rsrc_t rs;
+  unsigned colstride, rowoff;
+};
+
+template <typename C>
+__device__ __forceinline__ TileMem tile_mem(const KArgs& a, int s, int f, const Chunks& ch, int r0, int nr, int c0,
+                                            int nc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool piv = c0 < ch.p;
+  const C* base = piv ? (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f] + (int64_t)c0 * ch.m
+                      : (const C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f] + (int64_t)(c0 - ch.p) * ch.u;
+  const unsigned ld = piv ? ch.m : ch.u;
+  const int row = piv ? r0 + lane : r0 - ch.p + lane;
+  TileMem t;
+  t.rs = buffer_of(base, (unsigned)nc * ld * (unsigned)sizeof(C));
+  t.colstride = 4u * ld * (unsigned)sizeof(C);
+  t.rowoff = lane < nr ? ((unsigned)wave * ld + (unsigned)row) * (unsigned)sizeof(C) : kOob;
+  return t;
+}
+
+// The children's gather rows for tile (rows r0.., columns c0..) of front f,
+// into LDS (the maps are static, so this may run before the task's waits):
+// kid[128 k + e], e < 64, is child k's update-block row of tile row r0 + e,
+// and kid[128 k + 64 + e] that of tile column c0 + e (-1: none).  A front has
+// at most two children (each dissection step halves a rectangle), so the 256
+// threads cover them in one pass.
+__device__ __forceinline__ void stage_kid_rows(const KArgs& a, int f, int m, int r0, int nr, int c0, int nc, int* kid) {
+  static_assert(kThreads == 256, "two children x 128 gather rows per thread block");
+  const int nch = a.child_ptr[f + 1] - a.child_ptr[f];
+  const int k = threadIdx.x >> 7, e = threadIdx.x & 127;
+  if (k < nch) {
+    const int32_t* g = a.gmap + a.gmap_ptr[f] + (int64_t)k * m;
+    kid[threadIdx.x] = e < 64 ? (e < nr ? g[r0 + e] : -1) : (e - 64 < nc ? g[c0 + e - 64] : -1);
+  }
+}
+
+// v[t] += the children's update-block entries that land on the lower-
+// triangle entry (r0 + lane, c0 + wave + 4t) of the tile, child 0 then child
+// 1, from the rows stage_kid_rows put in kid: both children's sixteen loads
+// per thread are in flight together.
+template <typename C>
+__device__ __forceinline__ void add_kids_tile(const KArgs& a, int s, int f, const int* kid, int r0, int c0,
+                                              C (&v)[16]) {
+  const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = r0 + lane;
+  const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
+  C w[2][16];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k < nch) {
+      const int chf = a.child_list[cb + k];
+      const unsigned nu = a.nupd[chf];
+      const __amdgpu_buffer_rsrc_t rs = buffer_of(Ub + a.upd_off[chf], nu * nu * (unsigned)sizeof(C));
+      const int gr = kid[128 * k + lane];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int c = wave + 4 * t;
+        const int gc = kid[128 * k + 64 + c];
+        const bool ok = gr >= 0 && gc >= 0 && r >= c0 + c;
+        w[k][t] = ld_buf<C>(rs, ok ? ((unsigned)gc * nu + (unsigned)gr) * (unsigned)sizeof(C) : kOob);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) w[k][t] = czero<C>();
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) v[t] = cadd(cadd(v[t], w[0][t]), w[1][t]);
+}
+
+// LDS of ASM(I,J): the staged stencils (5 kBW entries), their neighbour rows
+// (4 kBW ints), then the children's gather rows (256 ints).
+template <typename C> __device__ __forceinline__ int* asm_kid_rows(unsigned char* smem) {
+  return reinterpret_cast<int*>(smem + 5 * kBW * sizeof(C) + 4 * kBW * sizeof(int));
+}
+
 // The first part of ASM(I,J) on a pivot column chunk: the original operator
 // entries of its columns (stage_columns), which depend on no other task, so
 // the kernel runs it before the task's dependency wait.  A barrier follows in
 // the caller before task_asm reads them.
 template <typename R>
-__device__ __forceinline__ void asm_stage(const KArgs& a, int s, int f, int J, unsigned char* smem) {
+__device__ __forceinline__ void asm_stage(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int c0 = ch.lo(J), nc = ch.hi(J) - c0;
@@ -1122,14 +1252,15 @@ __device__ __forceinline__ void asm_stage(const KArgs& a, int s, int f, int J, u
     C* sv = reinterpret_cast<C*>(smem);
     stage_columns(a, s, f, c0, nc, sv, reinterpret_cast<int*>(sv + 5 * kBW));
   }
+  const int r0 = ch.lo(I);
+  stage_kid_rows(a, f, ch.m, r0, ch.hi(I) - r0, c0, nc, asm_kid_rows<C>(smem));
 }
 
 // ASM(I,J): the tile's original entries (pivot columns only, from the
 // stencils asm_stage placed in LDS) plus the children's update-block entries
-// that land on it.  Lane = row, wave w takes the columns w, w+4, ...; per
-// child one round of gather-index loads (the row's, and the sixteen columns'
-// which are the same across the wave) is followed by one round of all sixteen
-// value loads, so a tile costs two memory round trips per child.
+// that land on it, from the gather rows asm_stage also staged before the
+// task's wait: after the wait one round of value loads (both children's at
+// once) and one of stores.  Lane = row, wave w takes the columns w, w+4, ...
 template <typename R>
 __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, int J, unsigned char* smem) {
   typedef typename Cx<R>::T C;
@@ -1148,32 +1279,14 @@ __device__ __forceinline__ void task_asm(const KArgs& a, int s, int f, int I, in
     const bool ok = lane < nr && tt < nc && r >= c;
     v[t] = (ok && piv) ? staged_entry(sv, nbv, tt, r, c) : czero<C>();
   }
-  const int32_t* g = a.gmap + a.gmap_ptr[f];
-  const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
-  for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k, g += ch.m) {
-    const int chf = a.child_list[k];
-    const C* Uc = Ub + a.upd_off[chf];
-    const int nu = a.nupd[chf];
-    const int gr = lane < nr ? g[r] : -1;
-    int gc[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int tt = wave + 4 * t;
-      gc[t] = tt < nc ? g[c0 + tt] : -1;
-    }
-    C w[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const bool ok = gr >= 0 && gc[t] >= 0 && r >= c0 + wave + 4 * t;
-      w[t] = ok ? ld_ag(Uc + (int64_t)gc[t] * nu + gr) : czero<C>();
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) v[t] = cadd(v[t], w[t]);
-  }
+  add_kids_tile<C>(a, s, f, asm_kid_rows<C>(smem), r0, c0, v);
+  // pivot columns are written whole (zeros above the diagonal), update
+  // blocks in their lower triangle
+  const TileMem tm = tile_mem<C>(a, s, f, ch, r0, nr, c0, nc);
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
-    const int tt = wave + 4 * t, c = c0 + tt;
-    if (lane < nr && tt < nc && (r >= c || piv)) st_ag(front_elem<C>(a, s, f, ch.p, ch.u, ch.m, r, c), v[t]);
+    const bool ok = piv || r >= c0 + wave + 4 * t;
+    st_buf<C>(tm.rs, ok ? tm.rowoff + t * tm.colstride : kOob, v[t]);
   }
 }
 
@@ -1449,15 +1562,22 @@ __device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O
 template <typename C>
 __device__ __forceinline__ void syrk_load(const C* L, int m, int kb, int kn, int r0, int nr, int c0, int nc,
                                           C (&va)[16], C (&vb)[16], C& dv) {
+  // the block's kn columns as one buffer: columns q >= kn read zero
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t rs = buffer_of(L + (int64_t)kb * m, (unsigned)(kn * m) * (unsigned)sizeof(C));
+  const unsigned cs = sizeof(C), step = 4u * (unsigned)m * cs;
+  unsigned oa = lane < nr ? ((unsigned)(wave * m + r0 + lane)) * cs : kOob;
+  unsigned ob = lane < nc ? ((unsigned)(wave * m + c0 + lane)) * cs : kOob;
+  // the 32 offsets below do not depend on the block: kept opaque here, so
+  // that they are formed load by load rather than hoisted out of the caller's
+  // loop into 32 more live registers
+  asm volatile("" : "+v"(oa), "+v"(ob));
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
-    const int q = wave + 4 * t;
-    const C* col = L + (int64_t)(kb + min(q, kn - 1)) * m;
-    va[t] = (q < kn && lane < nr) ? ld_ag(col + r0 + lane) : czero<C>();
-    vb[t] = (q < kn && lane < nc) ? ld_ag(col + c0 + lane) : czero<C>();
+    va[t] = ld_buf<C>(rs, oa + t * step);
+    vb[t] = ld_buf<C>(rs, ob + t * step);
   }
-  dv = (int)threadIdx.x < kn ? ld_ag(L + (int64_t)(kb + threadIdx.x) * (m + 1)) : czero<C>();
+  dv = ld_buf<C>(rs, threadIdx.x < 64u ? ((unsigned)threadIdx.x * (unsigned)m + kb + threadIdx.x) * cs : kOob);
 }
 
 // O[c][r] += sum_q A[q][r] d_q B[q][c] for LDS-resident 64 x 64 operands
@@ -1522,6 +1642,11 @@ __device__ __forceinline__ void task_tile_update(const KArgs& a, int s, int f, i
     re[bj] = v4{0, 0, 0, 0};
     im[bj] = v4{0, 0, 0, 0};
   }
+  // the first group of a Schur tile assembles it from the children: their
+  // gather rows go to LDS now (the loop's barriers order them before use)
+  const bool first = k0 == 0 && J >= ch.nbk;
+  int* kid = reinterpret_cast<int*>(Ds + kBW);
+  if (first) stage_kid_rows(a, f, m, r0, nr, c0, nc, kid);
   C va[16], vb[16], dv;
   syrk_load(L, m, k0 * kBW, min(kBW, p - k0 * kBW), r0, nr, c0, nc, va, vb, dv);
   for (int k = k0; k < k1; ++k) {
@@ -1547,50 +1672,23 @@ __device__ __forceinline__ void task_tile_update(const KArgs& a, int s, int f, i
       As[(16 * bj + Mfma<R>::row(lane, r)) * kBW + 16 * wave + (lane & 15)] = v;
     }
   __syncthreads();
+  // the tile's lower triangle: read (or assembled from the children), minus
+  // the products, written back
+  const TileMem tm = tile_mem<C>(a, s, f, ch, r0, nr, c0, nc);
   C v[16];
-  C* dst[16];
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int c = wave + 4 * t;
-    const bool ok = c < nc && lane < nr && r0 + lane >= c0 + c;
-    dst[t] = ok ? front_elem<C>(a, s, f, p, u, m, r0 + lane, c0 + c) : nullptr;
-  }
-  if (k0 == 0 && J >= ch.nbk) {
-    // the tile's assembly: the children's update-block entries that land on it
-    // (the ordering of update rows keeps every child entry in its lower triangle)
+  if (first) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) v[t] = czero<C>();
-    const int32_t* g = a.gmap + a.gmap_ptr[f];
-    const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
-    for (int k = a.child_ptr[f]; k < a.child_ptr[f + 1]; ++k, g += m) {
-      const int chf = a.child_list[k];
-      const C* Uc = Ub + a.upd_off[chf];
-      const int nu = a.nupd[chf];
-      const int gr = lane < nr ? g[r0 + lane] : -1;
-      int gc[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int c = wv + 4 * t;
-        gc[t] = c < nc ? g[c0 + c] : -1;
-      }
-      C w[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int c = wv + 4 * t;
-        const bool ok = gr >= 0 && gc[t] >= 0 && r0 + lane >= c0 + c;
-        w[t] = ok ? ld_ag(Uc + (int64_t)gc[t] * nu + gr) : czero<C>();
-      }
-#pragma unroll
-      for (int t = 0; t < 16; ++t) v[t] = cadd(v[t], w[t]);
-    }
+    add_kids_tile<C>(a, s, f, kid, r0, c0, v);
   } else {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) v[t] = dst[t] ? ld_ag(dst[t]) : czero<C>();
+    for (int t = 0; t < 16; ++t)
+      v[t] = ld_buf<C>(tm.rs, r0 + lane >= c0 + wave + 4 * t ? tm.rowoff + t * tm.colstride : kOob);
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t)
-    if (dst[t]) st_ag(dst[t], csub(v[t], As[(wave + 4 * t) * kBW + lane]));
+    st_buf<C>(tm.rs, r0 + lane >= c0 + wave + 4 * t ? tm.rowoff + t * tm.colstride : kOob,
+              csub(v[t], As[(wave + 4 * t) * kBW + lane]));
 }
 
 // FUSED(k): the critical chain of one pivot step in one workgroup,
@@ -1667,7 +1765,7 @@ __global__ __launch_bounds__(kThreads) void k_large_tiles(KArgs a, TileArgs ta, 
     const int type = tk[0], f = tk[1], k = tk[2], I = tk[3], J = tk[4];
     const Chunks ch(a.npiv[f], a.nupd[f]);
     int32_t* st = ta.state + (int64_t)s * ta.ntiles + ta.tile_base[f];
-    if (type == T_ASM) asm_stage<R>(a, s, f, J, smem_raw);  // independent of the wait below
+    if (type == T_ASM) asm_stage<R>(a, s, f, I, J, smem_raw);  // independent of the wait below
     {
       // the task's dependencies, one thread each (each read is a memory
       // round trip; one thread reading them in turn would chain them)
