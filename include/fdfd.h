@@ -143,7 +143,9 @@ typedef struct {
  * max_rhs is not limited by the front sizes: the sweeps hold a front's
  * right-hand-side block in LDS and take the columns in as many passes as
  * needed (fdfd_info.rhs_group per pass); a front whose single column does not
- * fit is refused with FDFD_ERR_ARG.
+ * fit is refused with FDFD_ERR_ARG, and so is a front of m rows with
+ * m * m * (bytes per complex entry) >= 2 GiB (m > 11585 in complex128, about
+ * a 7700 x 7700 grid).
  */
 fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out);
 

@@ -596,9 +596,10 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   // the sweeps take the right-hand sides in groups that fit the LDS (and at
   // most FDFD_SWEEP_RHS at a time); one column of the largest front has to
   P.rhs_cap = std::max(1, env_int("FDFD_SWEEP_RHS", 64));
-  // the tile tasks address a pivot block's 64 columns of a front through one
-  // buffer resource of fewer than 2 GiB
-  if (P.an.max_front >= (1 << 20)) {
+  // the tile tasks address a child's whole update block (and a pivot block's
+  // 64 columns of a front) through one buffer resource of fewer than 2 GiB:
+  // fronts up to 11585 rows in complex128, 16383 in complex64
+  if ((int64_t)P.an.max_front * P.an.max_front * (int64_t)P.csize >= ((int64_t)1 << 31)) {
     delete h;
     return fail(nullptr, FDFD_ERR_ARG, "front too large for the tile kernels");
   }
