@@ -23,6 +23,14 @@ stretched-coordinate PML:
 sampled at cell centres p = i + 1/2 and faces p = i.  This A is the negative of
 the paper's operator in grid units; the sign and the -i omega mu0 dx^2 factor of
 the source only rescale x, F and dF/deps and do not change the method.
+
+TE (Hz) variant (same five-point pattern, the permittivity inside the
+derivatives; the paper states Eq. (1) for E only, so this is a reading):
+  A_TE = Sx_c^-1 Dxb (eps_x Sx_f)^-1 Dxf + Sy_c^-1 Dyb (eps_y Sy_f)^-1 Dyf + omega^2 I
+with eps_x, eps_y on the faces: the mean of the two cells a face separates, and
+a face on the grid edge takes the permittivity of its one cell.  The gradient
+is formed face by face from dF/deps_n = -2 Re(lam^T dA/deps_n x), each face's
+permittivity depending on its one or two cells.
 """
 from __future__ import annotations
 
@@ -103,6 +111,50 @@ def operator_coefficients(nx, ny, npml_x, npml_y, omega, eps):
     diag = omega ** 2 * eps - (xm + xp + ym + yp)
     return {"diag": diag, "xm": xm, "xp": xp, "ym": ym, "yp": yp,
             "nx": nx, "ny": ny}
+
+
+def face_permittivity(eps):
+    """eps on the x faces (ny, nx + 1) and the y faces (ny + 1, nx) of the
+    grid: the mean of the two cells a face separates; a face on the grid
+    edge takes its one cell's value (TE reading)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    ny, nx = eps.shape
+    ex = np.empty((ny, nx + 1))
+    ex[:, 1:nx] = 0.5 * (eps[:, :-1] + eps[:, 1:])
+    ex[:, 0] = eps[:, 0]
+    ex[:, nx] = eps[:, -1]
+    ey = np.empty((ny + 1, nx))
+    ey[1:ny, :] = 0.5 * (eps[:-1, :] + eps[1:, :])
+    ey[0, :] = eps[0, :]
+    ey[ny, :] = eps[-1, :]
+    return ex, ey
+
+
+def operator_coefficients_te(nx, ny, npml_x, npml_y, omega, eps):
+    """Five-point coefficients of the TE operator A_TE, in the same layout as
+    operator_coefficients: the x-face between cells i-1 and i carries
+    1 / (eps_x sx_f[i]), the y-face likewise, and the diagonal is omega^2
+    minus the four couplings."""
+    eps = np.asarray(eps, dtype=np.float64).reshape(ny, nx)
+    sxc, sxf = pml_stretch(nx, npml_x, omega)
+    syc, syf = pml_stretch(ny, npml_y, omega)
+    ex, ey = face_permittivity(eps)
+    xm = 1.0 / (sxc[None, :] * sxf[None, :-1] * ex[:, :-1])
+    xp = 1.0 / (sxc[None, :] * sxf[None, 1:] * ex[:, 1:])
+    ym = 1.0 / (syc[:, None] * syf[:-1, None] * ey[:-1, :])
+    yp = 1.0 / (syc[:, None] * syf[1:, None] * ey[1:, :])
+    diag = omega ** 2 - (xm + xp + ym + yp)
+    return {"diag": diag, "xm": xm, "xp": xp, "ym": ym, "yp": yp,
+            "nx": nx, "ny": ny}
+
+
+def operator(pol, nx, ny, npml_x, npml_y, omega, eps):
+    """Coefficients of the TM (Ez) or TE (Hz) operator."""
+    if pol == "tm":
+        return operator_coefficients(nx, ny, npml_x, npml_y, omega, eps)
+    if pol == "te":
+        return operator_coefficients_te(nx, ny, npml_x, npml_y, omega, eps)
+    raise ValueError("pol must be 'tm' or 'te'")
 
 
 def symmetrizer(nx, ny, npml_x, npml_y, omega):
@@ -217,18 +269,66 @@ def gradient(omega, x, lam):
     return -2.0 * omega ** 2 * np.real(lam * x)
 
 
+def gradient_te(coef, eps, x, lam):
+    """dF/deps_n = -2 Re(lam^T dA_TE/deps_n x) for x, lam (..., N), summed over
+    the leading axes' entries separately (returns (..., N)).
+
+    A face f couples the cells p (before) and q (after) along its axis: it
+    puts a_p = coupling of row p towards q and a_q = coupling of row q towards
+    p off the diagonal and subtracts each from its row's diagonal; both are
+    proportional to 1 / eps_f.  Hence
+        lam^T dA/deps_f x = -(1 / eps_f) [a_p lam_p (x_q - x_p) + a_q lam_q (x_p - x_q)],
+    and eps_f depends on eps_p and eps_q with weight 1/2 each.  A face on the
+    grid edge touches one cell p only: -(1 / eps_f) a_p lam_p (0 - x_p), with
+    weight 1 (eps_f = eps_p).
+    """
+    nx, ny = coef["nx"], coef["ny"]
+    eps = np.asarray(eps, dtype=np.float64).reshape(ny, nx)
+    ex, ey = face_permittivity(eps)
+    shp = x.shape
+    X = np.asarray(x, dtype=np.complex128).reshape(shp[:-1] + (ny, nx))
+    Lm = np.asarray(lam, dtype=np.complex128).reshape(shp[:-1] + (ny, nx))
+    G = np.zeros(X.shape)
+    # interior x-faces between (j, i) = p and (j, i + 1) = q
+    ap, aq = coef["xp"][:, :-1], coef["xm"][:, 1:]
+    xp_, xq = X[..., :, :-1], X[..., :, 1:]
+    lp, lq = Lm[..., :, :-1], Lm[..., :, 1:]
+    t = -(ap * lp * (xq - xp_) + aq * lq * (xp_ - xq)) / ex[:, 1:nx]
+    g = -2.0 * np.real(t)
+    G[..., :, :-1] += 0.5 * g
+    G[..., :, 1:] += 0.5 * g
+    # interior y-faces between (j, i) = p and (j + 1, i) = q
+    ap, aq = coef["yp"][:-1, :], coef["ym"][1:, :]
+    xp_, xq = X[..., :-1, :], X[..., 1:, :]
+    lp, lq = Lm[..., :-1, :], Lm[..., 1:, :]
+    t = -(ap * lp * (xq - xp_) + aq * lq * (xp_ - xq)) / ey[1:ny, :]
+    g = -2.0 * np.real(t)
+    G[..., :-1, :] += 0.5 * g
+    G[..., 1:, :] += 0.5 * g
+    # edge faces: left, right, bottom, top
+    for a_edge, e_edge, sl in ((coef["xm"][:, 0], ex[:, 0], (slice(None), 0)),
+                               (coef["xp"][:, -1], ex[:, nx], (slice(None), nx - 1)),
+                               (coef["ym"][0, :], ey[0, :], (0, slice(None))),
+                               (coef["yp"][-1, :], ey[ny, :], (ny - 1, slice(None)))):
+        idx = (Ellipsis,) + sl
+        t = -(a_edge * Lm[idx] * (0.0 - X[idx])) / e_edge
+        G[idx] += -2.0 * np.real(t)
+    return G.reshape(shp)
+
+
 # ----------------------------------------------------------------------------
 # One design iteration
 # ----------------------------------------------------------------------------
 
-def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None, npml_y=None):
+def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None, npml_y=None, pol="tm"):
     """Factor once per system, solve forward for every RHS, solve the adjoint
     with the same factors, and form the permittivity gradient.
 
     eps: (ny, nx) or (nsys, ny, nx);  b: (nsys, nrhs, N);  c: (N,) objective
     vector, or g: (nsys, nrhs, N) given adjoint sources.  npml is the PML
-    width along x, npml_y along y (default: npml).  Returns a dict with
-    x, lam (nsys, nrhs, N), F (nsys, nrhs) and grad (nsys, N) summed over RHS.
+    width along x, npml_y along y (default: npml); pol "tm" (Ez) or "te" (Hz).
+    Returns a dict with x, lam (nsys, nrhs, N), F (nsys, nrhs) and grad
+    (nsys, N) summed over RHS.
     """
     npml_y = npml if npml_y is None else npml_y
     omegas = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
@@ -241,7 +341,7 @@ def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None, npml_y=None):
     grad = np.zeros((nsys, nx * ny))
     for s in range(nsys):
         e = eps if eps.ndim == 2 else eps[s]
-        coef = operator_coefficients(nx, ny, npml, npml_y, omegas[s], e)
+        coef = operator(pol, nx, ny, npml, npml_y, omegas[s], e)
         lu = BandLU(band_matrix(coef))
         x[s] = lu.solve(b[s])
         if g is None:
@@ -250,13 +350,16 @@ def design_iteration(nx, ny, npml, omegas, eps, b, c=None, g=None, npml_y=None):
         else:
             gs = np.asarray(g, dtype=np.complex128).reshape(nsys, -1, nx * ny)[s]
         lam[s] = lu.solve(gs, transpose=True)
-        grad[s] = gradient(omegas[s], x[s], lam[s]).sum(axis=0)
+        if pol == "tm":
+            grad[s] = gradient(omegas[s], x[s], lam[s]).sum(axis=0)
+        else:
+            grad[s] = gradient_te(coef, e, x[s], lam[s]).sum(axis=0)
     return {"x": x, "lam": lam, "F": F, "grad": grad}
 
 
-def relative_residual(nx, ny, npml, omega, eps, x, b, npml_y=None):
+def relative_residual(nx, ny, npml, omega, eps, x, b, npml_y=None, pol="tm"):
     """||b - A x|| / ||b|| in float64 with the oracle's own operator."""
-    coef = operator_coefficients(nx, ny, npml, npml if npml_y is None else npml_y, omega, eps)
+    coef = operator(pol, nx, ny, npml, npml if npml_y is None else npml_y, omega, eps)
     r = np.asarray(b, dtype=np.complex128) - apply_operator(coef, np.asarray(x, dtype=np.complex128))
     return float(np.linalg.norm(r) / np.linalg.norm(b))
 
