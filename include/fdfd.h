@@ -73,6 +73,20 @@ typedef enum {
                                   /* per argument set (pointers, sizes, omegas, */
                                   /* refinement settings) and replay it; not    */
                                   /* with FDFD_PROFILE or FDFD_TRACE            */
+#define FDFD_POL_TE 8             /* the TE (Hz) operator instead of TM (Ez):   */
+                                  /* the same five-point pattern (one analysis */
+                                  /* serves both) with the permittivity inside */
+                                  /* the derivatives, on the faces (the mean  */
+                                  /* of the two cells a face separates; a grid */
+                                  /* edge face takes its one cell's value):    */
+                                  /* A = Sx_c^-1 Dxb (eps_x Sx_f)^-1 Dxf       */
+                                  /*   + Sy_c^-1 Dyb (eps_y Sy_f)^-1 Dyf       */
+                                  /*   + omega^2 I.  The gradient of           */
+                                  /* fdfd_adjoint_grad then collects each      */
+                                  /* cell's share of its four faces' terms     */
+                                  /* -2 Re(lam^T dA/deps_f x) (the curl-curl   */
+                                  /* operator of Eq. (1) written for H; the    */
+                                  /* paper states E only)                      */
 
 typedef struct {
   int32_t nx, ny;          /* grid cells, nx, ny >= 2                           */
@@ -83,6 +97,7 @@ typedef struct {
   int32_t device;          /* HIP device ordinal, -1 = current device          */
   int32_t leaf;            /* cells per undivided dissection leaf, 0 = default */
   int32_t flags;           /* FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH */
+                           /* | FDFD_POL_TE                                     */
   int32_t small_lds;       /* LDS bytes a front may use in the one-workgroup-  */
                            /* per-front kernel (the bottom levels whose fronts */
                            /* all fit run there, the rest as 64 x 64 tile     */

@@ -395,7 +395,7 @@ fdfd_status check_desc(const fdfd_desc* d) {
   if (d->small_lds < -1) return fail(nullptr, FDFD_ERR_ARG, "small_lds must be >= -1");
   if (d->reserved != 0) return fail(nullptr, FDFD_ERR_ARG, "reserved must be 0");
   if (d->mem_cap_bytes < 0) return fail(nullptr, FDFD_ERR_ARG, "mem_cap_bytes must be >= 0");
-  if (d->flags & ~(FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH))
+  if (d->flags & ~(FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH | FDFD_POL_TE))
     return fail(nullptr, FDFD_ERR_ARG, "unknown desc flags");
   if ((d->flags & FDFD_GRAPH) && ((d->flags & FDFD_PROFILE) || std::getenv("FDFD_TRACE")))
     return fail(nullptr, FDFD_ERR_ARG, "FDFD_GRAPH cannot be combined with FDFD_PROFILE or FDFD_TRACE");

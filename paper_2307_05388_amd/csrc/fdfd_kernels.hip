@@ -90,6 +90,7 @@ struct KArgs {
   DevStatus* st;
   double tau;
   int32_t nfronts;
+  int32_t te;  // 1: the TE (Hz) operator, 0: TM (Ez)
 };
 
 // ---------------------------------------------------------------------------
@@ -99,6 +100,22 @@ struct Stencil {
   double2 diag, c[4];  // couplings to x-1, x+1, y-1, y+1
 };
 
+// The permittivity on the four faces of cell (i, j) of system s (TE): the
+// mean of the two cells a face separates, the cell's own on the grid edge.
+// Both cells of a face evaluate the same expression, so the couplings of S*A
+// stay exactly symmetric.
+__device__ __forceinline__ void face_eps(const KArgs& a, int s, int n, double (&ef)[4]) {
+  const int nx = a.nx, i = n % nx, j = n / nx;
+  const double* E = a.eps + (int64_t)s * a.N;
+  const double e = E[n];
+  ef[0] = i > 0 ? 0.5 * (e + E[n - 1]) : e;
+  ef[1] = i < nx - 1 ? 0.5 * (e + E[n + 1]) : e;
+  ef[2] = j > 0 ? 0.5 * (e + E[n - nx]) : e;
+  ef[3] = j < a.ny - 1 ? 0.5 * (e + E[n + nx]) : e;
+}
+
+// TM (Ez):  S*A = Sy_c Dxb Sx_f^-1 Dxf + Sx_c Dyb Sy_f^-1 Dyf + omega^2 eps Sx_c Sy_c
+// TE (Hz):  S*A = Sy_c Dxb (eps_x Sx_f)^-1 Dxf + Sx_c Dyb (eps_y Sy_f)^-1 Dyf + omega^2 Sx_c Sy_c
 __device__ __forceinline__ Stencil stencil_at(const KArgs& a, int s, int n) {
   const int nx = a.nx, ny = a.ny;
   const int i = n % nx, j = n / nx;
@@ -112,9 +129,18 @@ __device__ __forceinline__ Stencil stencil_at(const KArgs& a, int s, int n) {
   S.c[2] = ddiv(sxc, syf0);
   S.c[3] = ddiv(sxc, syf1);
   const double w = a.omega[s];
-  const double e = a.eps[(int64_t)s * a.N + n];
   const double2 sc = dmul(sxc, syc);
-  double2 d = make_double2(w * w * e * sc.x, w * w * e * sc.y);
+  double2 d;
+  if (a.te) {
+    double ef[4];
+    face_eps(a, s, n, ef);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S.c[k] = make_double2(S.c[k].x / ef[k], S.c[k].y / ef[k]);
+    d = make_double2(w * w * sc.x, w * w * sc.y);
+  } else {
+    const double e = a.eps[(int64_t)s * a.N + n];
+    d = make_double2(w * w * e * sc.x, w * w * e * sc.y);
+  }
   d = dsub(d, dadd(dadd(S.c[0], S.c[1]), dadd(S.c[2], S.c[3])));
   S.diag = d;
   return S;
@@ -3074,23 +3100,60 @@ __global__ void k_ir_end(DevStatus* st, int mode, int with_ir) {
 }
 
 // lam = S lam' ; grad_n (+)= -2 w^2 sum_rhs Re(lam_n x_n), one system per grid row
-__global__ __launch_bounds__(kThreads) void k_gradient(KArgs a, const double2* x, const double2* lsym,
-                                                        int nrhs, double2* lam_out, double* grad,
-                                                        int accumulate) {
-  const int s = blockIdx.y;
-  const double w = a.omega[s];
-  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-       n += (int64_t)gridDim.x * blockDim.x) {
-    const double2 S = sym_scale(a, s, (int)n);
-    double gsum = 0.0;
+// dF/deps_n of system s summed over the right-hand sides, from x and the
+// symmetric adjoint solution lsym (lambda = S lsym); lambda goes to lam_out
+// when asked for.
+//   TM: -2 omega^2 Re(lambda_n x_n)                                  (Eq. 3)
+//   TE: eps_n enters the four faces of cell n.  Through a face shared with
+//       cell m it contributes -(c / eps_f) Re((x_m - x_n)(lsym_m - lsym_n)),
+//       c the face's coupling in S*A and eps_f its permittivity (half of
+//       the face's -2 Re(lambda^T dA/deps_f x), the face permittivity being
+//       the mean of its two cells); through a grid-edge face, whose
+//       permittivity is the cell's own, -(2 c / eps_f) Re(x_n lsym_n).
+__device__ __forceinline__ double grad_cell(const KArgs& a, int s, int64_t n, const double2* x,
+                                            const double2* lsym, int nrhs, double2* lam_out) {
+  const double2 S = sym_scale(a, s, (int)n);
+  double g = 0.0;
+  if (!a.te) {
+    const double w = a.omega[s];
     for (int r = 0; r < nrhs; ++r) {
       const int64_t o = ((int64_t)s * nrhs + r) * a.N + n;
       const double2 lam = dmul(S, lsym[o]);
       if (lam_out) lam_out[o] = lam;
       const double2 xv = x[o];
-      gsum += lam.x * xv.x - lam.y * xv.y;
+      g += lam.x * xv.x - lam.y * xv.y;
     }
-    const double gv = -2.0 * w * w * gsum;
+    return -2.0 * w * w * g;
+  }
+  const Stencil st = stencil_at(a, s, (int)n);
+  double ef[4];
+  face_eps(a, s, (int)n, ef);
+  const int nx = a.nx, i = (int)(n % nx), j = (int)(n / nx);
+  const bool in[4] = {i > 0, i < nx - 1, j > 0, j < a.ny - 1};
+  const int64_t step[4] = {-1, 1, -(int64_t)nx, (int64_t)nx};
+  for (int r = 0; r < nrhs; ++r) {
+    const int64_t o = ((int64_t)s * nrhs + r) * a.N + n;
+    const double2 xn = x[o], ln = lsym[o];
+    if (lam_out) lam_out[o] = dmul(S, ln);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 dx = in[k] ? dsub(x[o + step[k]], xn) : make_double2(-xn.x, -xn.y);
+      const double2 dl = in[k] ? dsub(lsym[o + step[k]], ln) : make_double2(-ln.x, -ln.y);
+      const double2 cw = make_double2(st.c[k].x / ef[k], st.c[k].y / ef[k]);
+      const double2 p = dmul(cw, dmul(dx, dl));
+      g -= (in[k] ? 1.0 : 2.0) * p.x;
+    }
+  }
+  return g;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gradient(KArgs a, const double2* x, const double2* lsym,
+                                                        int nrhs, double2* lam_out, double* grad,
+                                                        int accumulate) {
+  const int s = blockIdx.y;
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const double gv = grad_cell(a, s, n, x, lsym, nrhs, lam_out);
     double* gp = grad + (int64_t)s * a.N + n;
     *gp = accumulate ? *gp + gv : gv;
   }
@@ -3103,19 +3166,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient_sum(KArgs a, const double
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
        n += (int64_t)gridDim.x * blockDim.x) {
     double tot = 0.0;
-    for (int s = 0; s < a.nsys; ++s) {
-      const double w = a.omega[s];
-      const double2 S = sym_scale(a, s, (int)n);
-      double gsum = 0.0;
-      for (int r = 0; r < nrhs; ++r) {
-        const int64_t o = ((int64_t)s * nrhs + r) * a.N + n;
-        const double2 lam = dmul(S, lsym[o]);
-        if (lam_out) lam_out[o] = lam;
-        const double2 xv = x[o];
-        gsum += lam.x * xv.x - lam.y * xv.y;
-      }
-      tot += -2.0 * w * w * gsum;
-    }
+    for (int s = 0; s < a.nsys; ++s) tot += grad_cell(a, s, n, x, lsym, nrhs, lam_out);
     grad[n] = accumulate ? grad[n] + tot : tot;
   }
 }
@@ -3157,6 +3208,7 @@ KArgs make_args(Plan& P) {
   // pivot threshold tau * ||SA||_max, by default tau = sqrt(unit roundoff)
   a.tau = P.pivot_tau;
   a.nfronts = P.an.nfronts;
+  a.te = (P.desc.flags & FDFD_POL_TE) ? 1 : 0;
   return a;
 }
 

@@ -20,6 +20,7 @@ FDFD_C128, FDFD_C64_IR = 0, 1
 FDFD_ANALYZE_HOST_ONLY = 1
 FDFD_PROFILE = 2
 FDFD_GRAPH = 4
+FDFD_POL_TE = 8
 FDFD_GRAD_ACCUMULATE, FDFD_GRAD_SUM_SYSTEMS = 1, 2
 FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE, FDFD_TABLE_TASKS = 0, 1, 2, 3
 
@@ -140,9 +141,12 @@ class Plan:
 
     def __init__(self, nx, ny, npml_x, npml_y=None, nsys=1, max_rhs=1, prec="c128",
                  device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False, graph=False,
-                 small_lds=0, tuned=True):
+                 small_lds=0, tuned=True, pol="tm"):
         """With leaf = small_lds = 0 and tuned=True the front layout comes from
-        the autotuner's table for this workload when it has an entry."""
+        the autotuner's table for this workload when it has an entry.  pol:
+        "tm" (Ez) or "te" (Hz, FDFD_POL_TE)."""
+        if pol not in ("tm", "te"):
+            raise ValueError(f"unknown polarisation {pol!r}")
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         if tuned and leaf == 0 and small_lds == 0 and not host_only:
@@ -154,7 +158,7 @@ class Plan:
                  nsys=nsys, max_rhs=max_rhs, prec=FDFD_C64_IR if prec in ("c64", FDFD_C64_IR) else FDFD_C128,
                  device=device, leaf=leaf, small_lds=small_lds,
                  flags=(FDFD_ANALYZE_HOST_ONLY if host_only else 0) | (FDFD_PROFILE if profile else 0)
-                 | (FDFD_GRAPH if graph else 0),
+                 | (FDFD_GRAPH if graph else 0) | (FDFD_POL_TE if pol == "te" else 0),
                  mem_cap_bytes=mem_cap_bytes)
         if prec not in ("c64", "c128", FDFD_C64_IR, FDFD_C128):
             raise ValueError(f"unknown precision {prec!r}")
@@ -164,6 +168,7 @@ class Plan:
         self.nx, self.ny, self.N = nx, ny, nx * ny
         self.nsys, self.max_rhs = nsys, max_rhs
         self.prec = "c64" if d.prec == FDFD_C64_IR else "c128"
+        self.pol = pol
         self.host_only = host_only
         self.generation = 0
 
