@@ -246,7 +246,8 @@ def main():
                       "n_perturbed": r["info"]["n_perturbed"], "gate": gate[m]}
                   for m, r in results.items()},
         "analysis": {k: rb["info"][k] for k in ("nfronts", "nlevels", "nnz_factor", "refactor_flops",
-                                                "factor_bytes", "leaf", "small_levels")},
+                                                "factor_bytes", "leaf", "small_levels", "small_lds",
+                                                "syrk_group", "split_kb", "block_split")},
     }
     if not args.no_caching:
         out["caching"] = caching_split(args, p, best, eps_all, b, c, omegas, rb["ms_per_step"])

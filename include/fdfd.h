@@ -104,6 +104,17 @@ typedef struct {
                            /* tasks); 0 = default (64 KiB), -1 = tiles only   */
   int32_t reserved;        /* must be 0                                         */
   int64_t mem_cap_bytes;   /* refuse plans needing more device memory, 0 = off  */
+  /* Schedule knobs (layout of the work only, never the solution; 0 = the   */
+  /* default, or the environment variable of the same name if it is set):   */
+  int32_t syrk_group;      /* pivot blocks one Schur-tile task accumulates     */
+                           /* before it writes the tile (default 8; -1 = all) */
+  int32_t split_kb;        /* L21 size (KiB) from which the sweeps take a      */
+                           /* front's update rows as 64-row chunk items       */
+                           /* (default 128; -1 = never)                       */
+  int32_t block_split;     /* pivot blocks from which the sweeps take a front's */
+                           /* pivot part one 64-row block per item (default 6; */
+                           /* -1 = never)                                      */
+  int32_t reserved2;       /* must be 0                                         */
 } fdfd_desc;
 
 typedef struct fdfd_plan_s* fdfd_plan;
@@ -135,7 +146,10 @@ typedef struct {
   int32_t rhs_group;         /* right-hand sides per sweep pass at max_rhs: the   */
                              /* sweeps hold a front's right-hand-side block in   */
                              /* LDS, so more columns take more passes            */
-  int32_t reserved_info;
+  int32_t syrk_group;        /* the schedule knobs in effect (fdfd_desc; -1:     */
+  int32_t split_kb;          /* all blocks / never)                              */
+  int32_t block_split;
+  int32_t small_lds;         /* the one-workgroup kernel's LDS budget in effect  */
 } fdfd_info;
 
 /*
@@ -146,11 +160,11 @@ typedef struct {
  * Read here from the environment, for measurement only (all optional):
  *   FDFD_SMALL_LDS  LDS budget (bytes) of the one-workgroup front kernel when
  *                   desc->small_lds is 0;
- *   FDFD_SPLIT_KB   L21 size (KiB) from which the sweeps split a front into a
- *                   pivot item and update-row chunks (default 128);
- *   FDFD_BLOCK_SPLIT pivot blocks from which the sweeps take a front's pivot
- *                   part one 64-row block per item (default 6, 0 = never);
- *   FDFD_SYRK_GROUP pivot blocks one Schur-tile task accumulates (default 8);
+ *   FDFD_SPLIT_KB   desc->split_kb when that is 0;
+ *   FDFD_BLOCK_SPLIT, FDFD_SYRK_GROUP  the schedule knobs of fdfd_desc of
+ *                   the same name when the desc leaves them at 0 (for
+ *                   FDFD_BLOCK_SPLIT and FDFD_SYRK_GROUP, 0 means never /
+ *                   all blocks);
  *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
  *                   passes also never take more than fit the LDS);
  *   FDFD_PIVOT_TAU  static pivot threshold relative to the matrix norm;

@@ -1,19 +1,28 @@
-"""Autotuner for the front layout of the multifrontal solver.
+"""Autotuner for the layout of the multifrontal solver's work.
 
-Two knobs shape the fronts the GPU factors and sweeps:
-  * leaf       -- cells per undivided nested-dissection leaf: the size of the
-                  dense leaf fronts and the height of the separator tree;
-  * small_lds  -- the LDS budget of the one-workgroup-per-front kernel: the
-                  bottom levels whose fronts all fit run there, every level
-                  above runs as a task graph over 64 x 64 tiles.
-Both change only the factor's layout, never the solution.  The tuner times
-whole design iterations (refactor + forward solve + objective + adjoint solve +
-gradient, the unit of the paper's caching experiments) for each candidate on
-the caller's GPU, with the caller's workload, and keeps the fastest.  Results
-are cached in a JSON file keyed by grid, batch shape and precision, and the
-committed table ``tuned.json`` next to this module holds the choices measured
-on MI355X for the standard workloads; ``Plan`` consults it when the caller
-leaves both knobs at 0.
+Five knobs shape what the GPU factors and sweeps; none changes the solution:
+  * leaf        -- cells per undivided nested-dissection leaf: the size of the
+                   dense leaf fronts and the height of the separator tree;
+  * small_lds   -- the LDS budget of the one-workgroup-per-front kernel: the
+                   bottom levels whose fronts all fit run there, every level
+                   above runs as a task graph over 64 x 64 tiles;
+  * syrk_group  -- pivot blocks a Schur-tile task accumulates on the matrix
+                   cores before it writes the tile (deeper: fewer tile reads
+                   and writes; shallower: more tasks to spread);
+  * split_kb    -- L21 size from which the sweeps take a front's update rows
+                   as 64-row chunk items of their own;
+  * block_split -- pivot blocks from which the sweeps take a front's pivot
+                   part one 64-row block per item.
+(The tile width itself, 64, is built into the kernels' register and LDS
+layouts and is not a knob.)  The tuner times whole design iterations
+(refactor + forward solve + objective + adjoint solve + gradient, the unit of
+the paper's caching experiments) on the caller's GPU with the caller's
+workload: first every (leaf, small_lds) pair, then, at the best pair, each
+schedule knob in turn over a few values, keeping the fastest.  Results are
+keyed by GPU architecture, grid, batch shape and precision; the committed
+table ``tuned.json`` next to this module holds the choices measured on MI355X
+(gfx950) for the standard workloads, and ``Plan`` consults it when the caller
+leaves every knob at 0.
 """
 from __future__ import annotations
 
@@ -27,10 +36,25 @@ TABLE = os.path.join(_PKG, "tuned.json")
 
 LEAVES = (16, 25, 36, 49, 64)
 SMALL_LDS = (-1, 32768, 65536, 98304)
+SYRK_GROUPS = (4, 8, 16)
+SPLIT_KBS = (64, 128, 256, -1)
+BLOCK_SPLITS = (4, 6, 10, -1)
+KNOBS = ("leaf", "small_lds", "syrk_group", "split_kb", "block_split")
 
 
-def key(nx, ny, npml, nsys, nrhs, prec):
-    return f"{nx}x{ny}/pml{npml}/sys{nsys}/rhs{nrhs}/{prec}"
+def device_arch():
+    """The current GPU's architecture name (e.g. gfx950), or None."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return None
+
+
+def key(arch, nx, ny, npml, nsys, nrhs, prec):
+    return f"{arch}/{nx}x{ny}/pml{npml}/sys{nsys}/rhs{nrhs}/{prec}"
 
 
 def _load(path):
@@ -41,10 +65,15 @@ def _load(path):
         return {}
 
 
-def lookup(nx, ny, npml, nsys, nrhs, prec, path=TABLE):
-    """Tuned (leaf, small_lds) for this workload, or None."""
-    e = _load(path).get(key(nx, ny, npml, nsys, nrhs, prec))
-    return (int(e["leaf"]), int(e["small_lds"])) if e else None
+def lookup(nx, ny, npml, nsys, nrhs, prec, path=TABLE, arch=None):
+    """The tuned knobs {leaf, small_lds, syrk_group, split_kb, block_split}
+    for this workload on this GPU architecture (default: the current
+    device's), or None."""
+    arch = arch or device_arch()
+    if arch is None:
+        return None
+    e = _load(path).get(key(arch, nx, ny, npml, nsys, nrhs, prec))
+    return {k: int(e[k]) for k in KNOBS} if e else None
 
 
 def time_iterations(plan, eps_list, b, c, omegas, max_ir=0, tol=1e-10, warmup=2):
@@ -78,17 +107,20 @@ def time_iterations(plan, eps_list, b, c, omegas, max_ir=0, tol=1e-10, warmup=2)
 
 
 def autotune(p, prec="c128", max_ir=0, tol=1e-10, iters=6, leaves=LEAVES, small_lds=SMALL_LDS,
-             cache=None, verbose=False):
-    """Time every (leaf, small_lds) candidate on problem p (problems.Problem)
-    and return {"leaf", "small_lds", "ms", "table"}.  Candidates whose schedule
-    coincides with one already timed (same leaf, same number of bottom levels in
-    the one-workgroup kernel) are skipped.  With cache=path the result is read
-    from / merged into that JSON file."""
+             syrk_groups=SYRK_GROUPS, split_kbs=SPLIT_KBS, block_splits=BLOCK_SPLITS, cache=None,
+             verbose=False):
+    """Tune problem p (problems.Problem) on the current GPU and return
+    {knobs..., "ms", "table"}: every (leaf, small_lds) pair (pairs whose
+    schedule coincides with one already timed -- same leaf, same number of
+    bottom levels in the one-workgroup kernel -- are skipped), then each of
+    syrk_group, split_kb, block_split in turn at the best setting so far.
+    With cache=path the result is read from / merged into that JSON file."""
     import torch
     from . import problems as P
     from .fdfd import Plan
 
-    k = key(p.nx, p.ny, p.npml, p.nsys, p.nrhs, prec)
+    arch = device_arch()
+    k = key(arch, p.nx, p.ny, p.npml, p.nsys, p.nrhs, prec)
     if cache:
         hit = _load(cache).get(k)
         if hit:
@@ -99,27 +131,47 @@ def autotune(p, prec="c128", max_ir=0, tol=1e-10, iters=6, leaves=LEAVES, small_
     c = torch.from_numpy(P.objective_vector(p)).to(dev)
     om = P.omegas(p)
     table = []
+
+    def run(cfg, plan=None):
+        plan = plan or Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, tuned=False, **cfg)
+        levels = plan.query()["small_levels"]
+        ms = time_iterations(plan, eps_list, b, c, om, max_ir=max_ir, tol=tol)
+        info = plan.query()
+        plan.close()
+        # the values in effect (a 0 in cfg stands for the library's default)
+        row = {kk: int(info[kk]) for kk in KNOBS}
+        row.update(small_levels=levels, ms=ms, status=info["status_str"])
+        table.append(row)
+        if verbose:
+            print("autotune", k, row, flush=True)
+        return row
+
+    def good(r):
+        return r["status"] in ("ok", "pivots perturbed")
+
+    base = {"syrk_group": 0, "split_kb": 0, "block_split": 0}
     for leaf in leaves:
         seen = set()
         for sl in small_lds:
-            plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, leaf=leaf, small_lds=sl)
+            cfg = dict(base, leaf=leaf, small_lds=sl)
+            plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, tuned=False, **cfg)
             levels = plan.query()["small_levels"]
             if levels in seen:
                 plan.close()
                 continue
             seen.add(levels)
-            ms = time_iterations(plan, eps_list, b, c, om, max_ir=max_ir, tol=tol)
-            info = plan.query()
-            plan.close()
-            row = {"leaf": leaf, "small_lds": sl, "small_levels": levels, "ms": ms,
-                   "status": info["status_str"]}
-            table.append(row)
-            if verbose:
-                print("autotune", k, row, flush=True)
-    ok = [r for r in table if r["status"] in ("ok", "pivots perturbed")]
-    best = min(ok, key=lambda r: r["ms"])
-    out = {"leaf": best["leaf"], "small_lds": best["small_lds"], "ms": best["ms"], "max_ir": max_ir,
-           "ir_tol": tol, "table": table}
+            run(cfg, plan)
+    best = min(filter(good, table), key=lambda r: r["ms"])
+    for name, values in (("syrk_group", syrk_groups), ("split_kb", split_kbs), ("block_split", block_splits)):
+        for v in values:
+            cfg = {kk: best[kk] for kk in KNOBS}
+            cfg[name] = v
+            if any(all(r[kk] == cfg[kk] for kk in KNOBS) for r in table):
+                continue
+            run(cfg)
+        best = min(filter(good, table), key=lambda r: r["ms"])
+    out = {kk: best[kk] for kk in KNOBS}
+    out.update(ms=best["ms"], max_ir=max_ir, ir_tol=tol, arch=arch, table=table)
     if cache:
         d = _load(cache)
         d[k] = out
@@ -131,13 +183,14 @@ def autotune(p, prec="c128", max_ir=0, tol=1e-10, iters=6, leaves=LEAVES, small_
 
 
 def main(argv=None):
-    """python -m paper_2307_05388_amd.autotune --workloads plain300,mux400 --out tuned.json"""
+    """python -m paper_2307_05388_amd.autotune --workloads small60,plain300,diff500,mux400,large2000"""
     import argparse
     from . import problems as P
     ap = argparse.ArgumentParser(description=main.__doc__)
-    ap.add_argument("--workloads", default="plain300,diff500,mux400")
+    ap.add_argument("--workloads", default="small60,plain300,diff500,mux400,large2000")
     ap.add_argument("--precs", default="c128,c64")
-    ap.add_argument("--max-ir", type=int, default=4, help="refinement steps for the complex64 form")
+    ap.add_argument("--max-ir-c128", type=int, default=2, help="refinement steps for the complex128 form")
+    ap.add_argument("--max-ir-c64", type=int, default=16, help="refinement steps for the complex64 form")
     ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--iters", type=int, default=6)
     ap.add_argument("--out", default=TABLE)
@@ -145,9 +198,10 @@ def main(argv=None):
     for name in a.workloads.split(","):
         p = P.make_problem(name)
         for prec in a.precs.split(","):
-            r = autotune(p, prec=prec, max_ir=a.max_ir if prec == "c64" else 0, tol=a.ir_tol, iters=a.iters,
+            r = autotune(p, prec=prec, max_ir=a.max_ir_c64 if prec == "c64" else a.max_ir_c128, tol=a.ir_tol,
+                         iters=a.iters,
                          cache=a.out, verbose=True)
-            print(name, prec, "->", {k: r[k] for k in ("leaf", "small_lds", "ms")}, flush=True)
+            print(name, prec, "->", {k: r[k] for k in KNOBS + ("ms",)}, flush=True)
 
 
 if __name__ == "__main__":

@@ -393,7 +393,9 @@ fdfd_status check_desc(const fdfd_desc* d) {
   if (d->prec != FDFD_C128 && d->prec != FDFD_C64_IR) return fail(nullptr, FDFD_ERR_ARG, "unknown precision");
   if (d->leaf < 0) return fail(nullptr, FDFD_ERR_ARG, "leaf must be >= 0");
   if (d->small_lds < -1) return fail(nullptr, FDFD_ERR_ARG, "small_lds must be >= -1");
-  if (d->reserved != 0) return fail(nullptr, FDFD_ERR_ARG, "reserved must be 0");
+  if (d->reserved != 0 || d->reserved2 != 0) return fail(nullptr, FDFD_ERR_ARG, "reserved fields must be 0");
+  if (d->syrk_group < -1 || d->split_kb < -1 || d->block_split < -1)
+    return fail(nullptr, FDFD_ERR_ARG, "schedule knobs must be >= -1");
   if (d->mem_cap_bytes < 0) return fail(nullptr, FDFD_ERR_ARG, "mem_cap_bytes must be >= 0");
   if (d->flags & ~(FDFD_ANALYZE_HOST_ONLY | FDFD_PROFILE | FDFD_GRAPH | FDFD_POL_TE))
     return fail(nullptr, FDFD_ERR_ARG, "unknown desc flags");
@@ -461,7 +463,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   }
   P.profile = (desc->flags & FDFD_PROFILE) != 0;
   // FDFD_SYRK_GROUP: pivot blocks per Schur-complement task (0 = all of them)
-  P.syrk_group = env_int("FDFD_SYRK_GROUP", fdfd::kSyrkGroup);
+  P.syrk_group = desc->syrk_group != 0 ? desc->syrk_group : env_int("FDFD_SYRK_GROUP", fdfd::kSyrkGroup);
   if (P.syrk_group <= 0) P.syrk_group = 1 << 20;
   if (P.host_only) {
     // the schedule a device plan with the default LDS budgets would run
@@ -513,6 +515,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   // a few hundred bytes stay free for the kernels' static LDS
   const size_t lds_dyn = (size_t)lds_limit - 512;
   small_cap = std::min(small_cap, lds_dyn);
+  P.small_lds = small_cap == 0 ? -1 : (int)small_cap;
 
 
   std::vector<int32_t> tasks, tile_base, is_tiled;
@@ -537,8 +540,13 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     int nc_total = 0, nb_total = 0;
     // FDFD_SPLIT_KB: the L21 size (KiB) from which a front is split;
     // FDFD_BLOCK_SPLIT: pivot blocks from which the pivot part is split (0 = never)
-    const int64_t split_bytes = (int64_t)env_int("FDFD_SPLIT_KB", (int)(fdfd::kSplitBytes >> 10)) << 10;
-    const int block_split = env_int("FDFD_BLOCK_SPLIT", fdfd::kBlockSplit);
+    const int split_kb =
+        desc->split_kb != 0 ? desc->split_kb : env_int("FDFD_SPLIT_KB", (int)(fdfd::kSplitBytes >> 10));
+    const int64_t split_bytes = split_kb < 0 ? INT64_MAX : (int64_t)split_kb << 10;
+    const int block_split = desc->block_split != 0 ? (desc->block_split < 0 ? 0 : desc->block_split)
+                                                   : env_int("FDFD_BLOCK_SPLIT", fdfd::kBlockSplit);
+    P.split_kb = split_kb < 0 ? -1 : split_kb;
+    P.block_split = block_split > 0 ? block_split : -1;
     for (int k = nlow; k < P.an.nfronts; ++k) {
       const int f = P.an.level_fronts[k];
       const int64_t p = P.an.npiv[f], u = P.an.nupd[f];
@@ -874,7 +882,10 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   info->rel_residual_adjoint = -1.0;
   info->refactor_ms = info->solve_ms = info->adjoint_ms = -1.0;
   info->rhs_group = P.rhs_group;
-  info->reserved_info = 0;
+  info->syrk_group = P.syrk_group >= (1 << 20) ? -1 : P.syrk_group;
+  info->split_kb = P.split_kb;
+  info->block_split = P.block_split;
+  info->small_lds = P.small_lds;
   if (P.host_only) return FDFD_OK;
   DeviceGuard guard(P.device);
   hipError_t e = hipMemcpyAsync(P.status_host, P.status, sizeof(fdfd::DevStatus), hipMemcpyDeviceToHost,

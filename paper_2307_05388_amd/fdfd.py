@@ -36,7 +36,9 @@ class Desc(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("leaf", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("small_lds", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("mem_cap_bytes", ctypes.c_int64)]
+                ("mem_cap_bytes", ctypes.c_int64),
+                ("syrk_group", ctypes.c_int32), ("split_kb", ctypes.c_int32),
+                ("block_split", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -51,7 +53,8 @@ class Info(ctypes.Structure):
                 ("rel_residual_solve", ctypes.c_double), ("rel_residual_adjoint", ctypes.c_double),
                 ("device_flags", ctypes.c_int32), ("small_levels", ctypes.c_int32),
                 ("refactor_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
-                ("rhs_group", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
+                ("rhs_group", ctypes.c_int32), ("syrk_group", ctypes.c_int32), ("split_kb", ctypes.c_int32),
+                ("block_split", ctypes.c_int32), ("small_lds", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -141,22 +144,27 @@ class Plan:
 
     def __init__(self, nx, ny, npml_x, npml_y=None, nsys=1, max_rhs=1, prec="c128",
                  device=-1, leaf=0, host_only=False, mem_cap_bytes=0, profile=False, graph=False,
-                 small_lds=0, tuned=True, pol="tm"):
-        """With leaf = small_lds = 0 and tuned=True the front layout comes from
-        the autotuner's table for this workload when it has an entry.  pol:
-        "tm" (Ez) or "te" (Hz, FDFD_POL_TE)."""
+                 small_lds=0, tuned=True, pol="tm", syrk_group=0, split_kb=0, block_split=0):
+        """With every layout knob at 0 (leaf, small_lds, syrk_group, split_kb,
+        block_split) and tuned=True the layout comes from the autotuner's
+        table for this GPU and workload when it has an entry.  pol: "tm" (Ez)
+        or "te" (Hz, FDFD_POL_TE)."""
         if pol not in ("tm", "te"):
             raise ValueError(f"unknown polarisation {pol!r}")
         self._lib = load_library()
         self._h = ctypes.c_void_p()
-        if tuned and leaf == 0 and small_lds == 0 and not host_only:
+        self.tuned_entry = None
+        if tuned and (leaf, small_lds, syrk_group, split_kb, block_split) == (0, 0, 0, 0, 0):
             from .autotune import lookup
             hit = lookup(nx, ny, npml_x, nsys, max_rhs, "c64" if prec in ("c64", FDFD_C64_IR) else "c128")
             if hit:
-                leaf, small_lds = hit
+                leaf, small_lds = hit["leaf"], hit["small_lds"]
+                syrk_group, split_kb, block_split = hit["syrk_group"], hit["split_kb"], hit["block_split"]
+                self.tuned_entry = hit
         d = Desc(nx=nx, ny=ny, npml_x=npml_x, npml_y=npml_x if npml_y is None else npml_y,
                  nsys=nsys, max_rhs=max_rhs, prec=FDFD_C64_IR if prec in ("c64", FDFD_C64_IR) else FDFD_C128,
                  device=device, leaf=leaf, small_lds=small_lds,
+                 syrk_group=syrk_group, split_kb=split_kb, block_split=block_split,
                  flags=(FDFD_ANALYZE_HOST_ONLY if host_only else 0) | (FDFD_PROFILE if profile else 0)
                  | (FDFD_GRAPH if graph else 0) | (FDFD_POL_TE if pol == "te" else 0),
                  mem_cap_bytes=mem_cap_bytes)

@@ -23,12 +23,15 @@ def make_plan(p, prec="c128", max_rhs=None, leaf=0, small_lds=None, like=None):
     of p and q are computed identically)."""
     from paper_2307_05388_amd.fdfd import Plan
     sl = 0 if small_lds is None else (-1 if small_lds == 0 else small_lds)
+    knobs = {}
     if like is not None and leaf == 0 and small_lds is None:
         from paper_2307_05388_amd.autotune import lookup
         hit = lookup(like.nx, like.ny, like.npml, like.nsys, like.nrhs, prec)
         if hit:
-            leaf, sl = hit
-    return Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=max_rhs or p.nrhs, prec=prec, leaf=leaf, small_lds=sl)
+            leaf, sl = hit["leaf"], hit["small_lds"]
+            knobs = {k: hit[k] for k in ("syrk_group", "split_kb", "block_split")}
+    return Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=max_rhs or p.nrhs, prec=prec, leaf=leaf, small_lds=sl,
+                **knobs)
 
 
 def gpu_iteration(plan, p, eps, b, g=None, c=None, max_ir=0, tol=0.0):

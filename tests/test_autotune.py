@@ -1,28 +1,40 @@
 """The autotuner's table and lookup (CPU).  The timing itself runs on the GPU
-(tests/test_gpu_workloads.py uses the tuned layouts through Plan's default)."""
+(the GPU tests and the benchmark use the tuned layouts through Plan's
+default)."""
 import json
 
 from paper_2307_05388_amd import autotune
 from paper_2307_05388_amd import problems as P
 
+ARCH = "gfx950"
+
 
 def test_committed_table_covers_standard_workloads():
     table = json.load(open(autotune.TABLE))
-    for name in ("plain300", "diff500", "mux400"):
+    for name in ("small60", "plain300", "diff500", "mux400", "large2000"):
         p = P.make_problem(name)
         for prec in ("c128", "c64"):
-            e = table[autotune.key(p.nx, p.ny, p.npml, p.nsys, p.nrhs, prec)]
+            e = table[autotune.key(ARCH, p.nx, p.ny, p.npml, p.nsys, p.nrhs, prec)]
+            assert e["arch"] == ARCH
             assert e["leaf"] >= 4 and e["small_lds"] >= -1
+            assert e["syrk_group"] >= -1 and e["split_kb"] >= -1 and e["block_split"] >= -1
             # the choice is the fastest row the tuner measured
             ok = [r for r in e["table"] if r["status"] in ("ok", "pivots perturbed")]
             assert min(r["ms"] for r in ok) == e["ms"]
-            assert any(r["leaf"] == e["leaf"] and r["small_lds"] == e["small_lds"] for r in ok)
+            assert any(all(r[k] == e[k] for k in autotune.KNOBS) for r in ok)
+            # every schedule knob was varied at the chosen front layout (one knob
+            # at a time, from the best setting found before it)
+            layout = [r for r in ok if r["leaf"] == e["leaf"] and r["small_lds"] == e["small_lds"]]
+            for k in ("syrk_group", "split_kb", "block_split"):
+                assert len({r[k] for r in layout}) >= 3
 
 
 def test_lookup(tmp_path):
     path = tmp_path / "t.json"
-    k = autotune.key(10, 12, 2, 1, 1, "c128")
-    path.write_text(json.dumps({k: {"leaf": 25, "small_lds": 32768, "ms": 1.0, "table": []}}))
-    assert autotune.lookup(10, 12, 2, 1, 1, "c128", path=str(path)) == (25, 32768)
-    assert autotune.lookup(10, 12, 2, 1, 1, "c64", path=str(path)) is None
-    assert autotune.lookup(10, 12, 2, 1, 1, "c128", path=str(tmp_path / "missing.json")) is None
+    k = autotune.key(ARCH, 10, 12, 2, 1, 1, "c128")
+    row = {"leaf": 25, "small_lds": 32768, "syrk_group": 4, "split_kb": 64, "block_split": -1}
+    path.write_text(json.dumps({k: dict(row, ms=1.0, table=[])}))
+    assert autotune.lookup(10, 12, 2, 1, 1, "c128", path=str(path), arch=ARCH) == row
+    assert autotune.lookup(10, 12, 2, 1, 1, "c64", path=str(path), arch=ARCH) is None
+    assert autotune.lookup(10, 12, 2, 1, 1, "c128", path=str(path), arch="gfx942") is None
+    assert autotune.lookup(10, 12, 2, 1, 1, "c128", path=str(tmp_path / "missing.json"), arch=ARCH) is None
