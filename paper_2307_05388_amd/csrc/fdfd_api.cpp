@@ -241,6 +241,29 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     P.small_lds_prefix = std::max(P.small_lds_prefix, P.levels[P.small_prefix].small_lds);
     ++P.small_prefix;
   }
+  // the leaves (the bottom level, fronts without children) one wavefront
+  // each when every leaf has at most 64 rows and four panels fit the LDS
+  // (FDFD_LEAF_WAVE=0 keeps them in the one-workgroup kernel)
+  P.leaf_wave = 0;
+  P.leaf_ldsw = 0;
+  if (P.small_prefix > 0 && env_int("FDFD_LEAF_WAVE", 1) != 0) {
+    int mmax = 0, pmax = 0;
+    bool leaves = true;
+    for (int k = P.levels[0].first; k < P.levels[0].first + P.levels[0].count; ++k) {
+      const int f = A.level_fronts[k];
+      mmax = std::max(mmax, A.m(f));
+      pmax = std::max(pmax, A.npiv[f]);
+      leaves = leaves && A.child_ptr[f + 1] == A.child_ptr[f];
+    }
+    // panel m x p, p pivots, a 64-entry column buffer; 16-byte aligned slices
+    const size_t ldsw = (((size_t)mmax * pmax + pmax + 64) * cs + 15) / 16 * 16 / cs;
+    const size_t lds_dyn = P.lds_limit > 512 ? P.lds_limit - 512 : 65536;
+    if (leaves && mmax <= 64 && pmax <= 40 && 4 * ldsw * cs <= lds_dyn) {
+      P.leaf_wave = 1;
+      P.leaf_ldsw = (int)ldsw;
+      P.leaf_pmax = pmax;
+    }
+  }
   tasks.clear();
   tile_base.assign(A.nfronts, 0);
   is_tiled.assign(A.nfronts, 0);
@@ -926,7 +949,9 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
             for (int q = 0; q < 5; ++q) it[q] = P.tile_tasks_host[5 * (t / ns) + q];
           } else {
             const int pos = t / ns;
-            it[1] = A.level_fronts[k == 3 ? A.nfronts - 1 - pos : pos];
+            // the small-front launch starts after the leaves when k_leaf_fronts took them
+            const int skip = k == 0 && P.leaf_wave ? P.levels[0].count : 0;
+            it[1] = A.level_fronts[k == 3 ? A.nfronts - 1 - pos : skip + pos];
           }
           std::fprintf(fp, "%d %d %lld %lld %lld %lld %d %d %d %d %d\n", k, t, tr[4 * t], tr[4 * t + 1],
                        tr[4 * t + 2], tr[4 * t + 3], it[0], it[1], it[2], it[3], it[4]);

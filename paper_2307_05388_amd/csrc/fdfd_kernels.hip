@@ -91,6 +91,7 @@ struct KArgs {
   double tau;
   int32_t nfronts;
   int32_t te;  // 1: the TE (Hz) operator, 0: TM (Ez)
+  int32_t leaves_done;  // 1: the leaf fronts were factored by an earlier launch (k_leaf_fronts)
 };
 
 // ---------------------------------------------------------------------------
@@ -315,13 +316,35 @@ __device__ __forceinline__ C fix_pivot(C d, double thr, double anorm, int& npert
 }
 
 // min2: smallest |d|^2 of the pivots examined by this thread (INFINITY if none).
-__device__ __forceinline__ void record_pivots(DevStatus* st, int npert, double min2, int nonfin, double anorm) {
-  if (npert) atomicAdd(&st->n_perturbed, npert);
-  if (nonfin) atomicExch(&st->nonfinite, 1);
-  if (min2 < INFINITY) {
-    const double ratio = anorm > 0 ? sqrt(min2) / anorm : sqrt(min2);
-    atomicMin(&st->min_ratio_bits, (unsigned long long)__double_as_longlong(ratio));
+// Pivot statistics of several fronts, gathered in registers and flushed with
+// one set of device atomics: one atomic per front on the same status words
+// serialises at the memory side when hundreds of thousands of small fronts
+// finish within a few milliseconds.
+struct PivotStats {
+  int npert = 0, nonfin = 0;
+  double ratio = INFINITY;  // min |d_k| / ||SA||_max
+  __device__ __forceinline__ void add(int np, double min2, int nf, double anorm) {
+    npert += np;
+    nonfin |= nf;
+    if (min2 < INFINITY) ratio = fmin(ratio, anorm > 0 ? sqrt(min2) / anorm : sqrt(min2));
   }
+  __device__ __forceinline__ void flush(DevStatus* st) const {
+    if (npert) atomicAdd(&st->n_perturbed, npert);
+    if (nonfin) atomicExch(&st->nonfinite, 1);
+    if (ratio < INFINITY) {
+      // a positive double's bits order like its value; the minimum only
+      // changes for the few fronts below it, so most flushes end at the load
+      const unsigned long long b = (unsigned long long)__double_as_longlong(ratio);
+      if (b < __hip_atomic_load(&st->min_ratio_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin(&st->min_ratio_bits, b);
+    }
+  }
+};
+
+__device__ __forceinline__ void record_pivots(DevStatus* st, int npert, double min2, int nonfin, double anorm) {
+  PivotStats ps;
+  ps.add(npert, min2, nonfin, anorm);
+  ps.flush(st);
 }
 
 __device__ __forceinline__ double anorm_of(const KArgs& a, int s) {
@@ -484,8 +507,12 @@ __device__ __forceinline__ void wait_flag(const Queue& q, int ep, const int32_t*
 
 // One thread per child (each flag read is a memory round trip).
 __device__ __forceinline__ void wait_children(const Queue& q, int ep, const KArgs& a, int s, int f) {
-  for (int k = a.child_ptr[f] + threadIdx.x; k < a.child_ptr[f + 1]; k += blockDim.x)
-    wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + a.child_list[k]);
+  for (int k = a.child_ptr[f] + threadIdx.x; k < a.child_ptr[f + 1]; k += blockDim.x) {
+    const int c = a.child_list[k];
+    // a leaf factored by k_leaf_fronts finished with that earlier launch
+    if (a.leaves_done && a.child_ptr[c + 1] == a.child_ptr[c]) continue;
+    wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + c);
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   __syncthreads();
 }
@@ -504,6 +531,13 @@ __device__ __forceinline__ void wait_parent(const Queue& q, int ep, const KArgs&
 __device__ __forceinline__ void drain_stores() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained (gfx9 encoding)
+}
+
+// Orders one wavefront's LDS accesses across its lanes (its LDS operations
+// complete in program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ void publish(const Queue& q, int ep, int64_t idx) {
@@ -984,7 +1018,7 @@ __device__ __forceinline__ void small_front_stage(const KArgs& a, int s, int f, 
 
 template <typename R>
 __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f, const Kids<typename Cx<R>::T>& kids,
-                            unsigned char* smem_raw) {
+                            unsigned char* smem_raw, PivotStats& ps) {
   typedef typename Cx<R>::T C;
   C* F = reinterpret_cast<C*>(smem_raw);
   const int p = a.npiv[f], u = a.nupd[f], m = p + u;
@@ -1089,7 +1123,126 @@ __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   for (int c = wave; c < p; c += 4)
     for (int r = c + lane; r < m; r += 64) L[(int64_t)c * m + r] = r > c ? F[c * m + r] : dd[c];
-  if (threadIdx.x == 0) record_pivots(a.st, npert, minr, nonfin, anorm);
+  if (threadIdx.x == 0) ps.add(npert, minr, nonfin, anorm);
+}
+
+// Component-wise select, so that conditional updates of a register array
+// stay branch-free (a branch around each update makes the compiler keep the
+// array in scratch across the branches).
+template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
+  C r;
+  r.x = c ? a.x : b.x;
+  r.y = c ? a.y : b.y;
+  return r;
+}
+
+// Pivot step K of the leaf LDL^T and every step after it, unrolled through
+// template recursion so that the row stays in registers (a loop the compiler
+// declines to unroll fully would index x dynamically, i.e. through scratch).
+template <int K, int PMAX, typename C>
+struct LeafSteps {
+  __device__ __forceinline__ static void run(C (&x)[PMAX], C* col, C* dd, int p, int lane, double thr,
+                                             double anorm, int& npert, double& minr, int& nonfin) {
+    if constexpr (K < PMAX) {
+      if (K >= p) return;
+      col[lane] = x[K];
+      wave_sync();
+      const C d = fix_pivot(col[K], thr, anorm, npert, minr, nonfin);
+      const C l = csel(lane > K, cmul(x[K], cinv(d)), czero<C>());
+#pragma unroll
+      for (int j = K + 1; j < PMAX; ++j)
+        if (j < p) x[j] = csel(lane >= j, csub(x[j], cmul(l, col[j])), x[j]);
+      x[K] = csel(lane > K, l, csel(lane == K, d, x[K]));
+      if (lane == 0) dd[K] = d;
+      wave_sync();
+      LeafSteps<K + 1, PMAX, C>::run(x, col, dd, p, lane, thr, anorm, npert, minr, nonfin);
+    }
+  }
+};
+
+// Leaf fronts (no children, at most 64 rows and PMAX pivots), one wavefront
+// per front and four per workgroup, each with its own slice of LDS.  The
+// pivot columns' original entries are scattered into an m x p panel in LDS
+// (lane c < p writes column c: its diagonal and its neighbours below it, so
+// every entry of the lower part is written once); then lane i holds row i of
+// the panel in registers and the LDL^T runs right-looking with the loops
+// unrolled against PMAX: at step k every lane publishes its a_ik to a 64-entry
+// LDS buffer, reads the column back as broadcasts, and row i > k takes
+// a_ij -= (a_ik / d_k) a_jk for the pivot columns k < j <= i.  The waves run
+// independently (one wave's LDS operations complete in program order), where
+// the one-workgroup kernel spends a workgroup and a barrier per pivot step on
+// each front.  The update block U = -L_u D L_u^T goes to the update arena and
+// the panel (D on the diagonal, unit-lower L below, as k_front_small stores
+// it) to the factor arena; the parents read both in later launches.  Pivots
+// are checked and perturbed as in every other factor path.
+template <typename R, int PMAX>
+__device__ __forceinline__ void leaf_front(const KArgs& a, int f, int s, int ldsw, unsigned char* smem_raw,
+                                           PivotStats& ps) {
+  typedef typename Cx<R>::T C;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
+  C* F = reinterpret_cast<C*>(smem_raw) + (size_t)wave * ldsw;  // m x p panel
+  C* dd = F + m * p;                                             // p pivots
+  C* col = dd + p;                                               // 64: the column being eliminated
+  for (int e = lane; e < m * p; e += 64) F[e] = czero<C>();
+  wave_sync();
+  if (lane < p) {
+    const int q = pb + lane;
+    const Stencil S = stencil_at(a, s, a.perm[q]);
+    F[lane * m + lane] = from_d2<C>(S.diag);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int r = a.nbr_row[4 * (int64_t)q + d];
+      if (r > lane) F[lane * m + r] = from_d2<C>(S.c[d]);
+    }
+  }
+  wave_sync();
+  const bool row = lane < m;
+  C x[PMAX];
+  const int lr = row ? lane : 0;  // a lane past the front reads row 0 and keeps zeros
+#pragma unroll
+  for (int c = 0; c < PMAX; ++c) x[c] = csel(c < p && row && lane >= c, F[min(c, p - 1) * m + lr], czero<C>());
+  const double anorm = anorm_of(a, s);
+  const double thr = a.tau * anorm;
+  int npert = 0, nonfin = 0;
+  double minr = INFINITY;
+  LeafSteps<0, PMAX, C>::run(x, col, dd, p, lane, thr, anorm, npert, minr, nonfin);
+  // the panel to the factor arena (row lane: D on the diagonal, L below)
+  C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
+#pragma unroll
+  for (int c = 0; c < PMAX; ++c)
+    if (c < p && row && lane >= c) L[(int64_t)c * m + lane] = x[c];
+  // update block: U[r][c] = -sum_k l_(p+r)k (d_k l_(p+c)k), c <= r, from the
+  // d-scaled update rows published to LDS
+  if (u > 0) {
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c)
+      if (c < p && lane >= p && row) F[c * m + lane] = cmul(x[c], dd[c]);
+    wave_sync();
+    const int cl = p < 1 ? 0 : p - 1;
+    C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
+    const int r = lane - p;
+    for (int c = 0; c < u; ++c) {
+      C acc = czero<C>();
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k)
+        if (k < p) acc = cadd(acc, cmul(x[k], F[min(k, cl) * m + p + c]));
+      if (r >= c && r < u) U[(int64_t)c * u + r] = csub(czero<C>(), acc);
+    }
+  }
+  ps.add(npert, minr, nonfin, anorm);
+}
+
+template <typename R, int PMAX>
+__global__ __launch_bounds__(kThreads) void k_leaf_fronts(KArgs a, const int32_t* order, int nitems, int ldsw) {
+  typedef typename Cx<R>::T C;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int item = blockIdx.x * (kThreads / 64) + wave;
+  if (item >= nitems) return;  // the whole wave: nothing below synchronises the workgroup
+  PivotStats ps;
+  leaf_front<R, PMAX>(a, order[item / a.nsys], item % a.nsys, ldsw, smem_raw, ps);
+  if (lane == 0) ps.flush(a.st);
 }
 
 // Persistent launch over fronts order[0 .. ntasks/nsys): with q.wait set, a
@@ -1101,6 +1254,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, c
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
   const int ep = launch_epoch(q);
+  PivotStats ps;
   for (;;) {
     const int t = claim(q, &sh);
     if (t >= q.ntasks) break;
@@ -1111,9 +1265,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, c
     if (q.wait) wait_children(q, ep, a, s, f);
     else __syncthreads();
     trace_mark(q, t, 1);
-    small_front<R>(a, q, ep, s, f, kids, smem_raw);
+    small_front<R>(a, q, ep, s, f, kids, smem_raw, ps);
     trace_mark(q, t, 2);
   }
+  if (threadIdx.x == 0) ps.flush(a.st);
   leave(q, ep);
 }
 
@@ -2709,10 +2864,6 @@ __global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs 
 // sweeps, so that four waves per SIMD stay resident (128 registers).
 template <typename R> constexpr int kWaveBatch = sizeof(R) == 8 ? 8 : 16;
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 __device__ __forceinline__ void trace_wave(const Queue& q, int t, int slot) {
   if (q.trace && (threadIdx.x & 63) == 0 && t < q.ntasks) {
@@ -3209,6 +3360,7 @@ KArgs make_args(Plan& P) {
   a.tau = P.pivot_tau;
   a.nfronts = P.an.nfronts;
   a.te = (P.desc.flags & FDFD_POL_TE) ? 1 : 0;
+  a.leaves_done = 0;
   return a;
 }
 
@@ -3271,6 +3423,17 @@ size_t tile_lds(const Plan& P) {
   return tile_lds_entries() * P.csize;
 }
 
+// Workgroups of a persistent launch: as many as can be resident at once for
+// this kernel and LDS footprint, never more than the work items.
+unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems, int threads = kThreads) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int g = P.n_cu * per_cu;
+  if (g > nitems) g = nitems;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
 template <typename R>
 hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStream_t st) {
   const KArgs a = make_args(P);
@@ -3286,15 +3449,33 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
     hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
   }
   const int32_t* lf = P.t.level_fronts;
-  // the small levels at the bottom of the tree: one persistent launch
+  // the small levels at the bottom of the tree: the leaves one wavefront
+  // each (when they fit one), then one persistent launch for the rest
   if (P.small_prefix > 0) {
     const int nf = P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count;
-    const Queue q = make_queue(P, nf * nsys, 1, 0);
-    double fl = 0.0;
-    for (int k = 0; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
-    Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
-    hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, nf * nsys)),
-                       dim3(kThreads), P.small_lds_prefix, st, a, q, lf);
+    const int nleaf = P.leaf_wave ? P.levels[0].count : 0;
+    if (nleaf > 0) {
+      double fl = 0.0;
+      for (int k = 0; k < nleaf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+      Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
+      const int nitems = nleaf * nsys, wpg = kThreads / 64;
+      const size_t lds = (size_t)wpg * P.leaf_ldsw * P.csize;
+      const dim3 grid((nitems + wpg - 1) / wpg);
+      if (P.leaf_pmax <= 24)
+        hipLaunchKernelGGL((k_leaf_fronts<R, 24>), grid, dim3(kThreads), lds, st, a, lf, nitems, P.leaf_ldsw);
+      else
+        hipLaunchKernelGGL((k_leaf_fronts<R, 40>), grid, dim3(kThreads), lds, st, a, lf, nitems, P.leaf_ldsw);
+    }
+    if (nf > nleaf) {
+      KArgs as = a;
+      as.leaves_done = nleaf > 0 ? 1 : 0;
+      const Queue q = make_queue(P, (nf - nleaf) * nsys, 1, 0);
+      double fl = 0.0;
+      for (int k = nleaf; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+      Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
+      hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, (nf - nleaf) * nsys)),
+                         dim3(kThreads), P.small_lds_prefix, st, as, q, lf + nleaf);
+    }
   }
   // every level above them: one persistent launch of the tile task graph
   if (P.ntile_tasks > 0) {
@@ -3325,16 +3506,6 @@ size_t sweep_lds(const Plan& P, int nrhs) {
 // LDS of the wave-item sweeps: four waves, each with nrhs x wave_ld entries.
 size_t sweep_wave_lds(const Plan& P, int nrhs) { return (size_t)4 * P.wave_ld * nrhs * P.csize; }
 
-// Workgroups of a persistent launch: as many as can be resident at once for
-// this kernel and LDS footprint, never more than the work items.
-unsigned resident_grid(const Plan& P, const void* fn, size_t lds, int nitems, int threads = kThreads) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  int g = P.n_cu * per_cu;
-  if (g > nitems) g = nitems;
-  return (unsigned)(g < 1 ? 1 : g);
-}
 
 // Right-hand sides one sweep launch takes at once: the most whose LDS blocks
 // fit (a front's right-hand-side block is held whole in LDS).
@@ -3520,7 +3691,8 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
 template <typename R>
 hipError_t set_lds_limits(int limit) {
   hipError_t e = hipSuccess;
-  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_large_tiles<R>,
+  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_leaf_fronts<R, 24>,
+                       (const void*)k_leaf_fronts<R, 40>, (const void*)k_large_tiles<R>,
                        (const void*)k_fwd_sweep<R>,   (const void*)k_bwd_sweep<R>,
                        (const void*)k_fwd_sweep_waves<R>, (const void*)k_bwd_sweep_waves<R>};
   for (const void* fn : fns) {

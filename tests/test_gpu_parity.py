@@ -214,3 +214,28 @@ def test_schur_groups_forced(oracle, monkeypatch, group, prec):
     assert entry_err(out["x"], ref["x"]) < 1e3 * bar
     assert rel(out["grad"], ref["grad"]) < 10 * bar
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("leaf_wave", ["0", "1"])
+@pytest.mark.parametrize("leaf", [16, 36])
+def test_leaf_fronts_both_paths(oracle, monkeypatch, prec, leaf_wave, leaf):
+    """The leaves factored one wavefront each (k_leaf_fronts) and in the
+    one-workgroup kernel (FDFD_LEAF_WAVE=0): both against the oracle."""
+    monkeypatch.setenv("FDFD_LEAF_WAVE", leaf_wave)
+    p = P.custom_problem(90, 77, 10, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss"))
+    say(f"case leaves {'one wave each' if leaf_wave == '1' else 'one workgroup each'} leaf={leaf} {prec}")
+    eps = P.design_eps(p, t=6)
+    b = P.sources(p)
+    c = P.objective_vector(p)
+    plan = make_plan(p, prec, leaf=leaf)
+    ir = (10, 1e-12) if prec == "c64" else (0, 0.0)
+    out = gpu_iteration(plan, p, eps, b, c=c, max_ir=ir[0], tol=ir[1])
+    ref = _oracle(oracle, p, eps, b, c=c)
+    tol = 1e-10 if prec == "c128" else 1e-8
+    say(f"  x {rel(out['x'], ref['x']):.2e} lam {rel(out['lam'], ref['lam']):.2e} grad {rel(out['grad'], ref['grad']):.2e}")
+    assert out["info"]["status"] in (0, 6)
+    assert rel(out["x"], ref["x"]) < tol and rel(out["lam"], ref["lam"]) < tol
+    assert entry_err(out["x"], ref["x"]) < 1e3 * tol
+    assert rel(out["grad"], ref["grad"]) < 10 * tol
+    plan.close()
