@@ -1728,9 +1728,12 @@ __device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O
 // Tile update over a group of pivot blocks:
 //   T_IJ -= sum_{k0 <= k < k1} L_Ik D_k L_Jk^T,
 // accumulated on the matrix cores over the whole group before the tile is
-// touched.  Each block's operands are loaded into registers while the
-// previous block's products run (software pipelining, one LDS buffer); the
-// tile is then read and written once.  Used by
+// touched.  Each wave's A operand (its 16 output rows) is private to it and
+// goes from memory straight into registers in the matrix-core layout, one
+// block ahead; B (shared by the four waves) is scaled by the pivots as it is
+// written to one of two LDS buffers, in the middle of the previous block's
+// products, so a block costs one barrier and no idle matrix core between
+// blocks.  The tile is then read and written once.  Used by
 //   SYRK(I,J,[k0,k1))  tiles of the front's Schur complement (I >= J >= nbk);
 //                      the first group gathers the children's update-block
 //                      entries instead of reading the tile (its assembly);
@@ -1740,56 +1743,61 @@ __device__ __forceinline__ void mfma_tile_abt_lower(const C* A, const C* B, C* O
 //                      for the update rows.
 // The one-block-per-task form instead reads and writes the tile, and pays a
 // task's claim, waits and store drain, once per pivot block.
+// Operands of one pivot block of a tile update, loaded from memory ahead of
+// their use: A (this wave's 16 output rows) straight into registers in the
+// matrix-core layout, af[s] = L[r0 + 16 wave + l % 16][kb + 4 s + l / 16]; B
+// (the 64 output columns, lane = row, wave w the columns w, w + 4, ...) and,
+// in lanes 0..15, the pivots d of those sixteen columns.  The block's kn
+// columns form one buffer, so columns beyond kn read zero.
 template <typename C>
-__device__ __forceinline__ void syrk_load(const C* L, int m, int kb, int kn, int r0, int nr, int c0, int nc,
-                                          C (&va)[16], C (&vb)[16], C& dv) {
-  // the block's kn columns as one buffer: columns q >= kn read zero
+__device__ __forceinline__ void tile_block_load(const C* L, int m, int kb, int kn, int r0, int nr, int c0, int nc,
+                                                C (&af)[16], C (&vb)[16], C& dq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
   const __amdgpu_buffer_rsrc_t rs = buffer_of(L + (int64_t)kb * m, (unsigned)(kn * m) * (unsigned)sizeof(C));
   const unsigned cs = sizeof(C), step = 4u * (unsigned)m * cs;
-  unsigned oa = lane < nr ? ((unsigned)(wave * m + r0 + lane)) * cs : kOob;
+  unsigned oa = 16 * wave + i < nr ? ((unsigned)(kq * m + r0 + 16 * wave + i)) * cs : kOob;
   unsigned ob = lane < nc ? ((unsigned)(wave * m + c0 + lane)) * cs : kOob;
-  // the 32 offsets below do not depend on the block: kept opaque here, so
-  // that they are formed load by load rather than hoisted out of the caller's
-  // loop into 32 more live registers
-  asm volatile("" : "+v"(oa), "+v"(ob));
+  asm volatile("" : "+v"(oa), "+v"(ob));  // formed load by load, not hoisted into the caller's loop
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
-    va[t] = ld_buf<C>(rs, oa + t * step);
+    af[t] = ld_buf<C>(rs, oa + t * step);
     vb[t] = ld_buf<C>(rs, ob + t * step);
   }
-  dv = ld_buf<C>(rs, threadIdx.x < 64u ? ((unsigned)threadIdx.x * (unsigned)m + kb + threadIdx.x) * cs : kOob);
+  dq = ld_buf<C>(rs, lane < 16 ? ((unsigned)((wave + 4 * lane) * (m + 1) + kb)) * cs : kOob);
 }
 
-// O[c][r] += sum_q A[q][r] d_q B[q][c] for LDS-resident 64 x 64 operands
-// (column major, leading dimension kBW) into the caller's accumulators: wave
-// w owns output rows 16w..16w+15 as four 16 x 16 blocks (the layout of
-// mfma_tile_abt); d_q scales the A operand as it is read.  The LDS reads of
-// the next 4-deep step are issued before this step's products (one wave per
-// SIMD: a wait on LDS between the products would leave the matrix core idle).
-template <typename R, typename C>
-__device__ __forceinline__ void mfma_acc_adbt(const C* A, const C* B, const C* Dv, typename Mfma<R>::v4 (&re)[4],
-                                              typename Mfma<R>::v4 (&im)[4]) {
-  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = l & 15, kq = l >> 4;
-  C an = A[kq * kBW + 16 * wave + i], dn = Dv[kq];
+// B of the next block into its LDS buffer, each column scaled by its pivot:
+// Bs[q][c] = d_q L[c0 + c][kb + q].
+template <typename C>
+__device__ __forceinline__ void tile_block_stage(const C (&vb)[16], C dq, C* Bs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) Bs[(wave + 4 * t) * kBW + lane] = cmul(vb[t], bcast_c(dq, t));
+}
+
+// Steps [S0, S1) of one block's products on the matrix cores:
+// O[c][r] += sum_q A[q][r] Bs[q][c] with A from registers (af) and Bs from LDS
+// (the next step's LDS reads issued before this step's products); wave w
+// owns output rows 16w..16w+15 as four 16 x 16 blocks (the layout of
+// mfma_tile_abt).
+template <int S0, int S1, typename R, typename C>
+__device__ __forceinline__ void tile_block_mfma(const C (&af)[16], const C* Bs, typename Mfma<R>::v4 (&re)[4],
+                                                typename Mfma<R>::v4 (&im)[4]) {
+  const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
   C bn[4];
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj) bn[bj] = B[kq * kBW + 16 * bj + i];
-#pragma unroll 2
-  for (int k0 = 0; k0 < kBW; k0 += 4) {
-    const C a0 = an, d0 = dn;
+  for (int bj = 0; bj < 4; ++bj) bn[bj] = Bs[(4 * S0 + kq) * kBW + 16 * bj + i];
+#pragma unroll
+  for (int st = S0; st < S1; ++st) {
     C bv[4];
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) bv[bj] = bn[bj];
-    if (k0 + 4 < kBW) {
-      const int q = k0 + 4 + kq;
-      an = A[q * kBW + 16 * wave + i];
-      dn = Dv[q];
+    if (st + 1 < S1) {
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) bn[bj] = B[q * kBW + 16 * bj + i];
+      for (int bj = 0; bj < 4; ++bj) bn[bj] = Bs[(4 * (st + 1) + kq) * kBW + 16 * bj + i];
     }
-    const C av = cmul(a0, d0);
+    const C av = af[st];
     const R nai = -av.y;
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
@@ -1804,14 +1812,31 @@ __device__ __forceinline__ void mfma_acc_adbt(const C* A, const C* B, const C* D
   }
 }
 
+// One block of the pipelined update: products of block k (registers afc,
+// LDS Bc) in two halves; between them the next block's B goes into the other
+// buffer Bn (its loads, issued before the first half, have arrived); the
+// next block's operands are loaded into afn, vb, dq first.  One barrier per
+// block: after it every wave is done with Bc and Bn is complete.
+template <typename R, typename C>
+__device__ __forceinline__ void tile_block_step(const C* L, int m, int p, int k, int k1, int r0, int nr, int c0,
+                                                int nc, C (&afc)[16], C (&afn)[16], C (&vb)[16], C& dq, const C* Bc,
+                                                C* Bn, typename Mfma<R>::v4 (&re)[4], typename Mfma<R>::v4 (&im)[4]) {
+  const bool next = k + 1 < k1;
+  if (next) tile_block_load(L, m, (k + 1) * kBW, min(kBW, p - (k + 1) * kBW), r0, nr, c0, nc, afn, vb, dq);
+  tile_block_mfma<0, 8, R>(afc, Bc, re, im);
+  if (next) tile_block_stage(vb, dq, Bn);
+  tile_block_mfma<8, 16, R>(afc, Bc, re, im);
+  __syncthreads();
+}
+
 template <typename R>
 __device__ __forceinline__ void task_tile_update(const KArgs& a, int s, int f, int k0, int k1, int I, int J,
                                                  unsigned char* smem) {
   typedef typename Cx<R>::T C;
   typedef typename Mfma<R>::v4 v4;
-  C* As = reinterpret_cast<C*>(smem);  // As[q][r] = L[r0 + r][kb + q]; at the end the products O[c][r]
-  C* Bs = As + kBW * kBW;              // Bs[q][c] = L[c0 + c][kb + q]
-  C* Ds = Bs + kBW * kBW;              // d of the block's pivots
+  C* B0 = reinterpret_cast<C*>(smem);  // two B buffers; at the end the products O[c][r] in B0
+  C* B1 = B0 + kBW * kBW;
+  C* As = B0;
   const Chunks ch(a.npiv[f], a.nupd[f]);
   const int m = ch.m, p = ch.p, u = ch.u;
   const int r0 = ch.lo(I), nr = ch.hi(I) - r0, c0 = ch.lo(J), nc = ch.hi(J) - c0;
@@ -1826,21 +1851,16 @@ __device__ __forceinline__ void task_tile_update(const KArgs& a, int s, int f, i
   // the first group of a Schur tile assembles it from the children: their
   // gather rows go to LDS now (the loop's barriers order them before use)
   const bool first = k0 == 0 && J >= ch.nbk;
-  int* kid = reinterpret_cast<int*>(Ds + kBW);
+  int* kid = reinterpret_cast<int*>(B1 + kBW * kBW);
   if (first) stage_kid_rows(a, f, m, r0, nr, c0, nc, kid);
-  C va[16], vb[16], dv;
-  syrk_load(L, m, k0 * kBW, min(kBW, p - k0 * kBW), r0, nr, c0, nc, va, vb, dv);
-  for (int k = k0; k < k1; ++k) {
-    __syncthreads();  // the previous block's products have read As, Bs, Ds
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      As[(wave + 4 * t) * kBW + lane] = va[t];
-      Bs[(wave + 4 * t) * kBW + lane] = vb[t];
-    }
-    if (threadIdx.x < kBW) Ds[threadIdx.x] = dv;
-    __syncthreads();
-    if (k + 1 < k1) syrk_load(L, m, (k + 1) * kBW, min(kBW, p - (k + 1) * kBW), r0, nr, c0, nc, va, vb, dv);
-    mfma_acc_adbt<R>(As, Bs, Ds, re, im);
+  C af0[16], af1[16], vb[16], dq;
+  tile_block_load(L, m, k0 * kBW, min(kBW, p - k0 * kBW), r0, nr, c0, nc, af0, vb, dq);
+  tile_block_stage(vb, dq, B0);
+  __syncthreads();
+  for (int k = k0; k < k1; k += 2) {
+    tile_block_step<R>(L, m, p, k, k1, r0, nr, c0, nc, af0, af1, vb, dq, B0, B1, re, im);
+    if (k + 1 >= k1) break;
+    tile_block_step<R>(L, m, p, k + 1, k1, r0, nr, c0, nc, af1, af0, vb, dq, B1, B0, re, im);
   }
   __syncthreads();
 #pragma unroll
