@@ -165,6 +165,9 @@ typedef struct {
  *                   the same name when the desc leaves them at 0 (for
  *                   FDFD_BLOCK_SPLIT and FDFD_SYRK_GROUP, 0 means never /
  *                   all blocks);
+ *   FDFD_WAVE_FRONTS at most this many bottom levels factored one wavefront
+ *                   per front (each level's fronts must have at most 64 rows
+ *                   and 40 pivots; 0 = none, default all that qualify);
  *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
  *                   passes also never take more than fit the LDS);
  *   FDFD_PIVOT_TAU  static pivot threshold relative to the matrix norm;

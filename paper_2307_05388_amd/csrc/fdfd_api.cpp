@@ -241,27 +241,25 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     P.small_lds_prefix = std::max(P.small_lds_prefix, P.levels[P.small_prefix].small_lds);
     ++P.small_prefix;
   }
-  // the leaves (the bottom level, fronts without children) one wavefront
-  // each when every leaf has at most 64 rows and four panels fit the LDS
-  // (FDFD_LEAF_WAVE=0 keeps them in the one-workgroup kernel)
-  P.leaf_wave = 0;
-  P.leaf_ldsw = 0;
-  if (P.small_prefix > 0 && env_int("FDFD_LEAF_WAVE", 1) != 0) {
-    int mmax = 0, pmax = 0;
-    bool leaves = true;
-    for (int k = P.levels[0].first; k < P.levels[0].first + P.levels[0].count; ++k) {
-      const int f = A.level_fronts[k];
-      mmax = std::max(mmax, A.m(f));
-      pmax = std::max(pmax, A.npiv[f]);
-      leaves = leaves && A.child_ptr[f + 1] == A.child_ptr[f];
-    }
-    // panel m x p, p pivots, a 64-entry column buffer; 16-byte aligned slices
-    const size_t ldsw = (((size_t)mmax * pmax + pmax + 64) * cs + 15) / 16 * 16 / cs;
+  // the bottom levels whose fronts all have at most 64 rows and 40 pivots
+  // are factored one wavefront per front, a launch per level, when four such
+  // fronts fit the LDS (FDFD_WAVE_FRONTS caps the number of such levels; 0
+  // keeps every level in the one-workgroup kernel)
+  P.wave_front_levels.clear();
+  {
+    const int cap = env_int("FDFD_WAVE_FRONTS", 1 << 20);
     const size_t lds_dyn = P.lds_limit > 512 ? P.lds_limit - 512 : 65536;
-    if (leaves && mmax <= 64 && pmax <= 40 && 4 * ldsw * cs <= lds_dyn) {
-      P.leaf_wave = 1;
-      P.leaf_ldsw = (int)ldsw;
-      P.leaf_pmax = pmax;
+    for (int l = 0; l < P.small_prefix && (int)P.wave_front_levels.size() < cap; ++l) {
+      int mmax = 0, pmax = 0;
+      for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
+        const int f = A.level_fronts[k];
+        mmax = std::max(mmax, A.m(f));
+        pmax = std::max(pmax, A.npiv[f]);
+      }
+      // panel m x p, p pivots, a 64-entry column buffer, two rows of 64 gather indices
+      const size_t ldsw = ((((size_t)mmax * pmax + pmax + 64) * cs + 2 * 64 * sizeof(int32_t)) + 15) / 16 * 16;
+      if (mmax > 64 || pmax > 40 || 4 * ldsw > lds_dyn) break;
+      P.wave_front_levels.push_back({(int)ldsw, pmax});
     }
   }
   tasks.clear();
@@ -949,8 +947,9 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
             for (int q = 0; q < 5; ++q) it[q] = P.tile_tasks_host[5 * (t / ns) + q];
           } else {
             const int pos = t / ns;
-            // the small-front launch starts after the leaves when k_leaf_fronts took them
-            const int skip = k == 0 && P.leaf_wave ? P.levels[0].count : 0;
+            // the small-front launch starts above the levels k_wave_fronts took
+            const int nwl = (int)P.wave_front_levels.size();
+            const int skip = k == 0 && nwl > 0 ? P.levels[nwl - 1].first + P.levels[nwl - 1].count : 0;
             it[1] = A.level_fronts[k == 3 ? A.nfronts - 1 - pos : skip + pos];
           }
           std::fprintf(fp, "%d %d %lld %lld %lld %lld %d %d %d %d %d\n", k, t, tr[4 * t], tr[4 * t + 1],

@@ -91,7 +91,7 @@ struct KArgs {
   double tau;
   int32_t nfronts;
   int32_t te;  // 1: the TE (Hz) operator, 0: TM (Ez)
-  int32_t leaves_done;  // 1: the leaf fronts were factored by an earlier launch (k_leaf_fronts)
+  int32_t below_done;  // fronts of height < below_done were factored by earlier launches (k_wave_fronts)
 };
 
 // ---------------------------------------------------------------------------
@@ -509,8 +509,8 @@ __device__ __forceinline__ void wait_flag(const Queue& q, int ep, const int32_t*
 __device__ __forceinline__ void wait_children(const Queue& q, int ep, const KArgs& a, int s, int f) {
   for (int k = a.child_ptr[f] + threadIdx.x; k < a.child_ptr[f + 1]; k += blockDim.x) {
     const int c = a.child_list[k];
-    // a leaf factored by k_leaf_fronts finished with that earlier launch
-    if (a.leaves_done && a.child_ptr[c + 1] == a.child_ptr[c]) continue;
+    // a child factored by k_wave_fronts finished with that earlier launch
+    if (a.height[c] < a.below_done) continue;
     wait_flag(q, ep, q.done + (int64_t)s * a.nfronts + c);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -1160,30 +1160,42 @@ struct LeafSteps {
   }
 };
 
-// Leaf fronts (no children, at most 64 rows and PMAX pivots), one wavefront
-// per front and four per workgroup, each with its own slice of LDS.  The
-// pivot columns' original entries are scattered into an m x p panel in LDS
-// (lane c < p writes column c: its diagonal and its neighbours below it, so
-// every entry of the lower part is written once); then lane i holds row i of
-// the panel in registers and the LDL^T runs right-looking with the loops
-// unrolled against PMAX: at step k every lane publishes its a_ik to a 64-entry
-// LDS buffer, reads the column back as broadcasts, and row i > k takes
-// a_ij -= (a_ik / d_k) a_jk for the pivot columns k < j <= i.  The waves run
-// independently (one wave's LDS operations complete in program order), where
-// the one-workgroup kernel spends a workgroup and a barrier per pivot step on
-// each front.  The update block U = -L_u D L_u^T goes to the update arena and
-// the panel (D on the diagonal, unit-lower L below, as k_front_small stores
-// it) to the factor arena; the parents read both in later launches.  Pivots
-// are checked and perturbed as in every other factor path.
+// Fronts of the bottom levels (at most 64 rows and PMAX pivots), one
+// wavefront per front and four per workgroup, each with its own slice of LDS;
+// every child was factored by an earlier launch.
+//   * The pivot columns' original entries are scattered into an m x p panel
+//     in LDS (lane c < p writes column c: its diagonal and its neighbours below
+//     it, so every entry of the lower part is written once); lane i then
+//     holds row i in registers and adds both children's entries of that row
+//     (one round of loads through the gather rows, staged in LDS).
+//   * Right-looking LDL^T with the loops unrolled against PMAX: at step k
+//     every lane publishes its a_ik to a 64-entry LDS buffer, reads the
+//     column back as broadcasts, and row i > k takes a_ij -= (a_ik / d_k) a_jk
+//     for the pivot columns k < j <= i.
+//   * The panel (D on the diagonal, unit-lower L below, as k_front_small
+//     stores it) goes to the factor arena; the update block
+//     U = F22 - L_u D L_u^T is formed entry by entry over its lower triangle,
+//     enumerated column by column across the lanes (so the stores of a column
+//     are contiguous): the children's entries of F22 plus the products from
+//     the update rows of L, published to LDS.
+// The waves run independently (one wave's LDS operations complete in program
+// order), where the one-workgroup kernel spends a workgroup and a barrier per
+// pivot step on each front.  Pivots are checked and perturbed as in every
+// other factor path.
 template <typename R, int PMAX>
-__device__ __forceinline__ void leaf_front(const KArgs& a, int f, int s, int ldsw, unsigned char* smem_raw,
+__device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int ldsw, unsigned char* smem_raw,
                                            PivotStats& ps) {
   typedef typename Cx<R>::T C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
-  C* F = reinterpret_cast<C*>(smem_raw) + (size_t)wave * ldsw;  // m x p panel
+  C* F = reinterpret_cast<C*>(smem_raw + (size_t)wave * ldsw);  // m x p panel
   C* dd = F + m * p;                                             // p pivots
   C* col = dd + p;                                               // 64: the column being eliminated
+  int* gl = reinterpret_cast<int*>(col + 64);                    // 2 x 64: the children's gather rows
+  const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
+  const int32_t* g = a.gmap + a.gmap_ptr[f];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) gl[64 * k + lane] = k < nch && lane < m ? g[k * m + lane] : -1;
   for (int e = lane; e < m * p; e += 64) F[e] = czero<C>();
   wave_sync();
   if (lane < p) {
@@ -1198,10 +1210,30 @@ __device__ __forceinline__ void leaf_front(const KArgs& a, int f, int s, int lds
   }
   wave_sync();
   const bool row = lane < m;
-  C x[PMAX];
   const int lr = row ? lane : 0;  // a lane past the front reads row 0 and keeps zeros
+  C x[PMAX];
 #pragma unroll
   for (int c = 0; c < PMAX; ++c) x[c] = csel(c < p && row && lane >= c, F[min(c, p - 1) * m + lr], czero<C>());
+  // the children's entries of row lane in the pivot columns (both children's loads in flight together)
+  const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k < nch) {
+      const int chf = a.child_list[cb + k];
+      const int uk = a.nupd[chf];
+      const C* Uk = Ub + a.upd_off[chf];
+      const int gi = gl[64 * k + lane];
+      C w[PMAX];
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c) {
+        const int gc = gl[64 * k + min(c, 63)];
+        const bool ok = c < p && gi >= 0 && gc >= 0 && lane >= c && row;
+        w[c] = ok ? Uk[(int64_t)gc * uk + gi] : czero<C>();
+      }
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c) x[c] = cadd(x[c], w[c]);
+    }
+  }
   const double anorm = anorm_of(a, s);
   const double thr = a.tau * anorm;
   int npert = 0, nonfin = 0;
@@ -1212,36 +1244,59 @@ __device__ __forceinline__ void leaf_front(const KArgs& a, int f, int s, int lds
 #pragma unroll
   for (int c = 0; c < PMAX; ++c)
     if (c < p && row && lane >= c) L[(int64_t)c * m + lane] = x[c];
-  // update block: U[r][c] = -sum_k l_(p+r)k (d_k l_(p+c)k), c <= r, from the
-  // d-scaled update rows published to LDS
   if (u > 0) {
+    // the update rows of L back into the panel in LDS: the products read
+    // them (and d) as broadcasts
 #pragma unroll
     for (int c = 0; c < PMAX; ++c)
-      if (c < p && lane >= p && row) F[c * m + lane] = cmul(x[c], dd[c]);
+      if (c < p && lane >= p && row) F[c * m + lane] = x[c];
     wave_sync();
-    const int cl = p < 1 ? 0 : p - 1;
     C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
-    const int r = lane - p;
-    for (int c = 0; c < u; ++c) {
+    const int ntri = u * (u + 1) / 2;
+    for (int e0 = 0; e0 < ntri; e0 += 64) {
+      const int e = e0 + lane;
+      // column c' and row r >= c' of entry e, the lower triangle column by column
+      int cc = 0, off = 0;
+      if (e < ntri) {
+        // off(c) = c u - c (c - 1) / 2 is the first entry of column c
+        cc = (int)((2.0 * u + 1.0 - sqrt((2.0 * u + 1.0) * (2.0 * u + 1.0) - 8.0 * e)) * 0.5);
+        cc = max(0, min(cc, u - 1));
+        while (cc > 0 && cc * u - cc * (cc - 1) / 2 > e) --cc;
+        while (cc + 1 < u && (cc + 1) * u - (cc + 1) * cc / 2 <= e) ++cc;
+        off = cc * u - cc * (cc - 1) / 2;
+      }
+      const int rr = cc + (e - off);  // row of U (update-row index)
+      const bool ok = e < ntri;
+      // the children's entries of F22 at (p + rr, p + cc)
+      C v = czero<C>();
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (k < nch) {
+          const int chf = a.child_list[cb + k];
+          const int uk = a.nupd[chf];
+          const int gr = ok ? gl[64 * k + p + rr] : -1;
+          const int gc = ok ? gl[64 * k + p + cc] : -1;
+          if (gr >= 0 && gc >= 0) v = cadd(v, (Ub + a.upd_off[chf])[(int64_t)gc * uk + gr]);
+        }
+      }
       C acc = czero<C>();
 #pragma unroll
       for (int k = 0; k < PMAX; ++k)
-        if (k < p) acc = cadd(acc, cmul(x[k], F[min(k, cl) * m + p + c]));
-      if (r >= c && r < u) U[(int64_t)c * u + r] = csub(czero<C>(), acc);
+        if (k < p && ok) acc = cadd(acc, cmul(F[k * m + p + rr], cmul(F[k * m + p + cc], dd[k])));
+      if (ok) U[(int64_t)cc * u + rr] = csub(v, acc);
     }
   }
   ps.add(npert, minr, nonfin, anorm);
 }
 
 template <typename R, int PMAX>
-__global__ __launch_bounds__(kThreads) void k_leaf_fronts(KArgs a, const int32_t* order, int nitems, int ldsw) {
-  typedef typename Cx<R>::T C;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__global__ __launch_bounds__(kThreads) void k_wave_fronts(KArgs a, const int32_t* order, int nitems, int ldsw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int item = blockIdx.x * (kThreads / 64) + wave;
   if (item >= nitems) return;  // the whole wave: nothing below synchronises the workgroup
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   PivotStats ps;
-  leaf_front<R, PMAX>(a, order[item / a.nsys], item % a.nsys, ldsw, smem_raw, ps);
+  wave_front<R, PMAX>(a, order[item / a.nsys], item % a.nsys, ldsw, smem_raw, ps);
   if (lane == 0) ps.flush(a.st);
 }
 
@@ -3380,7 +3435,7 @@ KArgs make_args(Plan& P) {
   a.tau = P.pivot_tau;
   a.nfronts = P.an.nfronts;
   a.te = (P.desc.flags & FDFD_POL_TE) ? 1 : 0;
-  a.leaves_done = 0;
+  a.below_done = 0;
   return a;
 }
 
@@ -3469,32 +3524,36 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
     hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
   }
   const int32_t* lf = P.t.level_fronts;
-  // the small levels at the bottom of the tree: the leaves one wavefront
-  // each (when they fit one), then one persistent launch for the rest
+  // the small levels at the bottom of the tree: those whose fronts fit one
+  // wavefront one launch each, then one persistent launch for the rest
   if (P.small_prefix > 0) {
     const int nf = P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count;
-    const int nleaf = P.leaf_wave ? P.levels[0].count : 0;
-    if (nleaf > 0) {
+    // the bottom levels whose fronts fit one wavefront: one launch per level
+    const int nwl = (int)P.wave_front_levels.size();
+    for (int l = 0; l < nwl; ++l) {
+      const LevelPlan& LP = P.levels[l];
       double fl = 0.0;
-      for (int k = 0; k < nleaf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+      for (int k = LP.first; k < LP.first + LP.count; ++k) fl += P.front_flops[P.an.level_fronts[k]];
       Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
-      const int nitems = nleaf * nsys, wpg = kThreads / 64;
-      const size_t lds = (size_t)wpg * P.leaf_ldsw * P.csize;
+      const int nitems = LP.count * nsys, wpg = kThreads / 64;
+      const int ldsw = P.wave_front_levels[l].ldsw;
       const dim3 grid((nitems + wpg - 1) / wpg);
-      if (P.leaf_pmax <= 24)
-        hipLaunchKernelGGL((k_leaf_fronts<R, 24>), grid, dim3(kThreads), lds, st, a, lf, nitems, P.leaf_ldsw);
+      const size_t lds = (size_t)wpg * ldsw;
+      if (P.wave_front_levels[l].pmax <= 24)
+        hipLaunchKernelGGL((k_wave_fronts<R, 24>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
       else
-        hipLaunchKernelGGL((k_leaf_fronts<R, 40>), grid, dim3(kThreads), lds, st, a, lf, nitems, P.leaf_ldsw);
+        hipLaunchKernelGGL((k_wave_fronts<R, 40>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
     }
-    if (nf > nleaf) {
+    const int nskip = nwl > 0 ? P.levels[nwl - 1].first + P.levels[nwl - 1].count : 0;
+    if (nf > nskip) {
       KArgs as = a;
-      as.leaves_done = nleaf > 0 ? 1 : 0;
-      const Queue q = make_queue(P, (nf - nleaf) * nsys, 1, 0);
+      as.below_done = nwl;
+      const Queue q = make_queue(P, (nf - nskip) * nsys, 1, 0);
       double fl = 0.0;
-      for (int k = nleaf; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+      for (int k = nskip; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
       Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
-      hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, (nf - nleaf) * nsys)),
-                         dim3(kThreads), P.small_lds_prefix, st, as, q, lf + nleaf);
+      hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, (nf - nskip) * nsys)),
+                         dim3(kThreads), P.small_lds_prefix, st, as, q, lf + nskip);
     }
   }
   // every level above them: one persistent launch of the tile task graph
@@ -3711,8 +3770,8 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
 template <typename R>
 hipError_t set_lds_limits(int limit) {
   hipError_t e = hipSuccess;
-  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_leaf_fronts<R, 24>,
-                       (const void*)k_leaf_fronts<R, 40>, (const void*)k_large_tiles<R>,
+  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_wave_fronts<R, 24>,
+                       (const void*)k_wave_fronts<R, 40>, (const void*)k_large_tiles<R>,
                        (const void*)k_fwd_sweep<R>,   (const void*)k_bwd_sweep<R>,
                        (const void*)k_fwd_sweep_waves<R>, (const void*)k_bwd_sweep_waves<R>};
   for (const void* fn : fns) {

@@ -86,7 +86,12 @@ struct Plan {
   int rhs_group = 1;  // right-hand sides per sweep pass at max_rhs
   int rhs_cap = 64;   // at most this many per pass (FDFD_SWEEP_RHS)
   int split_kb = 0, block_split = 0, small_lds = 0;  // schedule knobs in effect (-1: never)
-  int leaf_wave = 0, leaf_ldsw = 0, leaf_pmax = 0;  // leaves one wavefront each; LDS entries per wave; max pivots
+  // bottom levels factored one wavefront per front (k_wave_fronts), one
+  // launch each: LDS bytes per wave and the largest pivot count of the level
+  struct WaveLevel {
+    int ldsw, pmax;
+  };
+  std::vector<WaveLevel> wave_front_levels;
   int32_t small_prefix = 0;    // leading levels run by one persistent small-front launch
   int32_t syrk_group = 8;      // pivot blocks accumulated per Schur-complement tile task
   size_t small_lds_prefix = 0;

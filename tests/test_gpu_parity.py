@@ -217,14 +217,15 @@ def test_schur_groups_forced(oracle, monkeypatch, group, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("leaf_wave", ["0", "1"])
+@pytest.mark.parametrize("wave_levels", ["0", "1", "2", "64"])
 @pytest.mark.parametrize("leaf", [16, 36])
-def test_leaf_fronts_both_paths(oracle, monkeypatch, prec, leaf_wave, leaf):
-    """The leaves factored one wavefront each (k_leaf_fronts) and in the
-    one-workgroup kernel (FDFD_LEAF_WAVE=0): both against the oracle."""
-    monkeypatch.setenv("FDFD_LEAF_WAVE", leaf_wave)
+def test_wave_fronts_all_paths(oracle, monkeypatch, prec, wave_levels, leaf):
+    """The bottom levels factored one wavefront per front (k_wave_fronts: none,
+    the leaves only, two levels, every level that qualifies) and the rest in
+    the one-workgroup kernel: all against the oracle."""
+    monkeypatch.setenv("FDFD_WAVE_FRONTS", wave_levels)
     p = P.custom_problem(90, 77, 10, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss"))
-    say(f"case leaves {'one wave each' if leaf_wave == '1' else 'one workgroup each'} leaf={leaf} {prec}")
+    say(f"case wave-front levels <= {wave_levels}, leaf={leaf} {prec}")
     eps = P.design_eps(p, t=6)
     b = P.sources(p)
     c = P.objective_vector(p)
