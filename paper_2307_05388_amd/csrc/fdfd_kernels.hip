@@ -2937,7 +2937,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_bwd_sweep(KArgs a, SweepArgs 
 // ---------------------------------------------------------------------------
 // Loads in flight per lane in the wave sweeps: fewer than in the workgroup
 // sweeps, so that four waves per SIMD stay resident (128 registers).
-template <typename R> constexpr int kWaveBatch = sizeof(R) == 8 ? 8 : 16;
+template <typename R> constexpr int kWaveBatch = sizeof(R) == 8 ? 4 : 8;
 
 
 __device__ __forceinline__ void trace_wave(const Queue& q, int t, int slot) {
@@ -3148,7 +3148,7 @@ __device__ __forceinline__ void publish_wave(const Queue& q, int ep, int64_t idx
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads, 2) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   sweep_status(w);
@@ -3177,7 +3177,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_fwd_sweep_waves(KArgs a, SweepA
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads, 2) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
