@@ -41,9 +41,9 @@ def kernel_source_sha256() -> str:
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"::(k_[a-z_0-9]+)(<(\w+)>)?\(", name)
+    m = re.search(r"::(k_[a-z_0-9]+)(<([\w, ]+)>)?\(", name)
     if m:
-        return m.group(1) + (f"<{m.group(3)}>" if m.group(3) else "")
+        return m.group(1) + (f"<{m.group(3).replace(' ', '')}>" if m.group(3) else "")
     n = name.replace("void ", "")
     depth, cut = 0, len(n)
     for i, ch in enumerate(n):   # drop the argument list (outside template brackets)
