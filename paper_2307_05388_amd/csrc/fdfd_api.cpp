@@ -236,11 +236,7 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     P.levels.push_back(L);
   }
   P.small_prefix = 0;
-  P.small_lds_prefix = 0;
-  while (P.small_prefix < (int)P.levels.size() && P.levels[P.small_prefix].small) {
-    P.small_lds_prefix = std::max(P.small_lds_prefix, P.levels[P.small_prefix].small_lds);
-    ++P.small_prefix;
-  }
+  while (P.small_prefix < (int)P.levels.size() && P.levels[P.small_prefix].small) ++P.small_prefix;
   // the bottom levels whose fronts all have at most 64 rows and 40 pivots
   // are factored one wavefront per front, a launch per level, when four such
   // fronts fit the LDS (FDFD_WAVE_FRONTS caps the number of such levels; 0

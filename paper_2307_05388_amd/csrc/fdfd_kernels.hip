@@ -3524,10 +3524,9 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
     hipLaunchKernelGGL(k_anorm, dim3(grid1d(P.an.N, 512), nsys), dim3(kThreads), 0, st, a);
   }
   const int32_t* lf = P.t.level_fronts;
-  // the small levels at the bottom of the tree: those whose fronts fit one
-  // wavefront one launch each, then one persistent launch for the rest
+  // the small levels at the bottom of the tree, one launch per level: one
+  // wavefront per front where a front fits one, else one workgroup per front
   if (P.small_prefix > 0) {
-    const int nf = P.levels[P.small_prefix - 1].first + P.levels[P.small_prefix - 1].count;
     // the bottom levels whose fronts fit one wavefront: one launch per level
     const int nwl = (int)P.wave_front_levels.size();
     for (int l = 0; l < nwl; ++l) {
@@ -3544,16 +3543,21 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
       else
         hipLaunchKernelGGL((k_wave_fronts<R, 40>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
     }
-    const int nskip = nwl > 0 ? P.levels[nwl - 1].first + P.levels[nwl - 1].count : 0;
-    if (nf > nskip) {
+    // the other small levels: one launch per level, each with the LDS its
+    // own largest front needs (the lower levels' small fronts then share a CU
+    // several at a time), every child finished by an earlier launch
+    for (int l = nwl; l < P.small_prefix; ++l) {
+      const LevelPlan& LP = P.levels[l];
       KArgs as = a;
-      as.below_done = nwl;
-      const Queue q = make_queue(P, (nf - nskip) * nsys, 1, 0);
+      as.below_done = l;
+      const int n = LP.count * nsys;
+      const Queue q = make_queue(P, n, 0, l == nwl ? 0 : -1);
       double fl = 0.0;
-      for (int k = nskip; k < nf; ++k) fl += P.front_flops[P.an.level_fronts[k]];
+      for (int k = LP.first; k < LP.first + LP.count; ++k) fl += P.front_flops[P.an.level_fronts[k]];
       Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
-      hipLaunchKernelGGL(k_front_small<R>, dim3(persistent_grid(P, P.small_lds_prefix, (nf - nskip) * nsys)),
-                         dim3(kThreads), P.small_lds_prefix, st, as, q, lf + nskip);
+      const size_t lds = (LP.small_lds + 15) & ~size_t(15);
+      hipLaunchKernelGGL(k_front_small<R>, dim3(resident_grid(P, (const void*)k_front_small<R>, lds, n)),
+                         dim3(kThreads), lds, st, as, q, lf + LP.first);
     }
   }
   // every level above them: one persistent launch of the tile task graph

@@ -92,9 +92,8 @@ struct Plan {
     int ldsw, pmax;
   };
   std::vector<WaveLevel> wave_front_levels;
-  int32_t small_prefix = 0;    // leading levels run by one persistent small-front launch
+  int32_t small_prefix = 0;    // leading levels run by the small-front launches (one per level)
   int32_t syrk_group = 8;      // pivot blocks accumulated per Schur-complement tile task
-  size_t small_lds_prefix = 0;
   int32_t n_cu = 256;
   size_t lds_limit = 65536;
   int32_t wave_levels = 0;      // bottom levels swept one wavefront per front
