@@ -1223,15 +1223,24 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
       const int uk = a.nupd[chf];
       const C* Uk = Ub + a.upd_off[chf];
       const int gi = gl[64 * k + lane];
-      C w[PMAX];
+      // eight columns' loads in flight at a time (all PMAX at once would hold
+      // the kernel to fewer waves per SIMD)
 #pragma unroll
-      for (int c = 0; c < PMAX; ++c) {
-        const int gc = gl[64 * k + min(c, 63)];
-        const bool ok = c < p && gi >= 0 && gc >= 0 && lane >= c && row;
-        w[c] = ok ? Uk[(int64_t)gc * uk + gi] : czero<C>();
+      for (int c0 = 0; c0 < PMAX; c0 += 8) {
+        if (c0 < p) {
+          C w[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int c = c0 + t;
+            const int gc = gl[64 * k + min(c, 63)];
+            const bool ok = c < p && gi >= 0 && gc >= 0 && lane >= c && row;
+            w[t] = ok ? Uk[(int64_t)gc * uk + gi] : czero<C>();
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (c0 + t < PMAX) x[c0 + t] = cadd(x[c0 + t], w[t]);
+        }
       }
-#pragma unroll
-      for (int c = 0; c < PMAX; ++c) x[c] = cadd(x[c], w[c]);
     }
   }
   const double anorm = anorm_of(a, s);
@@ -1253,10 +1262,18 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
     wave_sync();
     C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
     const int ntri = u * (u + 1) / 2;
-    for (int e0 = 0; e0 < ntri; e0 += 64) {
-      const int e = e0 + lane;
-      // column c' and row r >= c' of entry e, the lower triangle column by column
-      int cc = 0, off = 0;
+    const C* Uk[2];
+    int uk[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int chf = k < nch ? a.child_list[cb + k] : f;
+      Uk[k] = Ub + a.upd_off[chf];
+      uk[k] = a.nupd[chf];
+    }
+    // entry e of the lower triangle, column by column: column cc, row rr >= cc
+    auto entry = [&](int e, int& cc, int& rr) {
+      cc = 0;
+      int off = 0;
       if (e < ntri) {
         // off(c) = c u - c (c - 1) / 2 is the first entry of column c
         cc = (int)((2.0 * u + 1.0 - sqrt((2.0 * u + 1.0) * (2.0 * u + 1.0) - 8.0 * e)) * 0.5);
@@ -1265,25 +1282,39 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
         while (cc + 1 < u && (cc + 1) * u - (cc + 1) * cc / 2 <= e) ++cc;
         off = cc * u - cc * (cc - 1) / 2;
       }
-      const int rr = cc + (e - off);  // row of U (update-row index)
-      const bool ok = e < ntri;
-      // the children's entries of F22 at (p + rr, p + cc)
+      rr = cc + (e - off);
+    };
+    // the children's entries of F22 at (p + rr, p + cc)
+    auto kids_at = [&](int cc, int rr, bool ok) {
       C v = czero<C>();
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (k < nch) {
-          const int chf = a.child_list[cb + k];
-          const int uk = a.nupd[chf];
           const int gr = ok ? gl[64 * k + p + rr] : -1;
           const int gc = ok ? gl[64 * k + p + cc] : -1;
-          if (gr >= 0 && gc >= 0) v = cadd(v, (Ub + a.upd_off[chf])[(int64_t)gc * uk + gr]);
+          if (gr >= 0 && gc >= 0) v = cadd(v, Uk[k][(int64_t)gc * uk[k] + gr]);
         }
       }
+      return v;
+    };
+    // software pipelined: the children's entries of the next 64 entries are
+    // in flight while this round's products are formed
+    int cc, rr;
+    entry(lane, cc, rr);
+    C v = kids_at(cc, rr, lane < ntri);
+    for (int e0 = 0; e0 < ntri; e0 += 64) {
+      const bool ok = e0 + lane < ntri;
+      int cn, rn;
+      entry(e0 + 64 + lane, cn, rn);
+      const C vn = kids_at(cn, rn, e0 + 64 + lane < ntri);
       C acc = czero<C>();
 #pragma unroll
       for (int k = 0; k < PMAX; ++k)
         if (k < p && ok) acc = cadd(acc, cmul(F[k * m + p + rr], cmul(F[k * m + p + cc], dd[k])));
       if (ok) U[(int64_t)cc * u + rr] = csub(v, acc);
+      cc = cn;
+      rr = rn;
+      v = vn;
     }
   }
   ps.add(npert, minr, nonfin, anorm);
@@ -3538,7 +3569,11 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
       const int ldsw = P.wave_front_levels[l].ldsw;
       const dim3 grid((nitems + wpg - 1) / wpg);
       const size_t lds = (size_t)wpg * ldsw;
-      if (P.wave_front_levels[l].pmax <= 24)
+      if (P.wave_front_levels[l].pmax <= 8)
+        hipLaunchKernelGGL((k_wave_fronts<R, 8>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
+      else if (P.wave_front_levels[l].pmax <= 16)
+        hipLaunchKernelGGL((k_wave_fronts<R, 16>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
+      else if (P.wave_front_levels[l].pmax <= 24)
         hipLaunchKernelGGL((k_wave_fronts<R, 24>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
       else
         hipLaunchKernelGGL((k_wave_fronts<R, 40>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
@@ -3774,7 +3809,8 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
 template <typename R>
 hipError_t set_lds_limits(int limit) {
   hipError_t e = hipSuccess;
-  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_wave_fronts<R, 24>,
+  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_wave_fronts<R, 8>,
+                       (const void*)k_wave_fronts<R, 16>, (const void*)k_wave_fronts<R, 24>,
                        (const void*)k_wave_fronts<R, 40>, (const void*)k_large_tiles<R>,
                        (const void*)k_fwd_sweep<R>,   (const void*)k_bwd_sweep<R>,
                        (const void*)k_fwd_sweep_waves<R>, (const void*)k_bwd_sweep_waves<R>};
