@@ -246,14 +246,18 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
     const int cap = env_int("FDFD_WAVE_FRONTS", 1 << 20);
     const size_t lds_dyn = P.lds_limit > 512 ? P.lds_limit - 512 : 65536;
     for (int l = 0; l < P.small_prefix && (int)P.wave_front_levels.size() < cap; ++l) {
-      int mmax = 0, pmax = 0;
+      int mmax = 0, pmax = 0, umax = 0;
       for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
         const int f = A.level_fronts[k];
         mmax = std::max(mmax, A.m(f));
         pmax = std::max(pmax, A.npiv[f]);
+        umax = std::max(umax, A.nupd[f]);
       }
-      // panel m x p, p pivots, a 64-entry column buffer, two rows of 64 gather indices
-      const size_t ldsw = ((((size_t)mmax * pmax + pmax + 64) * cs + 2 * 64 * sizeof(int32_t)) + 15) / 16 * 16;
+      // per wave: four couplings per row (value and pivot column), later the
+      // update rows of L (u x p) in the same bytes; p pivots, a 64-entry
+      // column buffer, two rows of 64 gather indices
+      const size_t ub = (std::max((size_t)umax * pmax * cs, 4 * (size_t)mmax * (cs + sizeof(int32_t))) + 15) / 16 * 16;
+      const size_t ldsw = (ub + ((size_t)pmax + 64) * cs + 128 * sizeof(int32_t) + 15) / 16 * 16;
       if (mmax > 64 || pmax > 40 || 4 * ldsw > lds_dyn) break;
       P.wave_front_levels.push_back({(int)ldsw, pmax});
     }

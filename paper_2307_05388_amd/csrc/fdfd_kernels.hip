@@ -1163,11 +1163,11 @@ struct LeafSteps {
 // Fronts of the bottom levels (at most 64 rows and PMAX pivots), one
 // wavefront per front and four per workgroup, each with its own slice of LDS;
 // every child was factored by an earlier launch.
-//   * The pivot columns' original entries are scattered into an m x p panel
-//     in LDS (lane c < p writes column c: its diagonal and its neighbours below
-//     it, so every entry of the lower part is written once); lane i then
-//     holds row i in registers and adds both children's entries of that row
-//     (one round of loads through the gather rows, staged in LDS).
+//   * Lane i holds row i of the pivot columns in registers: its diagonal, if a
+//     pivot, from its own stencil, and its entries in the earlier pivot
+//     columns from the couplings those pivot lanes leave in its four LDS
+//     slots (one per direction); then both children's entries of the row are
+//     added (loads through the gather rows, staged in LDS).
 //   * Right-looking LDL^T with the loops unrolled against PMAX: at step k
 //     every lane publishes its a_ik to a 64-entry LDS buffer, reads the
 //     column back as broadcasts, and row i > k takes a_ij -= (a_ik / d_k) a_jk
@@ -1177,7 +1177,7 @@ struct LeafSteps {
 //     U = F22 - L_u D L_u^T is formed entry by entry over its lower triangle,
 //     enumerated column by column across the lanes (so the stores of a column
 //     are contiguous): the children's entries of F22 plus the products from
-//     the update rows of L, published to LDS.
+//     the update rows of L, published to LDS (the only panel part kept there).
 // The waves run independently (one wave's LDS operations complete in program
 // order), where the one-workgroup kernel spends a workgroup and a barrier per
 // pivot step on each front.  Pivots are checked and perturbed as in every
@@ -1188,32 +1188,60 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
   typedef typename Cx<R>::T C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
-  C* F = reinterpret_cast<C*>(smem_raw + (size_t)wave * ldsw);  // m x p panel
-  C* dd = F + m * p;                                             // p pivots
-  C* col = dd + p;                                               // 64: the column being eliminated
-  int* gl = reinterpret_cast<int*>(col + 64);                    // 2 x 64: the children's gather rows
+  // the wave's slice: the rows' couplings (4m values, then 4m pivot
+  // columns) until the rows are loaded, after the elimination the update
+  // rows of L (u x p) in the same bytes; then p pivots, a 64-entry column
+  // buffer and two rows of 64 gather indices
+  unsigned char* base = smem_raw + (size_t)wave * ldsw;
+  const int ub = (max(u * p * (int)sizeof(C), 4 * m * ((int)sizeof(C) + 4)) + 15) & ~15;
+  C* Fu = reinterpret_cast<C*>(base);
+  C* sv = reinterpret_cast<C*>(base);
+  int* sc = reinterpret_cast<int*>(base + 4 * m * sizeof(C));
+  C* dd = reinterpret_cast<C*>(base + ub);
+  C* col = dd + p;
+  int* gl = reinterpret_cast<int*>(col + 64);
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];
 #pragma unroll
   for (int k = 0; k < 2; ++k) gl[64 * k + lane] = k < nch && lane < m ? g[k * m + lane] : -1;
-  for (int e = lane; e < m * p; e += 64) F[e] = czero<C>();
-  wave_sync();
-  if (lane < p) {
-    const int q = pb + lane;
-    const Stencil S = stencil_at(a, s, a.perm[q]);
-    F[lane * m + lane] = from_d2<C>(S.diag);
+  if (lane < m) {
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int r = a.nbr_row[4 * (int64_t)q + d];
-      if (r > lane) F[lane * m + r] = from_d2<C>(S.c[d]);
-    }
+    for (int d = 0; d < 4; ++d) sc[4 * lane + d] = -1;
   }
   wave_sync();
   const bool row = lane < m;
-  const int lr = row ? lane : 0;  // a lane past the front reads row 0 and keeps zeros
   C x[PMAX];
 #pragma unroll
-  for (int c = 0; c < PMAX; ++c) x[c] = csel(c < p && row && lane >= c, F[min(c, p - 1) * m + lr], czero<C>());
+  for (int c = 0; c < PMAX; ++c) x[c] = czero<C>();
+  if (lane < p) {
+    // pivot lane c: its diagonal, and its couplings to the later rows r > c
+    // go to row r's slots, one per direction (a row has one neighbour per
+    // direction, so no two pivots share a slot)
+    const int q = pb + lane;
+    const Stencil S = stencil_at(a, s, a.perm[q]);
+    const C dg = from_d2<C>(S.diag);
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c) x[c] = csel(c == lane, dg, x[c]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int r = a.nbr_row[4 * (int64_t)q + d];
+      if (r > lane) {
+        sv[4 * r + d] = from_d2<C>(S.c[d]);
+        sc[4 * r + d] = lane;
+      }
+    }
+  }
+  wave_sync();
+  if (row) {
+    // row lane's entries in the pivot columns before it
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int c = sc[4 * lane + d];
+      const C v = sv[4 * lane + d];
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k) x[k] = csel(k == c, v, x[k]);
+    }
+  }
   // the children's entries of row lane in the pivot columns (both children's loads in flight together)
   const C* Ub = (const C*)a.upd + (int64_t)s * a.upd_total;
 #pragma unroll
@@ -1258,7 +1286,7 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
     // them (and d) as broadcasts
 #pragma unroll
     for (int c = 0; c < PMAX; ++c)
-      if (c < p && lane >= p && row) F[c * m + lane] = x[c];
+      if (c < p && lane >= p && row) Fu[c * u + lane - p] = x[c];
     wave_sync();
     C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
     const int ntri = u * (u + 1) / 2;
@@ -1310,7 +1338,7 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
       C acc = czero<C>();
 #pragma unroll
       for (int k = 0; k < PMAX; ++k)
-        if (k < p && ok) acc = cadd(acc, cmul(F[k * m + p + rr], cmul(F[k * m + p + cc], dd[k])));
+        if (k < p && ok) acc = cadd(acc, cmul(Fu[k * u + rr], cmul(Fu[k * u + cc], dd[k])));
       if (ok) U[(int64_t)cc * u + rr] = csub(v, acc);
       cc = cn;
       rr = rn;
@@ -1320,8 +1348,11 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
   ps.add(npert, minr, nonfin, anorm);
 }
 
+// Waves per SIMD the register budget must allow: three for up to 24 pivots
+// (the bottom level's fronts), two above.
 template <typename R, int PMAX>
-__global__ __launch_bounds__(kThreads) void k_wave_fronts(KArgs a, const int32_t* order, int nitems, int ldsw) {
+__global__ __launch_bounds__(kThreads, PMAX <= 24 ? 3 : 2) void k_wave_fronts(KArgs a, const int32_t* order, int nitems,
+                                                                             int ldsw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int item = blockIdx.x * (kThreads / 64) + wave;
   if (item >= nitems) return;  // the whole wave: nothing below synchronises the workgroup
