@@ -2700,6 +2700,49 @@ __device__ __forceinline__ void bwd_block(const C* L, int ldl, const C* X, C* re
   }
 }
 
+// A pivot block's column sums from a tile of at most 64 rows whose entries
+// were loaded ahead (bwd_tile_load, before the wait for the right-hand side):
+// the same lanes, rows and summation order as bwd_dots.
+template <typename C>
+__device__ __forceinline__ void bwd_tile_load(const C* Lc, bool colok, int r0, int r1, C (&l)[8]) {
+  const int q = (threadIdx.x & 63) >> 4, rq = (threadIdx.x >> 6) >> 2;
+  const int per = (r1 - r0 + kNQ - 1) / kNQ;  // at most 32 rows: eight per thread
+  const int q0 = r0 + rq * per, q1 = min(r1, q0 + per);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) l[t] = colok && q0 + q + 4 * t < q1 ? Lc[q0 + q + 4 * t] : czero<C>();
+}
+
+template <int NR, typename C>
+__device__ __forceinline__ void bwd_tile_group(const C (&l)[8], const C* X, C* red, int m, int r0, int r1, int c0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, rq = wave >> 2, jj = 16 * (wave & 3) + (lane & 15);
+  const int per = (r1 - r0 + kNQ - 1) / kNQ;
+  const int q0 = r0 + rq * per, q1 = min(r1, q0 + per);
+  C acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    acc[c] = czero<C>();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = q0 + q + 4 * t;
+      acc[c] = cadd(acc[c], cmul(l[t], i < q1 ? X[(c0 + c) * m + i] : czero<C>()));
+    }
+    acc[c] = cadd(acc[c], shfl_xor_c(acc[c], 16));
+    acc[c] = cadd(acc[c], shfl_xor_c(acc[c], 32));
+  }
+  if (lane < 16)
+#pragma unroll
+    for (int c = 0; c < NR; ++c) red[((c0 + c) * kNQ + rq) * kBW + jj] = acc[c];
+}
+
+template <typename C>
+__device__ __forceinline__ void bwd_tile(const C (&l)[8], const C* X, C* red, int m, int r0, int r1, int nrhs) {
+  for (int c0 = 0; c0 < nrhs; c0 += 2) {
+    if (nrhs - c0 >= 2) bwd_tile_group<2>(l, X, red, m, r0, r1, c0);
+    else bwd_tile_group<1>(l, X, red, m, r0, r1, c0);
+  }
+}
+
 // One front of the backward sweep.  X = [z_p; x(update rows)]; for kBW-wide
 // blocks from the last: X_blk -= L_below,blk^T X_below, then
 // X_blk <- Xinv^T X_blk (column dot products, bwd_dots; the row parts meet
@@ -2819,8 +2862,19 @@ __device__ void bwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
     X[col * m + r] = v;
   }
   const int nbk = (p + kBW - 1) / kBW;
+  // this thread's column of the block (bwd_dots' lane layout) and the tiles
+  // of it that the chain waits on, loaded ahead of each wait: block jp's
+  // rows before the wait for x_jp, the inverse's before the last wait
+  const int jj = 16 * ((threadIdx.x >> 6) & 3) + (threadIdx.x & 15);
+  const bool colok = jj < kn;
+  const C* Lj = L + (int64_t)(k0 + min(jj, kn - 1)) * ldl;
+  C li[8];
+  if (nbk - 1 == j) bwd_tile_load(Lj + k0, colok, jj + 1, kn, li);
   for (int jp = nbk - 1; jp > j; --jp) {
     const int kb = jp * kBW, kbn = min(kBW, p - kb);
+    C lt[8];
+    bwd_tile_load(Lj, colok, kb, kb + kbn, lt);
+    if (jp == j + 1) bwd_tile_load(Lj + k0, colok, jj + 1, kn, li);
     if (threadIdx.x == 0) {
       wait_flag(q, ep, blk_flag(q, a, w, s, f, jp));
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -2831,19 +2885,19 @@ __device__ void bwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
       X[col * m + r] = ld_ag(Y + (int64_t)col * a.N + pb + r);
     }
     __syncthreads();
-    bwd_block(L, ldl, X, red, m, k0, kn, kb, kb + kbn, nrhs, false);
+    bwd_tile(lt, X, red, m, kb, kb + kbn, nrhs);
     __syncthreads();
     for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
-      const int col = idx / kn, jj = idx - col * kn;
-      const C* rr = red + col * kNQ * kBW + jj;
+      const int col = idx / kn, jj2 = idx - col * kn;
+      const C* rr = red + col * kNQ * kBW + jj2;
       C acc = czero<C>();
 #pragma unroll
       for (int qq = 0; qq < kNQ; ++qq) acc = cadd(acc, rr[qq * kBW]);
-      X[col * m + k0 + jj] = csub(X[col * m + k0 + jj], acc);
+      X[col * m + k0 + jj2] = csub(X[col * m + k0 + jj2], acc);
     }
   }
   __syncthreads();
-  bwd_block(L, ldl, X, red, m, k0, kn, k0 + kn, m, nrhs, true);
+  bwd_tile(li, X + k0, red, m, jj + 1, kn, nrhs);
   __syncthreads();
   double2* O = w.out + (int64_t)s * w.io_ld;
   for (int idx = threadIdx.x; idx < kn * nrhs; idx += kSweepThreads) {
