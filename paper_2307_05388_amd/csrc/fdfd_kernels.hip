@@ -2455,6 +2455,18 @@ __device__ void fwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
   }
   for (int idx = threadIdx.x; idx < kSW * kBW * nrhs; idx += kSweepThreads) red[idx] = czero<C>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the stored strictly lower part of the block's inverted unit-lower
+  // diagonal block, loaded ahead of the last wait of the chain
+  const C* Xb = L + (int64_t)k0 * ldl + k0;
+  C xv[NT];
+  auto load_inv = [&]() {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int jj = wave + kSW * t;
+      xv[t] = (lane < kn && jj < lane) ? Xb[(int64_t)jj * ldl + lane] : czero<C>();
+    }
+  };
+  if (j == 0) load_inv();
   for (int jp = 0; jp < j; ++jp) {
     C l[NT];
 #pragma unroll
@@ -2462,6 +2474,7 @@ __device__ void fwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
       const int c = jp * kBW + wave + kSW * t;
       l[t] = lane < kn ? L[(int64_t)c * ldl + k0 + lane] : czero<C>();
     }
+    if (jp == j - 1) load_inv();
     if (threadIdx.x == 0) {
       wait_flag(q, ep, blk_flag(q, a, w, s, f, jp));
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -2491,14 +2504,7 @@ __device__ void fwd_piv_block(const KArgs& a, const SweepArgs& w, const Queue& q
   }
   __syncthreads();
   {
-    // V <- Xinv V: the stored strictly lower part of the inverted unit-lower block
-    const C* Xb = L + (int64_t)k0 * ldl + k0;
-    C xv[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int jj = wave + kSW * t;
-      xv[t] = (lane < kn && jj < lane) ? Xb[(int64_t)jj * ldl + lane] : czero<C>();
-    }
+    // V <- Xinv V
     for (int col = 0; col < nrhs; ++col) {
       C acc = czero<C>();
 #pragma unroll
