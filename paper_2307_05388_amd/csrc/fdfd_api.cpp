@@ -546,8 +546,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.wave_levels = P.small_prefix;
   P.wave_ld = 0;
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
-  // forward sweep items of the levels above: each front's pivot part, then
-  // the update-row chunks of the fronts whose L21 is split.  The pivot part
+  // forward sweep items of the levels above: per level, the fronts' pivot
+  // parts, then the update-row chunks of the fronts whose L21 is split.  The pivot part
   // of a front with many pivot blocks is itself split, one item per 64-row
   // pivot block (part -1 - j for block j), whose triangular solves stream the
   // other blocks' results as they are published; such a front always has
@@ -556,8 +556,6 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   std::vector<int32_t> blk_base(P.an.nfronts, -1);
   std::vector<int64_t> part_base(P.an.nfronts, 0);
   {
-    const int nlow =
-        P.wave_levels > 0 ? P.levels[P.wave_levels - 1].first + P.levels[P.wave_levels - 1].count : 0;
     int nc_total = 0, nb_total = 0;
     // FDFD_SPLIT_KB: the L21 size (KiB) from which a front is split;
     // FDFD_BLOCK_SPLIT: pivot blocks from which the pivot part is split (0 = never)
@@ -568,56 +566,70 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
                                                    : env_int("FDFD_BLOCK_SPLIT", fdfd::kBlockSplit);
     P.split_kb = split_kb < 0 ? -1 : split_kb;
     P.block_split = block_split > 0 ? block_split : -1;
-    for (int k = nlow; k < P.an.nfronts; ++k) {
-      const int f = P.an.level_fronts[k];
-      const int64_t p = P.an.npiv[f], u = P.an.nupd[f];
-      const int nbk = (int)((p + fdfd::kChunkRows - 1) / fdfd::kChunkRows);
-      const bool bsplit = block_split > 0 && nbk >= block_split;
-      const bool split = u > 0 && (bsplit || u * p * (int64_t)cs >= split_bytes);
-      const int nc = split ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
-      nch[f] = nc;
-      chunk_base[f] = nc_total;
-      if (bsplit) {
-        blk_base[f] = nb_total;
-        nb_total += nbk;
-        for (int j = 0; j < nbk; ++j) {
+    // per level, every front's pivot part first, then all the update-row
+    // chunks (a chunk waits for its front's pivot part; listing the level's
+    // pivot parts together lets them all start at once)
+    for (int l = P.wave_levels; l < (int)P.levels.size(); ++l) {
+      const int k_lo = P.levels[l].first, k_hi = k_lo + P.levels[l].count;
+      for (int k = k_lo; k < k_hi; ++k) {
+        const int f = P.an.level_fronts[k];
+        const int64_t p = P.an.npiv[f], u = P.an.nupd[f];
+        const int nbk = (int)((p + fdfd::kChunkRows - 1) / fdfd::kChunkRows);
+        const bool bsplit = block_split > 0 && nbk >= block_split;
+        const bool split = u > 0 && (bsplit || u * p * (int64_t)cs >= split_bytes);
+        const int nc = split ? (int)((u + fdfd::kChunkRows - 1) / fdfd::kChunkRows) : 0;
+        nch[f] = nc;
+        chunk_base[f] = nc_total;
+        nc_total += nc;
+        if (bsplit) {
+          blk_base[f] = nb_total;
+          nb_total += nbk;
+          for (int j = 0; j < nbk; ++j) {
+            fwd_items.push_back(f);
+            fwd_items.push_back(-1 - j);
+          }
+        } else {
           fwd_items.push_back(f);
-          fwd_items.push_back(-1 - j);
+          fwd_items.push_back(-1);
         }
-      } else {
-        fwd_items.push_back(f);
-        fwd_items.push_back(-1);
       }
-      for (int j = 0; j < nc; ++j) {
-        fwd_items.push_back(f);
-        fwd_items.push_back(j);
+      for (int k = k_lo; k < k_hi; ++k) {
+        const int f = P.an.level_fronts[k];
+        for (int j = 0; j < nch[f]; ++j) {
+          fwd_items.push_back(f);
+          fwd_items.push_back(j);
+        }
       }
-      nc_total += nc;
     }
     P.n_fwd_items = (int32_t)(fwd_items.size() / 2);
     P.nchunk = nc_total;
     P.nblk = nb_total;
     // backward: root first, a front's chunks (partial column sums of its
-    // update rows) before its pivot part, the pivot blocks last to first
+    // update rows) right before its pivot part, a split pivot part's blocks
+    // last to first (a pivot part releases the level below, so each front's
+    // items stay together)
     int64_t pt = 0;
-    for (int k = P.an.nfronts - 1; k >= nlow; --k) {
-      const int f = P.an.level_fronts[k];
-      for (int j = 0; j < nch[f]; ++j) {
-        bwd_items.push_back(f);
-        bwd_items.push_back(j);
-      }
-      if (blk_base[f] >= 0) {
-        const int nbk = (P.an.npiv[f] + fdfd::kChunkRows - 1) / fdfd::kChunkRows;
-        for (int j = nbk - 1; j >= 0; --j) {
+    for (int l = (int)P.levels.size() - 1; l >= P.wave_levels; --l) {
+      const int k_lo = P.levels[l].first, k_hi = k_lo + P.levels[l].count;
+      for (int k = k_hi - 1; k >= k_lo; --k) {
+        const int f = P.an.level_fronts[k];
+        for (int j = 0; j < nch[f]; ++j) {
           bwd_items.push_back(f);
-          bwd_items.push_back(-1 - j);
+          bwd_items.push_back(j);
         }
-      } else {
-        bwd_items.push_back(f);
-        bwd_items.push_back(-1);
+        if (blk_base[f] >= 0) {
+          const int nbk = (P.an.npiv[f] + fdfd::kChunkRows - 1) / fdfd::kChunkRows;
+          for (int j = nbk - 1; j >= 0; --j) {
+            bwd_items.push_back(f);
+            bwd_items.push_back(-1 - j);
+          }
+        } else {
+          bwd_items.push_back(f);
+          bwd_items.push_back(-1);
+        }
+        part_base[f] = pt;
+        pt += (int64_t)nch[f] * P.an.npiv[f];
       }
-      part_base[f] = pt;
-      pt += (int64_t)nch[f] * P.an.npiv[f];
     }
     P.part_total = pt;
     P.n_bwd_items = (int32_t)(bwd_items.size() / 2);
