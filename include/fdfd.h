@@ -170,6 +170,9 @@ typedef struct {
  *                   and 40 pivots; 0 = none, default all that qualify);
  *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
  *                   passes also never take more than fit the LDS);
+ *   FDFD_SWEEP_GROUP height of the bottom-level subtrees one wavefront
+ *                   sweeps whole, children before parents (default 3;
+ *                   0 = one front at a time);
  *   FDFD_PIVOT_TAU  static pivot threshold relative to the matrix norm;
  *   FDFD_TRACE      file for per-task timestamps (written by fdfd_query).
  * max_rhs is not limited by the front sizes: the sweeps hold a front's

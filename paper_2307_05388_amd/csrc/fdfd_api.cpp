@@ -546,6 +546,45 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.wave_levels = P.small_prefix;
   P.wave_ld = 0;
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
+  // their sweep items: every front of height <= H (FDFD_SWEEP_GROUP, default
+  // 3) belongs to the subtree of its highest ancestor of height <= H, which
+  // one wavefront sweeps whole, children before parents (no wait between
+  // them); the fronts above H up to the wave levels' top are items of their
+  // own, level by level.  No subtree item depends on another.
+  {
+    const int lw = P.wave_levels;
+    P.sweep_group = lw > 0 ? std::max(0, std::min(env_int("FDFD_SWEEP_GROUP", 3), lw - 1)) : 0;
+    const int H = P.sweep_group;
+    const fdfd::Analysis& A = P.an;
+    std::vector<int32_t>& seq = P.wave_seq_host;
+    std::vector<int32_t>& iptr = P.wave_item_ptr_host;
+    seq.clear();
+    iptr.assign(1, 0);
+    std::vector<int32_t> stack;
+    for (int l = 0; l < lw && l <= H; ++l)
+      for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
+        const int g = A.level_fronts[k];
+        const int par = A.parent[g];
+        if (A.height[g] > H || (par >= 0 && A.height[par] <= H)) continue;  // not a subtree root
+        // post-order of g's subtree: reversed pre-order with children pushed in order
+        const size_t at = seq.size();
+        stack.assign(1, g);
+        while (!stack.empty()) {
+          const int f = stack.back();
+          stack.pop_back();
+          seq.push_back(f);
+          for (int c = A.child_ptr[f]; c < A.child_ptr[f + 1]; ++c) stack.push_back(A.child_list[c]);
+        }
+        std::reverse(seq.begin() + (std::ptrdiff_t)at, seq.end());
+        iptr.push_back((int32_t)seq.size());
+      }
+    for (int l = H + 1; l < lw; ++l)
+      for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
+        seq.push_back(A.level_fronts[k]);
+        iptr.push_back((int32_t)seq.size());
+      }
+    P.wave_items = (int32_t)iptr.size() - 1;
+  }
   // forward sweep items of the levels above: per level, the fronts' pivot
   // parts, then the update-row chunks of the fronts whose L21 is split.  The pivot part
   // of a front with many pivot blocks is itself split, one item per 64-row
@@ -685,6 +724,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     TRY(upload(P, &P.t.perm, A.perm));
     TRY(upload(P, &P.t.iperm, A.iperm));
     TRY(upload(P, &P.t.level_fronts, A.level_fronts));
+    TRY(upload(P, &P.t.wave_seq, P.wave_seq_host));
+    TRY(upload(P, &P.t.wave_item_ptr, P.wave_item_ptr_host));
     TRY(upload(P, &P.t.tile_tasks, tasks));
     P.tile_tasks_host = tasks;
     TRY(upload(P, &P.t.tile_base, tile_base));
@@ -957,6 +998,10 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
           int it[5] = {-1, -1, -1, -1, -1};
           if (k == 1) {
             for (int q = 0; q < 5; ++q) it[q] = P.tile_tasks_host[5 * (t / ns) + q];
+          } else if (k >= 2 && P.wave_items > 0) {
+            // a bottom-level sweep item: its subtree root (or single front)
+            const int pos = t / ns, item = k == 2 ? pos : P.wave_items - 1 - pos;
+            it[1] = P.wave_seq_host[P.wave_item_ptr_host[item + 1] - 1];
           } else {
             const int pos = t / ns;
             // the small-front launch starts above the levels k_wave_fronts took

@@ -3269,8 +3269,13 @@ __device__ __forceinline__ void publish_wave(const Queue& q, int ep, int64_t idx
   if ((threadIdx.x & 63) == 0) __hip_atomic_store(q.done + idx, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Items: seq[iptr[i] .. iptr[i+1]) -- a subtree of the bottom levels,
+// children before parents, or a single front.  The wave sweeps the item's
+// fronts in turn; a front's wait for its children ends at once for those
+// the wave itself just published.
 template <typename R>
-__global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* seq,
+                                                                 const int32_t* iptr) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   sweep_status(w);
@@ -3285,21 +3290,26 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepA
     const int t = t0 + wave;
     if (t < q.ntasks) {
       trace_wave(q, t, 0);
-      const int f = order[t / a.nsys], s = t % a.nsys;
-      if (q.wait) sweep_wait_children(q, ep, a, w, s, f, threadIdx.x & 63, 64);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      trace_wave(q, t, 1);
-      fwd_front_wave<R>(a, w, s, f, V, w.wave_ld);
-      publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+      const int it = t / a.nsys, s = t % a.nsys;
+      for (int e = iptr[it]; e < iptr[it + 1]; ++e) {
+        const int f = seq[e];
+        if (q.wait) sweep_wait_children(q, ep, a, w, s, f, threadIdx.x & 63, 64);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (e == iptr[it]) trace_wave(q, t, 1);
+        fwd_front_wave<R>(a, w, s, f, V, w.wave_ld);
+        publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+      }
       trace_wave(q, t, 2);
     }
   }
   leave(q, ep);
 }
 
+// The same items in reverse, each swept parents first.
 template <typename R>
-__global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* seq,
+                                                                 const int32_t* iptr) {
   typedef typename Cx<R>::T C;
   if (done(w.flag)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -3313,13 +3323,16 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepA
     const int t = t0 + wave;
     if (t < q.ntasks) {
       trace_wave(q, t, 0);
-      const int f = order[q.ntasks / a.nsys - 1 - t / a.nsys], s = t % a.nsys;
-      if (q.wait && (threadIdx.x & 63) == 0) sweep_wait_parent(q, ep, a, w, s, f);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      trace_wave(q, t, 1);
-      bwd_front_wave<R>(a, w, s, f, X, w.wave_ld);
-      publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+      const int it = q.ntasks / a.nsys - 1 - t / a.nsys, s = t % a.nsys;
+      for (int e = iptr[it + 1] - 1; e >= iptr[it]; --e) {
+        const int f = seq[e];
+        if (q.wait && (threadIdx.x & 63) == 0) sweep_wait_parent(q, ep, a, w, s, f);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (e == iptr[it + 1] - 1) trace_wave(q, t, 1);
+        bwd_front_wave<R>(a, w, s, f, X, w.wave_ld);
+        publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+      }
       trace_wave(q, t, 2);
     }
   }
@@ -3772,10 +3785,10 @@ void sweep_cols(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src
   w.part_total = P.part_total;
   w.blk_base = P.t.blk_base;
   w.nblk = P.nblk;
-  const int32_t* lf = P.t.level_fronts;
   const int nlev = (int)P.levels.size();
   const int lw = P.wave_levels;
   const int nlow = lw > 0 ? P.levels[lw - 1].first + P.levels[lw - 1].count : 0;
+  const int nwi = P.wave_items;  // sweep items of those levels
   const int nhigh = P.an.nfronts - nlow;
   // algorithmic bytes: the lower-trapezoid factor once, the input vector read
   // in one precision and the output written in another
@@ -3793,10 +3806,10 @@ void sweep_cols(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src
     SweepArgs wl = w;
     wl.lev_lo = 0;
     wl.lev_hi = lw;
-    const int n = nlow * nsys;
+    const int n = nwi * nsys;
     Prof pr(P, st, KC_FWD_SWEEP, fb_low, 0.0);
     hipLaunchKernelGGL((k_fwd_sweep_waves<R>), dim3(resident_grid(P, fw, wlds, (n + 3) / 4)), dim3(kThreads), wlds,
-                       st, a, wl, make_queue(P, n, 1, 2), lf);
+                       st, a, wl, make_queue(P, n, 1, 2), P.t.wave_seq, P.t.wave_item_ptr);
     w.status_mode = -1;
   }
   if (nhigh > 0) {
@@ -3826,10 +3839,10 @@ void sweep_cols(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src
     wl.status_mode = -1;
     wl.lev_lo = 0;
     wl.lev_hi = lw;
-    const int n = nlow * nsys;
+    const int n = nwi * nsys;
     Prof pr(P, st, KC_BWD_SWEEP, fb_low, 0.0);
     hipLaunchKernelGGL((k_bwd_sweep_waves<R>), dim3(resident_grid(P, bw, wlds, (n + 3) / 4)), dim3(kThreads), wlds,
-                       st, a, wl, make_queue(P, n, 1, nhigh > 0 ? -1 : 3), lf);
+                       st, a, wl, make_queue(P, n, 1, nhigh > 0 ? -1 : 3), P.t.wave_seq, P.t.wave_item_ptr);
   }
 }
 

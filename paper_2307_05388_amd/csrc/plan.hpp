@@ -36,6 +36,7 @@ struct DevTables {
   int32_t *gmap = nullptr, *nbr_row = nullptr;
   int32_t *perm = nullptr, *iperm = nullptr;
   int32_t *level_fronts = nullptr;
+  int32_t *wave_seq = nullptr, *wave_item_ptr = nullptr;  // bottom-level sweep items
   int32_t *parent = nullptr, *height = nullptr;
   int32_t *tile_tasks = nullptr, *tile_base = nullptr, *is_tiled = nullptr;
   int32_t *fwd_items = nullptr, *bwd_items = nullptr, *nch = nullptr, *chunk_base = nullptr, *blk_base = nullptr;
@@ -98,6 +99,9 @@ struct Plan {
   size_t lds_limit = 65536;
   int32_t wave_levels = 0;      // bottom levels swept one wavefront per front
   int32_t wave_ld = 0;          // largest front (rows) among them
+  int32_t wave_items = 0;       // their sweep items: a subtree (children first) or one front
+  int32_t sweep_group = 0;      // height of the subtrees one sweep item takes
+  std::vector<int32_t> wave_seq_host, wave_item_ptr_host;
   // Forward sweep of the tiled levels: work items (front, part) in claim
   // order, part -1 the pivot rows, part j >= 0 the j-th kChunkRows update
   // rows of a front whose L21 is split over several workgroups.

@@ -240,3 +240,30 @@ def test_wave_fronts_all_paths(oracle, monkeypatch, prec, wave_levels, leaf):
     assert entry_err(out["x"], ref["x"]) < 1e3 * tol
     assert rel(out["grad"], ref["grad"]) < 10 * tol
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("group", ["0", "1", "2", "4", "99"])
+def test_sweep_subtree_items(oracle, monkeypatch, prec, group):
+    """The bottom-level sweeps with each wavefront taking a whole subtree of
+    height <= FDFD_SWEEP_GROUP (children first, parents first backwards; 0 =
+    one front per item, 99 = every bottom level), with three right-hand sides
+    and two systems: against the oracle."""
+    monkeypatch.setenv("FDFD_SWEEP_GROUP", group)
+    p = P.custom_problem(90, 77, 10, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss", "line"))
+    say(f"case sweep subtree items of height <= {group}, {prec}")
+    eps = P.design_eps(p, t=7)
+    b = P.sources(p)
+    c = P.objective_vector(p)
+    plan = make_plan(p, prec, leaf=16, small_lds=98304)
+    assert plan.query()["small_levels"] >= 3
+    ir = (10, 1e-12) if prec == "c64" else (0, 0.0)
+    out = gpu_iteration(plan, p, eps, b, c=c, max_ir=ir[0], tol=ir[1])
+    ref = _oracle(oracle, p, eps, b, c=c)
+    tol = 1e-10 if prec == "c128" else 1e-8
+    say(f"  x {rel(out['x'], ref['x']):.2e} lam {rel(out['lam'], ref['lam']):.2e} grad {rel(out['grad'], ref['grad']):.2e}")
+    assert out["info"]["status"] in (0, 6)
+    assert rel(out["x"], ref["x"]) < tol and rel(out["lam"], ref["lam"]) < tol
+    assert entry_err(out["x"], ref["x"]) < 1e3 * tol
+    assert rel(out["grad"], ref["grad"]) < 10 * tol
+    plan.close()
