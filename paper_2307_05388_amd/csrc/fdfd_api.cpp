@@ -222,10 +222,10 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       L.max_m = std::max(L.max_m, A.m(f));
       L.max_p = std::max(L.max_p, A.npiv[f]);
       L.max_u = std::max(L.max_u, A.nupd[f]);
-      // panel, d, 1/d, then the dense routines' scratch: 16 x 16 for the inverse
-      // blocks, 16 x (p - 16) for the d-scaled columns of the trailing update;
-      // then the children's gather rows (two rows of m ints)
-      const size_t scratch = std::max<size_t>(256, 16 * (size_t)std::max(0, A.npiv[f] - 16));
+      // panel, d, 1/d, then the dense routines' scratch (the LDL^T's 2 x 64
+      // pivot-column buffer, and the stencils staged before it: 5p values and
+      // 4p indices from d on); then the children's gather rows (two rows of m ints)
+      const size_t scratch = std::max<size_t>(128, 5 * (size_t)A.npiv[f]);
       const size_t rows = (8 * (size_t)A.m(f) + 15) & ~size_t(15);
       need = std::max(need, ((size_t)A.m(f) * A.npiv[f] + 2 * (size_t)A.npiv[f] + scratch) * cs + rows);
       L.lbytes += P.front_lbytes[f];

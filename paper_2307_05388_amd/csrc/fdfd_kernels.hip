@@ -747,10 +747,13 @@ __device__ void trsm_rows16(C* F, int ld, int o, int b, int r0, int m, const C* 
 // first; then lane = row (its 16 L values in registers), wave w takes the
 // columns c0+w, c0+w+4, ... and reads their scaled rows as broadcasts.
 template <typename C>
-__device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const C* dd, C* Lsc) {
+__device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const C* dd) {
+  // the d-scaled rows d_q L[c][o+q] go to rows o .. o+15 of column c, above
+  // its diagonal (c >= c0 = o + 16): nothing reads the panel's upper part,
+  // and the updates below touch rows >= c0 only
   for (int idx = threadIdx.x; idx < (p - c0) * 16; idx += kThreads) {
     const int c = c0 + (idx >> 4), q = idx & 15;
-    Lsc[idx] = q < b ? cmul(F[(o + q) * ld + c], dd[o + q]) : czero<C>();
+    F[c * ld + o + q] = q < b ? cmul(F[(o + q) * ld + c], dd[o + q]) : czero<C>();
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -761,7 +764,7 @@ __device__ void trail16(C* F, int ld, int o, int b, int c0, int p, int m, const 
     // uniform trip count: rows r < c update entries above the diagonal,
     // which no later step reads
     for (int c = c0 + wave; c < p; c += 4) {
-      const C* sc = Lsc + (c - c0) * 16;
+      const C* sc = F + c * ld + o;
       C acc = F[c * ld + r];
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc = cfms(acc, lr[q], sc[q]);
@@ -821,7 +824,9 @@ __device__ __forceinline__ void trail_mfma(C* F, int o, int b, int c0, int p, co
 // panel: per 16-column sub-block, wave 0 factors the diagonal sub-block, all
 // threads solve the rows below it and update the remaining panel columns.
 // Leaves the unit-lower L in place and d, 1/d in dd / invd.
-// scratch: 16 x 64 entries of LDS (pivot column buffer, scaled columns).
+// scratch: the pivot column buffer (2 x 64 entries of LDS); the diagonal tile
+// (DiagTile) also keeps its d-scaled rows there (16 x 64), the panel of a
+// small front in its own upper part.
 // DiagTile: the kBW x kBW pivot block of the DIAG task (ld = m = kBW), whose
 // trailing updates run on the matrix cores.
 template <bool DiagTile = false, typename C>
@@ -837,7 +842,7 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scrat
     }
     if (o + b < p) {
       if (DiagTile) trail_mfma(F, o, b, o + b, p, dd, scratch);
-      else trail16(F, ld, o, b, o + b, p, m, dd, scratch);
+      else trail16(F, ld, o, b, o + b, p, m, dd);
       __syncthreads();
     }
   }
@@ -952,7 +957,9 @@ __device__ __forceinline__ void invert_blocked(C* F, int ld, int nb, C* T) {
 // The stencils of the pivot columns are staged in the d / 1/d / scratch area,
 // which is free until the factorisation starts.
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int small_scratch_entries(int p) { return p - 16 > 16 ? 16 * (p - 16) : 256; }
+// (the 2 x 64 pivot-column buffer of the LDL^T, and the stencils staged before
+// it: 5p values and 4p indices from d on)
+__host__ __device__ constexpr int small_scratch_entries(int p) { return 5 * p > 128 ? 5 * p : 128; }
 
 // The children of a front (at most two: the separator tree is binary), read
 // once per front: the compiler cannot keep these table reads out of a loop
@@ -1364,10 +1371,11 @@ __global__ __launch_bounds__(kThreads, PMAX <= 24 ? 3 : 2) void k_wave_fronts(KA
 
 // Persistent launch over fronts order[0 .. ntasks/nsys): with q.wait set, a
 // front first waits for its children (claimed earlier in the same launch).
-// Two waves per SIMD: with up to three fronts' panels per CU in LDS, register
-// use (not LDS) would otherwise hold the kernel to one workgroup per CU.
+// Registers for two workgroups per CU in complex128, three in complex64
+// (complex128 at three spills heavily and runs slower).
 template <typename R>
-__global__ __launch_bounds__(kThreads, 2) void k_front_small(KArgs a, Queue q, const int32_t* order) {
+__global__ __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 3) void k_front_small(KArgs a, Queue q,
+                                                                                 const int32_t* order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sh;
   const int ep = launch_epoch(q);
