@@ -211,11 +211,11 @@ fdfd_status fdfd_solve(fdfd_plan plan, const void* b_dev, void* x_dev, int32_t n
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): fdfd_solve with the same arguments, results and errors, whose
  * work vectors (elimination-order and update vectors, split-front hand-over
- * buffers, FP64 residual and partial norms, residual counter) live in one
+ * buffers, FP64 residual and partial norms) live in one
  * file-scope device array of FDFD_NOALLOC_SCRATCH_BYTES (64 MiB) instead of
  * the plan's arenas.  It calls no hipMalloc, hipFree or other allocating
- * routine (the plan, made earlier by fdfd_analyze, is an input); it starts
- * with a fill kernel that clears the residual counter.  Every call on a GPU
+ * routine (the plan, made earlier by fdfd_analyze, is an input); nothing in
+ * the array has to start at zero (each launch writes what it reads).  Every call on a GPU
  * shares that GPU's array, which keeps the last call's contents: calls that
  * overlap on one GPU (other streams, other plans, other threads) race, and the
  * caller must serialise them.  Returns FDFD_ERR_ARG, enqueuing nothing, when

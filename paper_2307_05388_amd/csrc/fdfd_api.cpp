@@ -125,7 +125,6 @@ size_t carve_solve_work(const Plan& P, int nrhs, unsigned char* base, fdfd::Solv
   unsigned char* pv = take(cols * parts * cs);
   unsigned char* res = take(cols * N * 16);
   unsigned char* partial = take(cols * (size_t)P.res_blocks * 16);
-  unsigned char* counter = take(sizeof(int32_t));
   if (w) {
     w->y = y;
     w->wv = wv;
@@ -133,8 +132,6 @@ size_t carve_solve_work(const Plan& P, int nrhs, unsigned char* base, fdfd::Solv
     w->pv = pv;
     w->res = reinterpret_cast<double2*>(res);
     w->partial = reinterpret_cast<double*>(partial);
-    w->res_counter = reinterpret_cast<int32_t*>(counter);
-    w->clear_counter = true;
   }
   return off;
 }
@@ -691,7 +688,9 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   // memory plan
   const int64_t N = P.an.N, nsys = desc->nsys, R = desc->max_rhs;
   const int64_t sum_u = P.an.upd_ptr.back();
-  P.res_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
+  // one cell per residual thread up to 2^22 cells (one workgroup then sums
+  // the per-workgroup partials)
+  P.res_blocks = (int32_t)std::min<int64_t>(16384, std::max<int64_t>(1, (N + 255) / 256));
   const int64_t need = nsys * P.an.fac_total * (int64_t)cs + nsys * P.an.upd_total * (int64_t)cs +
                        nsys * (int64_t)P.ntiles * 4 + nsys * ((int64_t)P.an.nfronts + P.nchunk + P.nblk) * 4 +
                        nsys * (2 * desc->nx + 2 * desc->ny + 2) * 16 + nsys * 8 + nsys * N * 8 +

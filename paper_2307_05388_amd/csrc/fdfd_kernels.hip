@@ -3348,16 +3348,17 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepA
 }
 
 // ---------------------------------------------------------------------------
-// FP64 refinement: r = rhs_sym - (SA) x with per-block partial norms; the last
-// workgroup to finish reduces them in a fixed order, records the relative
-// residual and raises the converged flag (or the failure bits).
+// FP64 refinement: r = rhs_sym - (SA) x with per-workgroup partial norms
+// (k_residual, one cell per thread), then one workgroup sums them in a fixed
+// order, records the relative residual and raises the converged flag or the
+// failure bits (k_residual_norm).  Two launches and no completion counter:
+// a counter that every workgroup increments serialises thousands of atomics.
 // ---------------------------------------------------------------------------
 struct ResArgs {
   const double2* rhs;
   const double2* x;
   double2* res;
   double* partial;
-  int32_t* counter;
   const int* flag;
   double tol;
   int32_t nrhs, scale_rhs, step, last;
@@ -3389,7 +3390,6 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs a, ResArgs ra) {
     bb += b.x * b.x + b.y * b.y;
   }
   __shared__ double red[2][kThreads];
-  __shared__ int last_block;
   red[0][threadIdx.x] = rr;
   red[1][threadIdx.x] = bb;
   __syncthreads();
@@ -3400,39 +3400,42 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs a, ResArgs ra) {
     }
     __syncthreads();
   }
-  const int nblk = gridDim.x, ncols = gridDim.y;
   if (threadIdx.x == 0) {
-    double* pp = ra.partial + ((int64_t)col * nblk + blockIdx.x) * 2;
+    double* pp = ra.partial + ((int64_t)col * gridDim.x + blockIdx.x) * 2;
     pp[0] = red[0][0];
     pp[1] = red[1][0];
-    __threadfence();
-    last_block = atomicAdd(ra.counter, 1) == nblk * ncols - 1;
   }
-  __syncthreads();
-  if (!last_block) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  double wmax = 0.0;
-  int nf = 0;
-  for (int c = threadIdx.x; c < ncols; c += kThreads) {
+}
+
+// One workgroup: per column, thread t sums the partials of workgroups t,
+// t + kThreads, ..., then a fixed tree (the result is reproducible).
+__global__ __launch_bounds__(kThreads) void k_residual_norm(KArgs a, ResArgs ra, int nblk, int ncols) {
+  if (done(ra.flag)) return;
+  __shared__ double red[2][kThreads];
+  double mx = 0.0;
+  int anybad = 0;
+  for (int c = 0; c < ncols; ++c) {
     double r2 = 0.0, b2 = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
       r2 += ra.partial[((int64_t)c * nblk + b) * 2];
       b2 += ra.partial[((int64_t)c * nblk + b) * 2 + 1];
     }
-    const double rel = b2 > 0 ? sqrt(r2 / b2) : sqrt(r2);
-    if (!(rel <= DBL_MAX)) nf = 1;
-    wmax = fmax(wmax, rel);
-  }
-  red[0][threadIdx.x] = wmax;
-  red[1][threadIdx.x] = nf;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double mx = 0.0;
-    int anybad = 0;
-    for (int t = 0; t < kThreads; ++t) {
-      mx = fmax(mx, red[0][t]);
-      anybad |= red[1][t] != 0.0;
+    __syncthreads();
+    red[0][threadIdx.x] = r2;
+    red[1][threadIdx.x] = b2;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      }
+      __syncthreads();
     }
+    const double rel = red[1][0] > 0 ? sqrt(red[0][0] / red[1][0]) : sqrt(red[0][0]);
+    if (!(rel <= DBL_MAX)) anybad = 1;
+    mx = fmax(mx, rel);
+  }
+  if (threadIdx.x == 0) {
     DevStatus* st = a.st;
     st->ir_rel = anybad ? NAN : mx;
     st->ir_steps = ra.step;
@@ -3445,7 +3448,6 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs a, ResArgs ra) {
     } else if (ra.last) {
       st->ir_failed = 1;
     }
-    *ra.counter = 0;
   }
 }
 
@@ -3854,10 +3856,6 @@ void sweep_cols(Plan& P, const SolveWork& wk, const KArgs& a, const double2* src
   }
 }
 
-__global__ void k_clear_i32(int32_t* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
-}
-
 template <typename R>
 hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int nrhs, int max_ir,
                       double tol, hipStream_t st, const SolveWork* work) {
@@ -3872,10 +3870,7 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
     wk.pv = P.pv;
     wk.res = P.res;
     wk.partial = P.partial;
-    wk.res_counter = P.counters + 2;
   }
-  // a fill kernel rather than a memset, so a caller may capture the call
-  if (wk.clear_counter) hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, st, wk.res_counter, 1);
   const int ncols = P.desc.nsys * nrhs;
   double2* xdst = mode == 0 ? x_out : P.xw;
   const int scale = mode == 0 ? 1 : 0;
@@ -3892,7 +3887,6 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
   ra.x = xdst;
   ra.res = wk.res;
   ra.partial = wk.partial;
-  ra.counter = wk.res_counter;
   ra.flag = flag;
   ra.tol = tol;
   ra.nrhs = nrhs;
@@ -3905,6 +3899,7 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
     {
       Prof pr(P, st, KC_RESIDUAL, rbytes, 0.0);
       hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
+      hipLaunchKernelGGL(k_residual_norm, dim3(1), dim3(kThreads), 0, st, a, ra, P.res_blocks, ncols);
     }
     sweep<R>(P, wk, a, wk.res, xdst, nrhs, 0, 1, flag, st);
   }
@@ -3913,6 +3908,7 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
     ra.last = 1;
     Prof pr(P, st, KC_RESIDUAL, rbytes, 0.0);
     hipLaunchKernelGGL(k_residual, dim3(P.res_blocks, ncols), dim3(kThreads), 0, st, a, ra);
+    hipLaunchKernelGGL(k_residual_norm, dim3(1), dim3(kThreads), 0, st, a, ra, P.res_blocks, ncols);
   }
   hipLaunchKernelGGL(k_ir_end, dim3(1), dim3(1), 0, st, P.status, mode, 1);
   return hipGetLastError();

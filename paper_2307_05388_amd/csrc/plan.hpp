@@ -201,8 +201,6 @@ struct SolveWork {
   void* pv = nullptr;
   double2* res = nullptr;
   double* partial = nullptr;
-  int32_t* res_counter = nullptr;
-  bool clear_counter = false;  // zero res_counter (fill kernel) before the solve
 };
 
 // Kernel launchers (fdfd_kernels.hip).  Each returns hipSuccess or the first
