@@ -167,7 +167,8 @@ typedef struct {
  *                   all blocks);
  *   FDFD_WAVE_FRONTS at most this many bottom levels factored one wavefront
  *                   per front (each level's fronts must have at most 64 rows
- *                   and 40 pivots; 0 = none, default all that qualify);
+ *                   and 40 pivots, or 128 rows and 16 pivots; 0 = none,
+ *                   default all that qualify);
  *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
  *                   passes also never take more than fit the LDS);
  *   FDFD_SWEEP_GROUP height of the bottom-level subtrees one wavefront

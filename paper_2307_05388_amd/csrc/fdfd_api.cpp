@@ -234,10 +234,12 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
   }
   P.small_prefix = 0;
   while (P.small_prefix < (int)P.levels.size() && P.levels[P.small_prefix].small) ++P.small_prefix;
-  // the bottom levels whose fronts all have at most 64 rows and 40 pivots
-  // are factored one wavefront per front, a launch per level, when four such
-  // fronts fit the LDS (FDFD_WAVE_FRONTS caps the number of such levels; 0
-  // keeps every level in the one-workgroup kernel)
+  // the bottom levels whose fronts all have at most 64 rows and 40 pivots,
+  // or at most 128 rows (two per lane) and 16 pivots, are factored one
+  // wavefront per front, a launch per level, when the level's slices fit the
+  // LDS (four per workgroup with one row per lane, one with two);
+  // FDFD_WAVE_FRONTS caps the number of such levels (0 keeps every level in
+  // the one-workgroup kernel)
   P.wave_front_levels.clear();
   {
     const int cap = env_int("FDFD_WAVE_FRONTS", 1 << 20);
@@ -250,13 +252,15 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
         pmax = std::max(pmax, A.npiv[f]);
         umax = std::max(umax, A.nupd[f]);
       }
+      const int nr = mmax > 64 ? 2 : 1;
       // per wave: four couplings per row (value and pivot column), later the
       // update rows of L (u x p) in the same bytes; p pivots, a 64-entry
-      // column buffer, two rows of 64 gather indices
+      // column buffer, two rows of 64 nr gather indices
       const size_t ub = (std::max((size_t)umax * pmax * cs, 4 * (size_t)mmax * (cs + sizeof(int32_t))) + 15) / 16 * 16;
-      const size_t ldsw = (ub + ((size_t)pmax + 64) * cs + 128 * sizeof(int32_t) + 15) / 16 * 16;
-      if (mmax > 64 || pmax > 40 || 4 * ldsw > lds_dyn) break;
-      P.wave_front_levels.push_back({(int)ldsw, pmax});
+      const size_t ldsw = (ub + ((size_t)pmax + 64) * cs + 128 * (size_t)nr * sizeof(int32_t) + 15) / 16 * 16;
+      const int wpg = nr == 2 ? 1 : 4;
+      if (mmax > 128 || pmax > (nr == 2 ? 16 : 40) || (size_t)wpg * ldsw > lds_dyn) break;
+      P.wave_front_levels.push_back({(int)ldsw, pmax, nr});
     }
   }
   tasks.clear();

@@ -1146,23 +1146,33 @@ template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
 // Pivot step K of the leaf LDL^T and every step after it, unrolled through
 // template recursion so that the row stays in registers (a loop the compiler
 // declines to unroll fully would index x dynamically, i.e. through scratch).
-template <int K, int PMAX, typename C>
+template <int K, int PMAX, int NR, typename C>
 struct LeafSteps {
-  __device__ __forceinline__ static void run(C (&x)[PMAX], C* col, C* dd, int p, int lane, double thr,
+  __device__ __forceinline__ static void run(C (&x)[NR][PMAX], C* col, C* dd, int p, int lane, double thr,
                                              double anorm, int& npert, double& minr, int& nonfin) {
     if constexpr (K < PMAX) {
       if (K >= p) return;
-      col[lane] = x[K];
+      // the pivot rows are all among the first 64 (p <= 64): they publish
+      // the column; a lane's second row (lane + 64 > K) only takes updates
+      col[lane] = x[0][K];
       wave_sync();
       const C d = fix_pivot(col[K], thr, anorm, npert, minr, nonfin);
-      const C l = csel(lane > K, cmul(x[K], cinv(d)), czero<C>());
+      const C di = cinv(d);
+      const C l0 = csel(lane > K, cmul(x[0][K], di), czero<C>());
+      C l1 = czero<C>();
+      if constexpr (NR == 2) l1 = cmul(x[1][K], di);
 #pragma unroll
       for (int j = K + 1; j < PMAX; ++j)
-        if (j < p) x[j] = csel(lane >= j, csub(x[j], cmul(l, col[j])), x[j]);
-      x[K] = csel(lane > K, l, csel(lane == K, d, x[K]));
+        if (j < p) {
+          const C cj = col[j];
+          x[0][j] = csel(lane >= j, csub(x[0][j], cmul(l0, cj)), x[0][j]);
+          if constexpr (NR == 2) x[1][j] = csub(x[1][j], cmul(l1, cj));
+        }
+      x[0][K] = csel(lane > K, l0, csel(lane == K, d, x[0][K]));
+      if constexpr (NR == 2) x[1][K] = l1;
       if (lane == 0) dd[K] = d;
       wave_sync();
-      LeafSteps<K + 1, PMAX, C>::run(x, col, dd, p, lane, thr, anorm, npert, minr, nonfin);
+      LeafSteps<K + 1, PMAX, NR, C>::run(x, col, dd, p, lane, thr, anorm, npert, minr, nonfin);
     }
   }
 };
@@ -1189,16 +1199,17 @@ struct LeafSteps {
 // order), where the one-workgroup kernel spends a workgroup and a barrier per
 // pivot step on each front.  Pivots are checked and perturbed as in every
 // other factor path.
-template <typename R, int PMAX>
+template <typename R, int PMAX, int NR>
 __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int ldsw, unsigned char* smem_raw,
                                            PivotStats& ps) {
   typedef typename Cx<R>::T C;
+  constexpr int GW = 64 * NR;  // gather-row width: rows lane (and lane + 64)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = a.npiv[f], u = a.nupd[f], m = p + u, pb = a.pbeg[f];
   // the wave's slice: the rows' couplings (4m values, then 4m pivot
   // columns) until the rows are loaded, after the elimination the update
   // rows of L (u x p) in the same bytes; then p pivots, a 64-entry column
-  // buffer and two rows of 64 gather indices
+  // buffer and two rows of GW gather indices
   unsigned char* base = smem_raw + (size_t)wave * ldsw;
   const int ub = (max(u * p * (int)sizeof(C), 4 * m * ((int)sizeof(C) + 4)) + 15) & ~15;
   C* Fu = reinterpret_cast<C*>(base);
@@ -1210,16 +1221,21 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
   const int cb = a.child_ptr[f], nch = a.child_ptr[f + 1] - cb;
   const int32_t* g = a.gmap + a.gmap_ptr[f];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) gl[64 * k + lane] = k < nch && lane < m ? g[k * m + lane] : -1;
-  if (lane < m) {
+  for (int h = 0; h < NR; ++h) {
+    const int r = lane + 64 * h;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) sc[4 * lane + d] = -1;
+    for (int k = 0; k < 2; ++k) gl[GW * k + r] = k < nch && r < m ? g[k * m + r] : -1;
+    if (r < m) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) sc[4 * r + d] = -1;
+    }
   }
   wave_sync();
-  const bool row = lane < m;
-  C x[PMAX];
+  C x[NR][PMAX];
 #pragma unroll
-  for (int c = 0; c < PMAX; ++c) x[c] = czero<C>();
+  for (int h = 0; h < NR; ++h)
+#pragma unroll
+    for (int c = 0; c < PMAX; ++c) x[h][c] = czero<C>();
   if (lane < p) {
     // pivot lane c: its diagonal, and its couplings to the later rows r > c
     // go to row r's slots, one per direction (a row has one neighbour per
@@ -1228,7 +1244,7 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
     const Stencil S = stencil_at(a, s, a.perm[q]);
     const C dg = from_d2<C>(S.diag);
 #pragma unroll
-    for (int c = 0; c < PMAX; ++c) x[c] = csel(c == lane, dg, x[c]);
+    for (int c = 0; c < PMAX; ++c) x[0][c] = csel(c == lane, dg, x[0][c]);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
       const int r = a.nbr_row[4 * (int64_t)q + d];
@@ -1239,14 +1255,18 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
     }
   }
   wave_sync();
-  if (row) {
-    // row lane's entries in the pivot columns before it
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int c = sc[4 * lane + d];
-      const C v = sv[4 * lane + d];
+  for (int h = 0; h < NR; ++h) {
+    const int r = lane + 64 * h;
+    if (r < m) {
+      // row r's entries in the pivot columns before it
 #pragma unroll
-      for (int k = 0; k < PMAX; ++k) x[k] = csel(k == c, v, x[k]);
+      for (int d = 0; d < 4; ++d) {
+        const int c = sc[4 * r + d];
+        const C v = sv[4 * r + d];
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k) x[h][k] = csel(k == c, v, x[h][k]);
+      }
     }
   }
   // the children's entries of row lane in the pivot columns (both children's loads in flight together)
@@ -1257,23 +1277,31 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
       const int chf = a.child_list[cb + k];
       const int uk = a.nupd[chf];
       const C* Uk = Ub + a.upd_off[chf];
-      const int gi = gl[64 * k + lane];
-      // eight columns' loads in flight at a time (all PMAX at once would hold
-      // the kernel to fewer waves per SIMD)
+      int gi[NR];
+#pragma unroll
+      for (int h = 0; h < NR; ++h) gi[h] = gl[GW * k + lane + 64 * h];
+      // eight columns' loads per row in flight at a time (all PMAX at once
+      // would hold the kernel to fewer waves per SIMD)
 #pragma unroll
       for (int c0 = 0; c0 < PMAX; c0 += 8) {
         if (c0 < p) {
-          C w[8];
+          C w[NR][8];
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
             const int c = c0 + t;
-            const int gc = gl[64 * k + min(c, 63)];
-            const bool ok = c < p && gi >= 0 && gc >= 0 && lane >= c && row;
-            w[t] = ok ? Uk[(int64_t)gc * uk + gi] : czero<C>();
+            const int gc = gl[GW * k + min(c, 63)];
+#pragma unroll
+            for (int h = 0; h < NR; ++h) {
+              const int r = lane + 64 * h;
+              const bool ok = c < p && gi[h] >= 0 && gc >= 0 && r >= c && r < m;
+              w[h][t] = ok ? Uk[(int64_t)gc * uk + gi[h]] : czero<C>();
+            }
           }
 #pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (c0 + t < PMAX) x[c0 + t] = cadd(x[c0 + t], w[t]);
+          for (int h = 0; h < NR; ++h)
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+              if (c0 + t < PMAX) x[h][c0 + t] = cadd(x[h][c0 + t], w[h][t]);
         }
       }
     }
@@ -1282,18 +1310,26 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
   const double thr = a.tau * anorm;
   int npert = 0, nonfin = 0;
   double minr = INFINITY;
-  LeafSteps<0, PMAX, C>::run(x, col, dd, p, lane, thr, anorm, npert, minr, nonfin);
+  LeafSteps<0, PMAX, NR, C>::run(x, col, dd, p, lane, thr, anorm, npert, minr, nonfin);
   // the panel to the factor arena (row lane: D on the diagonal, L below)
   C* L = (C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
 #pragma unroll
-  for (int c = 0; c < PMAX; ++c)
-    if (c < p && row && lane >= c) L[(int64_t)c * m + lane] = x[c];
-  if (u > 0) {
-    // the update rows of L back into the panel in LDS: the products read
-    // them (and d) as broadcasts
+  for (int h = 0; h < NR; ++h) {
+    const int r = lane + 64 * h;
 #pragma unroll
     for (int c = 0; c < PMAX; ++c)
-      if (c < p && lane >= p && row) Fu[c * u + lane - p] = x[c];
+      if (c < p && r < m && r >= c) L[(int64_t)c * m + r] = x[h][c];
+  }
+  if (u > 0) {
+    // the update rows of L back into LDS: the products read them (and d)
+    // as broadcasts
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      const int r = lane + 64 * h;
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c)
+        if (c < p && r >= p && r < m) Fu[c * u + r - p] = x[h][c];
+    }
     wave_sync();
     C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
     const int ntri = u * (u + 1) / 2;
@@ -1325,8 +1361,8 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (k < nch) {
-          const int gr = ok ? gl[64 * k + p + rr] : -1;
-          const int gc = ok ? gl[64 * k + p + cc] : -1;
+          const int gr = ok ? gl[GW * k + p + rr] : -1;
+          const int gc = ok ? gl[GW * k + p + cc] : -1;
           if (gr >= 0 && gc >= 0) v = cadd(v, Uk[k][(int64_t)gc * uk[k] + gr]);
         }
       }
@@ -1356,16 +1392,18 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
 }
 
 // Waves per SIMD the register budget must allow: three for up to 24 pivots
-// (the bottom level's fronts), two above.
-template <typename R, int PMAX>
-__global__ __launch_bounds__(kThreads, PMAX <= 24 ? 3 : 2) void k_wave_fronts(KArgs a, const int32_t* order, int nitems,
-                                                                             int ldsw) {
+// and one row per lane (the bottom level's fronts), two otherwise.  A
+// workgroup holds one to four waves (blockDim), each with its own front.
+template <typename R, int PMAX, int NR>
+__global__ __launch_bounds__(kThreads, PMAX <= 24 && NR == 1 ? 3 : 2) void k_wave_fronts(KArgs a,
+                                                                                        const int32_t* order,
+                                                                                        int nitems, int ldsw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int item = blockIdx.x * (kThreads / 64) + wave;
+  const int item = blockIdx.x * (int)(blockDim.x >> 6) + wave;
   if (item >= nitems) return;  // the whole wave: nothing below synchronises the workgroup
   extern __shared__ __align__(16) unsigned char smem_raw[];
   PivotStats ps;
-  wave_front<R, PMAX>(a, order[item / a.nsys], item % a.nsys, ldsw, smem_raw, ps);
+  wave_front<R, PMAX, NR>(a, order[item / a.nsys], item % a.nsys, ldsw, smem_raw, ps);
   if (lane == 0) ps.flush(a.st);
 }
 
@@ -3679,18 +3717,28 @@ hipError_t refactor_impl(Plan& P, const double* eps, int64_t eps_stride, hipStre
       double fl = 0.0;
       for (int k = LP.first; k < LP.first + LP.count; ++k) fl += P.front_flops[P.an.level_fronts[k]];
       Prof pr(P, st, KC_FRONT_SMALL, 0.0, fl * nsys);
-      const int nitems = LP.count * nsys, wpg = kThreads / 64;
-      const int ldsw = P.wave_front_levels[l].ldsw;
-      const dim3 grid((nitems + wpg - 1) / wpg);
-      const size_t lds = (size_t)wpg * ldsw;
-      if (P.wave_front_levels[l].pmax <= 8)
-        hipLaunchKernelGGL((k_wave_fronts<R, 8>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
-      else if (P.wave_front_levels[l].pmax <= 16)
-        hipLaunchKernelGGL((k_wave_fronts<R, 16>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
-      else if (P.wave_front_levels[l].pmax <= 24)
-        hipLaunchKernelGGL((k_wave_fronts<R, 24>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
-      else
-        hipLaunchKernelGGL((k_wave_fronts<R, 40>), grid, dim3(kThreads), lds, st, a, lf + LP.first, nitems, ldsw);
+      const auto& WL = P.wave_front_levels[l];
+      // fronts of up to 64 rows: four waves per workgroup; two rows per lane:
+      // one wave per workgroup (its slice is larger; the LDS packs the CU)
+      const int nitems = LP.count * nsys, wpg = WL.nr == 2 ? 1 : kThreads / 64;
+      const dim3 grid((nitems + wpg - 1) / wpg), block(64 * wpg);
+      const size_t lds = (size_t)wpg * WL.ldsw;
+      const int32_t* ord = lf + LP.first;
+      if (WL.nr == 1) {
+        if (WL.pmax <= 8)
+          hipLaunchKernelGGL((k_wave_fronts<R, 8, 1>), grid, block, lds, st, a, ord, nitems, WL.ldsw);
+        else if (WL.pmax <= 16)
+          hipLaunchKernelGGL((k_wave_fronts<R, 16, 1>), grid, block, lds, st, a, ord, nitems, WL.ldsw);
+        else if (WL.pmax <= 24)
+          hipLaunchKernelGGL((k_wave_fronts<R, 24, 1>), grid, block, lds, st, a, ord, nitems, WL.ldsw);
+        else
+          hipLaunchKernelGGL((k_wave_fronts<R, 40, 1>), grid, block, lds, st, a, ord, nitems, WL.ldsw);
+      } else {
+        if (WL.pmax <= 8)
+          hipLaunchKernelGGL((k_wave_fronts<R, 8, 2>), grid, block, lds, st, a, ord, nitems, WL.ldsw);
+        else
+          hipLaunchKernelGGL((k_wave_fronts<R, 16, 2>), grid, block, lds, st, a, ord, nitems, WL.ldsw);
+      }
     }
     // the other small levels: one launch per level, each with the LDS its
     // own largest front needs (the lower levels' small fronts then share a CU
@@ -3917,9 +3965,10 @@ hipError_t solve_impl(Plan& P, int mode, const double2* rhs, double2* x_out, int
 template <typename R>
 hipError_t set_lds_limits(int limit) {
   hipError_t e = hipSuccess;
-  const void* fns[] = {(const void*)k_front_small<R>, (const void*)k_wave_fronts<R, 8>,
-                       (const void*)k_wave_fronts<R, 16>, (const void*)k_wave_fronts<R, 24>,
-                       (const void*)k_wave_fronts<R, 40>, (const void*)k_large_tiles<R>,
+  const void* fns[] = {(const void*)k_front_small<R>,     (const void*)k_wave_fronts<R, 8, 1>,
+                       (const void*)k_wave_fronts<R, 16, 1>, (const void*)k_wave_fronts<R, 24, 1>,
+                       (const void*)k_wave_fronts<R, 40, 1>, (const void*)k_wave_fronts<R, 8, 2>,
+                       (const void*)k_wave_fronts<R, 16, 2>, (const void*)k_large_tiles<R>,
                        (const void*)k_fwd_sweep<R>,   (const void*)k_bwd_sweep<R>,
                        (const void*)k_fwd_sweep_waves<R>, (const void*)k_bwd_sweep_waves<R>};
   for (const void* fn : fns) {

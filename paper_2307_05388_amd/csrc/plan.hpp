@@ -90,7 +90,7 @@ struct Plan {
   // bottom levels factored one wavefront per front (k_wave_fronts), one
   // launch each: LDS bytes per wave and the largest pivot count of the level
   struct WaveLevel {
-    int ldsw, pmax;
+    int ldsw, pmax, nr;  // LDS per wave, pivot bound, rows per lane (1 or 2)
   };
   std::vector<WaveLevel> wave_front_levels;
   int32_t small_prefix = 0;    // leading levels run by the small-front launches (one per level)
