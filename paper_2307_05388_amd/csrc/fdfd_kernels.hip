@@ -1355,37 +1355,53 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
       }
       rr = cc + (e - off);
     };
-    // the children's entries of F22 at (p + rr, p + cc)
-    auto kids_at = [&](int cc, int rr, bool ok) {
-      C v = czero<C>();
+    // the children's entries of F22 at (p + rr, p + cc): the loads are
+    // unconditional (entry 0 where the row or column is not the child's; a
+    // missing child's gather rows are -1 and its pointer is this front's own
+    // block) and their values are selected and added only in the next round,
+    // so the loads stay in flight across this round's products
+    auto kids_load = [&](int cc, int rr, bool ok, C (&val)[2], bool (&hit)[2]) {
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        if (k < nch) {
-          const int gr = ok ? gl[GW * k + p + rr] : -1;
-          const int gc = ok ? gl[GW * k + p + cc] : -1;
-          if (gr >= 0 && gc >= 0) v = cadd(v, Uk[k][(int64_t)gc * uk[k] + gr]);
-        }
+        const int gr = ok ? gl[GW * k + p + rr] : -1;
+        const int gc = ok ? gl[GW * k + p + cc] : -1;
+        hit[k] = gr >= 0 && gc >= 0;
+        val[k] = Uk[k][hit[k] ? (int64_t)gc * uk[k] + gr : 0];
       }
+    };
+    auto kids_sum = [&](const C (&val)[2], const bool (&hit)[2]) {
+      C v = czero<C>();
+#pragma unroll
+      for (int k = 0; k < 2; ++k) v = cadd(v, csel(hit[k], val[k], czero<C>()));
       return v;
     };
-    // software pipelined: the children's entries of the next 64 entries are
-    // in flight while this round's products are formed
     int cc, rr;
     entry(lane, cc, rr);
-    C v = kids_at(cc, rr, lane < ntri);
+    C kv[2];
+    bool kh[2];
+    kids_load(cc, rr, lane < ntri, kv, kh);
     for (int e0 = 0; e0 < ntri; e0 += 64) {
       const bool ok = e0 + lane < ntri;
       int cn, rn;
       entry(e0 + 64 + lane, cn, rn);
-      const C vn = kids_at(cn, rn, e0 + 64 + lane < ntri);
+      C kvn[2];
+      bool khn[2];
+      kids_load(cn, rn, e0 + 64 + lane < ntri, kvn, khn);
+      const C v = kids_sum(kv, kh);
+      // indices in range for every lane, so the sum needs no per-lane branch
+      // (a branch per term would keep its LDS reads from overlapping)
+      const int ra = ok ? rr : 0, ca = ok ? cc : 0;
       C acc = czero<C>();
-#pragma unroll
-      for (int k = 0; k < PMAX; ++k)
-        if (k < p && ok) acc = cadd(acc, cmul(Fu[k * u + rr], cmul(Fu[k * u + cc], dd[k])));
+#pragma unroll 4
+      for (int k = 0; k < p; ++k) acc = cadd(acc, cmul(Fu[k * u + ra], cmul(Fu[k * u + ca], dd[k])));
       if (ok) U[(int64_t)cc * u + rr] = csub(v, acc);
       cc = cn;
       rr = rn;
-      v = vn;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        kv[k] = kvn[k];
+        kh[k] = khn[k];
+      }
     }
   }
   ps.add(npert, minr, nonfin, anorm);
