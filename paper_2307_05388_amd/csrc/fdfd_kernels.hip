@@ -1358,8 +1358,8 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
     // the children's entries of F22 at (p + rr, p + cc): the loads are
     // unconditional (entry 0 where the row or column is not the child's; a
     // missing child's gather rows are -1 and its pointer is this front's own
-    // block) and their values are selected and added only in the next round,
-    // so the loads stay in flight across this round's products
+    // block) and their values are selected and added only when used, so the
+    // loads stay in flight across the products formed before
     auto kids_load = [&](int cc, int rr, bool ok, C (&val)[2], bool (&hit)[2]) {
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -1375,32 +1375,48 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
       for (int k = 0; k < 2; ++k) v = cadd(v, csel(hit[k], val[k], czero<C>()));
       return v;
     };
-    int cc, rr;
-    entry(lane, cc, rr);
-    C kv[2];
-    bool kh[2];
-    kids_load(cc, rr, lane < ntri, kv, kh);
-    for (int e0 = 0; e0 < ntri; e0 += 64) {
-      const bool ok = e0 + lane < ntri;
-      int cn, rn;
-      entry(e0 + 64 + lane, cn, rn);
-      C kvn[2];
-      bool khn[2];
-      kids_load(cn, rn, e0 + 64 + lane < ntri, kvn, khn);
-      const C v = kids_sum(kv, kh);
-      // indices in range for every lane, so the sum needs no per-lane branch
-      // (a branch per term would keep its LDS reads from overlapping)
-      const int ra = ok ? rr : 0, ca = ok ? cc : 0;
-      C acc = czero<C>();
-#pragma unroll 4
-      for (int k = 0; k < p; ++k) acc = cadd(acc, cmul(Fu[k * u + ra], cmul(Fu[k * u + ca], dd[k])));
-      if (ok) U[(int64_t)cc * u + rr] = csub(v, acc);
-      cc = cn;
-      rr = rn;
+    // QD rounds of 64 entries per batch; the next batch's loads are in flight
+    // while this batch's products are formed
+    constexpr int QD = NR == 2 ? 3 : PMAX <= 8 ? 1 : 2;
+    int cq[QD], rq[QD];
+    C kv[QD][2];
+    bool kh[QD][2];
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        kv[k] = kvn[k];
-        kh[k] = khn[k];
+    for (int q = 0; q < QD; ++q) {
+      entry(64 * q + lane, cq[q], rq[q]);
+      kids_load(cq[q], rq[q], 64 * q + lane < ntri, kv[q], kh[q]);
+    }
+    for (int e0 = 0; e0 < ntri; e0 += 64 * QD) {
+      int cn[QD], rn[QD];
+      C kvn[QD][2];
+      bool khn[QD][2];
+#pragma unroll
+      for (int q = 0; q < QD; ++q) {
+        const int e = e0 + 64 * (QD + q) + lane;
+        entry(e, cn[q], rn[q]);
+        kids_load(cn[q], rn[q], e < ntri, kvn[q], khn[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < QD; ++q) {
+        const bool ok = e0 + 64 * q + lane < ntri;
+        const C v = kids_sum(kv[q], kh[q]);
+        // indices in range for every lane, so the sum needs no per-lane
+        // branch (a branch per term would keep its LDS reads from overlapping)
+        const int ra = ok ? rq[q] : 0, ca = ok ? cq[q] : 0;
+        C acc = czero<C>();
+#pragma unroll 4
+        for (int k = 0; k < p; ++k) acc = cadd(acc, cmul(Fu[k * u + ra], cmul(Fu[k * u + ca], dd[k])));
+        if (ok) U[(int64_t)cq[q] * u + rq[q]] = csub(v, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < QD; ++q) {
+        cq[q] = cn[q];
+        rq[q] = rn[q];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          kv[q][k] = kvn[q][k];
+          kh[q][k] = khn[q][k];
+        }
       }
     }
   }
