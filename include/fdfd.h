@@ -169,11 +169,14 @@ typedef struct {
  *                   per front (each level's fronts must have at most 64 rows
  *                   and 40 pivots, or 128 rows and 16 pivots; 0 = none,
  *                   default all that qualify);
+ *   FDFD_WAVE_MIN_FRONTS fronts x systems a level of up to 128 rows needs
+ *                   for that (default 16 per CU);
  *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
  *                   passes also never take more than fit the LDS);
  *   FDFD_SWEEP_GROUP height of the bottom-level subtrees one wavefront
- *                   sweeps whole, children before parents (default 3;
- *                   0 = one front at a time);
+ *                   sweeps whole, children before parents (default: the
+ *                   highest level up to 3 with 16 fronts per CU; 0 = one
+ *                   front at a time);
  *   FDFD_PIVOT_TAU  static pivot threshold relative to the matrix norm;
  *   FDFD_TRACE      file for per-task timestamps (written by fdfd_query).
  * max_rhs is not limited by the front sizes: the sweeps hold a front's

@@ -243,6 +243,8 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
   P.wave_front_levels.clear();
   {
     const int cap = env_int("FDFD_WAVE_FRONTS", 1 << 20);
+    // fronts x systems a two-row level needs (FDFD_WAVE_MIN_FRONTS)
+    const int64_t two_row_min = env_int("FDFD_WAVE_MIN_FRONTS", 16 * P.n_cu);
     const size_t lds_dyn = P.lds_limit > 512 ? P.lds_limit - 512 : 65536;
     for (int l = 0; l < P.small_prefix && (int)P.wave_front_levels.size() < cap; ++l) {
       int mmax = 0, pmax = 0, umax = 0;
@@ -260,6 +262,9 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       const size_t ldsw = (ub + ((size_t)pmax + 64) * cs + 128 * (size_t)nr * sizeof(int32_t) + 15) / 16 * 16;
       const int wpg = nr == 2 ? 1 : 4;
       if (mmax > 128 || pmax > (nr == 2 ? 16 : 40) || (size_t)wpg * ldsw > lds_dyn) break;
+      // a two-row level runs one wave per front: only with enough fronts to
+      // fill the chip (otherwise a workgroup per front goes faster)
+      if (nr == 2 && (int64_t)P.levels[l].count * P.desc.nsys < two_row_min) break;
       P.wave_front_levels.push_back({(int)ldsw, pmax, nr});
     }
   }
@@ -547,14 +552,18 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.wave_levels = P.small_prefix;
   P.wave_ld = 0;
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
-  // their sweep items: every front of height <= H (FDFD_SWEEP_GROUP, default
-  // 3) belongs to the subtree of its highest ancestor of height <= H, which
-  // one wavefront sweeps whole, children before parents (no wait between
-  // them); the fronts above H up to the wave levels' top are items of their
-  // own, level by level.  No subtree item depends on another.
+  // their sweep items: every front of height <= H belongs to the subtree of
+  // its highest ancestor of height <= H, which one wavefront sweeps whole,
+  // children before parents (no wait between them); the fronts above H up to
+  // the wave levels' top are items of their own, level by level.  No subtree
+  // item depends on another.  H (FDFD_SWEEP_GROUP overrides it) is the
+  // highest level up to 3 that still has 16 fronts per CU.
   {
     const int lw = P.wave_levels;
-    P.sweep_group = lw > 0 ? std::max(0, std::min(env_int("FDFD_SWEEP_GROUP", 3), lw - 1)) : 0;
+    int hdef = 0;
+    for (int l = 1; l <= 3 && l < lw; ++l)
+      if ((int64_t)P.levels[l].count * P.desc.nsys >= 16 * (int64_t)P.n_cu) hdef = l;
+    P.sweep_group = lw > 0 ? std::max(0, std::min(env_int("FDFD_SWEEP_GROUP", hdef), lw - 1)) : 0;
     const int H = P.sweep_group;
     const fdfd::Analysis& A = P.an;
     std::vector<int32_t>& seq = P.wave_seq_host;

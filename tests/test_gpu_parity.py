@@ -221,9 +221,12 @@ def test_schur_groups_forced(oracle, monkeypatch, group, prec):
 @pytest.mark.parametrize("leaf", [16, 36])
 def test_wave_fronts_all_paths(oracle, monkeypatch, prec, wave_levels, leaf):
     """The bottom levels factored one wavefront per front (k_wave_fronts: none,
-    the leaves only, two levels, every level that qualifies) and the rest in
-    the one-workgroup kernel: all against the oracle."""
+    the leaves only, two levels, every level that qualifies, two rows per
+    lane included) and the rest in the one-workgroup kernel: all against the
+    oracle."""
     monkeypatch.setenv("FDFD_WAVE_FRONTS", wave_levels)
+    # fronts of up to 128 rows qualify at this size too (two rows per lane)
+    monkeypatch.setenv("FDFD_WAVE_MIN_FRONTS", "0")
     p = P.custom_problem(90, 77, 10, wavelengths_um=(1.50, 1.60), src_profiles=("gauss", "alt_gauss"))
     say(f"case wave-front levels <= {wave_levels}, leaf={leaf} {prec}")
     eps = P.design_eps(p, t=6)
