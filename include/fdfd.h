@@ -169,8 +169,9 @@ typedef struct {
  *                   per front (each level's fronts must have at most 64 rows
  *                   and 40 pivots, or 128 rows and 16 pivots; 0 = none,
  *                   default all that qualify);
- *   FDFD_WAVE_MIN_FRONTS fronts x systems a level of up to 128 rows needs
- *                   for that (default 16 per CU);
+ *   FDFD_WAVE_MIN_FRONTS fronts a level of up to 128 rows needs for that
+ *                   (default 16 per CU; per system, so a batch of systems
+ *                   is factored exactly as each system alone);
  *   FDFD_SWEEP_RHS  at most this many right-hand sides per sweep pass (the
  *                   passes also never take more than fit the LDS);
  *   FDFD_SWEEP_GROUP height of the bottom-level subtrees one wavefront

@@ -243,7 +243,8 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
   P.wave_front_levels.clear();
   {
     const int cap = env_int("FDFD_WAVE_FRONTS", 1 << 20);
-    // fronts x systems a two-row level needs (FDFD_WAVE_MIN_FRONTS)
+    // fronts a two-row level needs (FDFD_WAVE_MIN_FRONTS); counted per
+    // system, so that a batch of systems is factored exactly as each alone
     const int64_t two_row_min = env_int("FDFD_WAVE_MIN_FRONTS", 16 * P.n_cu);
     const size_t lds_dyn = P.lds_limit > 512 ? P.lds_limit - 512 : 65536;
     for (int l = 0; l < P.small_prefix && (int)P.wave_front_levels.size() < cap; ++l) {
@@ -264,7 +265,7 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
       if (mmax > 128 || pmax > (nr == 2 ? 16 : 40) || (size_t)wpg * ldsw > lds_dyn) break;
       // a two-row level runs one wave per front: only with enough fronts to
       // fill the chip (otherwise a workgroup per front goes faster)
-      if (nr == 2 && (int64_t)P.levels[l].count * P.desc.nsys < two_row_min) break;
+      if (nr == 2 && (int64_t)P.levels[l].count < two_row_min) break;
       P.wave_front_levels.push_back({(int)ldsw, pmax, nr});
     }
   }
