@@ -1177,18 +1177,20 @@ struct LeafSteps {
   }
 };
 
-// Fronts of the bottom levels (at most 64 rows and PMAX pivots), one
-// wavefront per front and four per workgroup, each with its own slice of LDS;
-// every child was factored by an earlier launch.
-//   * Lane i holds row i of the pivot columns in registers: its diagonal, if a
-//     pivot, from its own stencil, and its entries in the earlier pivot
-//     columns from the couplings those pivot lanes leave in its four LDS
-//     slots (one per direction); then both children's entries of the row are
-//     added (loads through the gather rows, staged in LDS).
+// Fronts of the bottom levels (at most 64 NR rows and PMAX pivots), one
+// wavefront per front (one to four per workgroup), each with its own slice of
+// LDS; every child was factored by an earlier launch.
+//   * Lane i holds rows i (and i + 64 when NR = 2) of the pivot columns in
+//     registers: a pivot row's diagonal from its own stencil, and each row's
+//     entries in the earlier pivot columns from the couplings those pivot
+//     lanes leave in its four LDS slots (one per direction); then both
+//     children's entries of the rows are added (loads through the gather
+//     rows, staged in LDS).
 //   * Right-looking LDL^T with the loops unrolled against PMAX: at step k
-//     every lane publishes its a_ik to a 64-entry LDS buffer, reads the
-//     column back as broadcasts, and row i > k takes a_ij -= (a_ik / d_k) a_jk
-//     for the pivot columns k < j <= i.
+//     every lane publishes its a_ik to a 64-entry LDS buffer (the pivot rows
+//     are all among the first 64), reads the column back as broadcasts, and
+//     row i > k takes a_ij -= (a_ik / d_k) a_jk for the pivot columns
+//     k < j <= i.
 //   * The panel (D on the diagonal, unit-lower L below, as k_front_small
 //     stores it) goes to the factor arena; the update block
 //     U = F22 - L_u D L_u^T is formed entry by entry over its lower triangle,
