@@ -272,6 +272,10 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info);
  *                      chain step, 6 Schur-complement tile over the blocks
  *                      [k & 0xffff, k >> 16); preceded by one int32 holding
  *                      ntasks (so the table has 1 + 5 ntasks entries)
+ *   FDFD_TABLE_SWEEP_ITEMS int32 the bottom levels' sweep items: nitems, the
+ *                      subtree height H, then nitems + 1 offsets into the
+ *                      fronts list that follows (each item's fronts,
+ *                      children before parents)
  * count is the capacity of out in int32 elements.  Returns FDFD_ERR_ARG if it
  * is too small.  Works for host-only plans.
  */
@@ -279,6 +283,7 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info);
 #define FDFD_TABLE_FRONTS 1
 #define FDFD_TABLE_UPDATE 2
 #define FDFD_TABLE_TASKS 3
+#define FDFD_TABLE_SWEEP_ITEMS 4
 fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t count);
 
 /*

@@ -353,6 +353,50 @@ void build_schedule(Plan& P, size_t small_cap, std::vector<int32_t>& tasks, std:
   P.ntile_tasks = (int32_t)(tasks.size() / 5);
 }
 
+// The bottom levels' sweep items (P.wave_levels set): every front of height
+// <= H belongs to the subtree of its highest ancestor of height <= H, which
+// one wavefront sweeps whole, children before parents (no wait between them);
+// the fronts above H up to the wave levels' top are items of their own, level
+// by level.  No subtree item depends on another.  H (FDFD_SWEEP_GROUP
+// overrides it) is the highest level up to 3 that still has 16 fronts per CU.
+void build_wave_items(Plan& P) {
+  const fdfd::Analysis& A = P.an;
+  const int lw = P.wave_levels;
+  int hdef = 0;
+  for (int l = 1; l <= 3 && l < lw; ++l)
+    if ((int64_t)P.levels[l].count * P.desc.nsys >= 16 * (int64_t)P.n_cu) hdef = l;
+  P.sweep_group = lw > 0 ? std::max(0, std::min(env_int("FDFD_SWEEP_GROUP", hdef), lw - 1)) : 0;
+  const int H = P.sweep_group;
+  std::vector<int32_t>& seq = P.wave_seq_host;
+  std::vector<int32_t>& iptr = P.wave_item_ptr_host;
+  seq.clear();
+  iptr.assign(1, 0);
+  std::vector<int32_t> stack;
+  for (int l = 0; l < lw && l <= H; ++l)
+    for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
+      const int g = A.level_fronts[k];
+      const int par = A.parent[g];
+      if (A.height[g] > H || (par >= 0 && A.height[par] <= H)) continue;  // not a subtree root
+      // post-order of g's subtree: reversed pre-order with children pushed in order
+      const size_t at = seq.size();
+      stack.assign(1, g);
+      while (!stack.empty()) {
+        const int f = stack.back();
+        stack.pop_back();
+        seq.push_back(f);
+        for (int c = A.child_ptr[f]; c < A.child_ptr[f + 1]; ++c) stack.push_back(A.child_list[c]);
+      }
+      std::reverse(seq.begin() + (std::ptrdiff_t)at, seq.end());
+      iptr.push_back((int32_t)seq.size());
+    }
+  for (int l = H + 1; l < lw; ++l)
+    for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
+      seq.push_back(A.level_fronts[k]);
+      iptr.push_back((int32_t)seq.size());
+    }
+  P.wave_items = (int32_t)iptr.size() - 1;
+}
+
 // Graph replay of launch chains (FDFD_GRAPH).  A chain is recorded on the
 // plan's own capture stream (the caller's may be the null stream, which cannot
 // be captured), instantiated once per argument set and launched on the
@@ -500,6 +544,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     std::vector<int32_t> tasks, tile_base, is_tiled;
     build_schedule(P, cap, tasks, tile_base, is_tiled);
     P.tile_tasks_host = tasks;
+    P.wave_levels = P.small_prefix;
+    build_wave_items(P);
     *out = h;
     return FDFD_OK;
   }
@@ -553,49 +599,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   P.wave_levels = P.small_prefix;
   P.wave_ld = 0;
   for (int l = 0; l < P.wave_levels; ++l) P.wave_ld = std::max(P.wave_ld, P.levels[l].max_m);
-  // their sweep items: every front of height <= H belongs to the subtree of
-  // its highest ancestor of height <= H, which one wavefront sweeps whole,
-  // children before parents (no wait between them); the fronts above H up to
-  // the wave levels' top are items of their own, level by level.  No subtree
-  // item depends on another.  H (FDFD_SWEEP_GROUP overrides it) is the
-  // highest level up to 3 that still has 16 fronts per CU.
-  {
-    const int lw = P.wave_levels;
-    int hdef = 0;
-    for (int l = 1; l <= 3 && l < lw; ++l)
-      if ((int64_t)P.levels[l].count * P.desc.nsys >= 16 * (int64_t)P.n_cu) hdef = l;
-    P.sweep_group = lw > 0 ? std::max(0, std::min(env_int("FDFD_SWEEP_GROUP", hdef), lw - 1)) : 0;
-    const int H = P.sweep_group;
-    const fdfd::Analysis& A = P.an;
-    std::vector<int32_t>& seq = P.wave_seq_host;
-    std::vector<int32_t>& iptr = P.wave_item_ptr_host;
-    seq.clear();
-    iptr.assign(1, 0);
-    std::vector<int32_t> stack;
-    for (int l = 0; l < lw && l <= H; ++l)
-      for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
-        const int g = A.level_fronts[k];
-        const int par = A.parent[g];
-        if (A.height[g] > H || (par >= 0 && A.height[par] <= H)) continue;  // not a subtree root
-        // post-order of g's subtree: reversed pre-order with children pushed in order
-        const size_t at = seq.size();
-        stack.assign(1, g);
-        while (!stack.empty()) {
-          const int f = stack.back();
-          stack.pop_back();
-          seq.push_back(f);
-          for (int c = A.child_ptr[f]; c < A.child_ptr[f + 1]; ++c) stack.push_back(A.child_list[c]);
-        }
-        std::reverse(seq.begin() + (std::ptrdiff_t)at, seq.end());
-        iptr.push_back((int32_t)seq.size());
-      }
-    for (int l = H + 1; l < lw; ++l)
-      for (int k = P.levels[l].first; k < P.levels[l].first + P.levels[l].count; ++k) {
-        seq.push_back(A.level_fronts[k]);
-        iptr.push_back((int32_t)seq.size());
-      }
-    P.wave_items = (int32_t)iptr.size() - 1;
-  }
+  build_wave_items(P);
   // forward sweep items of the levels above: per level, the fronts' pivot
   // parts, then the update-row chunks of the fronts whose L21 is split.  The pivot part
   // of a front with many pivot blocks is itself split, one item per 64-row
@@ -1090,6 +1094,17 @@ fdfd_status fdfd_get_table(fdfd_plan plan, int32_t which, int32_t* out, int64_t 
     if (count < 1 + (int64_t)P.tile_tasks_host.size()) return fail(&P, FDFD_ERR_ARG, "buffer too small");
     out[0] = (int32_t)(P.tile_tasks_host.size() / 5);
     std::copy(P.tile_tasks_host.begin(), P.tile_tasks_host.end(), out + 1);
+    return FDFD_OK;
+  }
+  if (which == FDFD_TABLE_SWEEP_ITEMS) {
+    const std::vector<int32_t>& ip = P.wave_item_ptr_host;
+    const std::vector<int32_t>& sq = P.wave_seq_host;
+    const int64_t n = 2 + (int64_t)ip.size() + (int64_t)sq.size();
+    if (count < n) return fail(&P, FDFD_ERR_ARG, "buffer too small");
+    out[0] = (int32_t)ip.size() - 1;
+    out[1] = P.sweep_group;
+    std::copy(ip.begin(), ip.end(), out + 2);
+    std::copy(sq.begin(), sq.end(), out + 2 + ip.size());
     return FDFD_OK;
   }
   return fail(&P, FDFD_ERR_ARG, "unknown table");

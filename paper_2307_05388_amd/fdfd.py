@@ -22,7 +22,7 @@ FDFD_PROFILE = 2
 FDFD_GRAPH = 4
 FDFD_POL_TE = 8
 FDFD_GRAD_ACCUMULATE, FDFD_GRAD_SUM_SYSTEMS = 1, 2
-FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE, FDFD_TABLE_TASKS = 0, 1, 2, 3
+FDFD_TABLE_PERM, FDFD_TABLE_FRONTS, FDFD_TABLE_UPDATE, FDFD_TABLE_TASKS, FDFD_TABLE_SWEEP_ITEMS = 0, 1, 2, 3, 4
 
 EXPORTED = ["fdfd_analyze", "fdfd_refactor", "fdfd_solve", "fdfd_solve_noalloc", "fdfd_adjoint_grad", "fdfd_query",
             "fdfd_kernel_stats", "fdfd_get_table", "fdfd_param_forward", "fdfd_param_backward",
@@ -268,15 +268,21 @@ class Plan:
         elif which == FDFD_TABLE_FRONTS:
             info = info or self.query()
             n = 4 * info["nfronts"]
-        elif which == FDFD_TABLE_TASKS:
+        elif which in (FDFD_TABLE_TASKS, FDFD_TABLE_SWEEP_ITEMS):
             # grown until the table fits (fdfd_get_table refuses a short buffer)
             out = np.zeros(1 << 12, dtype=np.int32)
             while True:
                 st = self._lib.fdfd_get_table(self._h, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                               out.size)
                 if st == FDFD_OK:
-                    return out[1:1 + 5 * int(out[0])].reshape(-1, 5)
+                    break
                 out = np.zeros(out.size * 4, dtype=np.int32)
+            if which == FDFD_TABLE_TASKS:
+                return out[1:1 + 5 * int(out[0])].reshape(-1, 5)
+            # (height H, item offsets, fronts)
+            nit = int(out[0])
+            ptr = out[2:3 + nit].copy()
+            return int(out[1]), ptr, out[3 + nit:3 + nit + int(ptr[-1])].copy()
         else:
             fr = self.table(FDFD_TABLE_FRONTS).reshape(-1, 4)
             n = int(fr[:, 2].sum())
