@@ -1377,50 +1377,61 @@ __device__ __forceinline__ void wave_front(const KArgs& a, int f, int s, int lds
       for (int k = 0; k < 2; ++k) v = cadd(v, csel(hit[k], val[k], czero<C>()));
       return v;
     };
-    // QD rounds of 64 entries per batch; the next batch's loads are in flight
-    // while this batch's products are formed
-    constexpr int QD = NR == 2 ? 3 : PMAX <= 8 ? 1 : 2;
-    int cq[QD], rq[QD];
-    C kv[QD][2];
-    bool kh[QD][2];
-#pragma unroll
-    for (int q = 0; q < QD; ++q) {
-      entry(64 * q + lane, cq[q], rq[q]);
-      kids_load(cq[q], rq[q], 64 * q + lane < ntri, kv[q], kh[q]);
-    }
-    for (int e0 = 0; e0 < ntri; e0 += 64 * QD) {
-      int cn[QD], rn[QD];
-      C kvn[QD][2];
-      bool khn[QD][2];
+    // the loop once with the children's loads and once without (a leaf):
+    // a uniform branch around the loads inside it would make every use
+    // wait for all loads in flight
+    auto rounds = [&](auto kids) {
+      constexpr bool KIDS = decltype(kids)::value;
+      // QD rounds of 64 entries per batch; the next batch's loads are in flight
+      // while this batch's products are formed
+      constexpr int QD = NR == 2 ? 3 : PMAX <= 8 ? 1 : 2;
+      int cq[QD], rq[QD];
+      C kv[QD][2];
+      bool kh[QD][2];
 #pragma unroll
       for (int q = 0; q < QD; ++q) {
-        const int e = e0 + 64 * (QD + q) + lane;
-        entry(e, cn[q], rn[q]);
-        kids_load(cn[q], rn[q], e < ntri, kvn[q], khn[q]);
+        entry(64 * q + lane, cq[q], rq[q]);
+        if constexpr (KIDS) kids_load(cq[q], rq[q], 64 * q + lane < ntri, kv[q], kh[q]);
       }
+      for (int e0 = 0; e0 < ntri; e0 += 64 * QD) {
+        int cn[QD], rn[QD];
+        C kvn[QD][2];
+        bool khn[QD][2];
 #pragma unroll
-      for (int q = 0; q < QD; ++q) {
-        const bool ok = e0 + 64 * q + lane < ntri;
-        const C v = kids_sum(kv[q], kh[q]);
-        // indices in range for every lane, so the sum needs no per-lane
-        // branch (a branch per term would keep its LDS reads from overlapping)
-        const int ra = ok ? rq[q] : 0, ca = ok ? cq[q] : 0;
-        C acc = czero<C>();
+        for (int q = 0; q < QD; ++q) {
+          const int e = e0 + 64 * (QD + q) + lane;
+          entry(e, cn[q], rn[q]);
+          if constexpr (KIDS) kids_load(cn[q], rn[q], e < ntri, kvn[q], khn[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < QD; ++q) {
+          const bool ok = e0 + 64 * q + lane < ntri;
+          C v = czero<C>();
+          if constexpr (KIDS) v = kids_sum(kv[q], kh[q]);
+          // indices in range for every lane, so the sum needs no per-lane
+          // branch (a branch per term would keep its LDS reads from overlapping)
+          const int ra = ok ? rq[q] : 0, ca = ok ? cq[q] : 0;
+          C acc = czero<C>();
 #pragma unroll 4
-        for (int k = 0; k < p; ++k) acc = cadd(acc, cmul(Fu[k * u + ra], cmul(Fu[k * u + ca], dd[k])));
-        if (ok) U[(int64_t)cq[q] * u + rq[q]] = csub(v, acc);
-      }
+          for (int k = 0; k < p; ++k) acc = cadd(acc, cmul(Fu[k * u + ra], cmul(Fu[k * u + ca], dd[k])));
+          if (ok) U[(int64_t)cq[q] * u + rq[q]] = csub(v, acc);
+        }
 #pragma unroll
-      for (int q = 0; q < QD; ++q) {
-        cq[q] = cn[q];
-        rq[q] = rn[q];
+        for (int q = 0; q < QD; ++q) {
+          cq[q] = cn[q];
+          rq[q] = rn[q];
+          if constexpr (KIDS) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          kv[q][k] = kvn[q][k];
-          kh[q][k] = khn[q][k];
+            for (int k = 0; k < 2; ++k) {
+              kv[q][k] = kvn[q][k];
+              kh[q][k] = khn[q][k];
+            }
+          }
         }
       }
-    }
+    };
+    if (nch > 0) rounds(std::true_type{});
+    else rounds(std::false_type{});
   }
   ps.add(npert, minr, nonfin, anorm);
 }
