@@ -987,6 +987,16 @@ __device__ __forceinline__ Kids<C> kids_of(const KArgs& a, int s, int f) {
   return k;
 }
 
+// Component-wise select, so that conditional updates of a register array
+// stay branch-free (a branch around each update makes the compiler keep the
+// array in scratch across the branches).
+template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
+  C r;
+  r.x = c ? a.x : b.x;
+  r.y = c ? a.y : b.y;
+  return r;
+}
+
 // Children's contributions to NB front entries (rr[e], cc[e]) (rr[e] >= cc[e],
 // rr[e] < 0 marks an unused slot), the children's gather rows staged in LDS
 // (gl: one row of m ints per child).  The loads of both children are issued
@@ -994,17 +1004,25 @@ __device__ __forceinline__ Kids<C> kids_of(const KArgs& a, int s, int f) {
 template <typename C, int NB>
 __device__ __forceinline__ void add_children_lds(const Kids<C>& k, int m, const int* gl, const int (&rr)[NB],
                                                  const int (&cc)[NB], C (&val)[NB]) {
+  // every load unconditional (entry 0 of the block where the entry is not
+  // the child's; a missing child's block pointer is the arena's start) and
+  // its value selected after all are issued: a load inside a branch would be
+  // waited for before the branch ends, one memory round trip per entry
   C v0[NB], v1[NB];
+  bool h0[NB], h1[NB];
 #pragma unroll
   for (int e = 0; e < NB; ++e) {
     const bool use = rr[e] >= 0;
     const int g0r = use && k.n > 0 ? gl[rr[e]] : -1, g0c = use && k.n > 0 ? gl[cc[e]] : -1;
     const int g1r = use && k.n > 1 ? gl[m + rr[e]] : -1, g1c = use && k.n > 1 ? gl[m + cc[e]] : -1;
-    v0[e] = (g0r >= 0 && g0c >= 0) ? ld_ag(k.u0 + (int64_t)g0c * k.nu0 + g0r) : czero<C>();
-    v1[e] = (g1r >= 0 && g1c >= 0) ? ld_ag(k.u1 + (int64_t)g1c * k.nu1 + g1r) : czero<C>();
+    h0[e] = g0r >= 0 && g0c >= 0;
+    h1[e] = g1r >= 0 && g1c >= 0;
+    v0[e] = ld_ag(k.u0 + (h0[e] ? (int64_t)g0c * k.nu0 + g0r : 0));
+    v1[e] = ld_ag(k.u1 + (h1[e] ? (int64_t)g1c * k.nu1 + g1r : 0));
   }
 #pragma unroll
-  for (int e = 0; e < NB; ++e) val[e] = cadd(cadd(val[e], v0[e]), v1[e]);
+  for (int e = 0; e < NB; ++e)
+    val[e] = cadd(cadd(val[e], csel(h0[e], v0[e], czero<C>())), csel(h1[e], v1[e], czero<C>()));
 }
 
 // The loads of a small front that depend on no other front: the pivot
@@ -1131,16 +1149,6 @@ __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f
   for (int c = wave; c < p; c += 4)
     for (int r = c + lane; r < m; r += 64) L[(int64_t)c * m + r] = r > c ? F[c * m + r] : dd[c];
   if (threadIdx.x == 0) ps.add(npert, minr, nonfin, anorm);
-}
-
-// Component-wise select, so that conditional updates of a register array
-// stay branch-free (a branch around each update makes the compiler keep the
-// array in scratch across the branches).
-template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
-  C r;
-  r.x = c ? a.x : b.x;
-  r.y = c ? a.y : b.y;
-  return r;
 }
 
 // Pivot step K of the leaf LDL^T and every step after it, unrolled through
