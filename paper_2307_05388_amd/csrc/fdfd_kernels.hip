@@ -3370,8 +3370,8 @@ __device__ __forceinline__ void publish_wave(const Queue& q, int ep, int64_t idx
 
 // Items: seq[iptr[i] .. iptr[i+1]) -- a subtree of the bottom levels,
 // children before parents, or a single front.  The wave sweeps the item's
-// fronts in turn; a front's wait for its children ends at once for those
-// the wave itself just published.
+// fronts in turn; the dependency flags are only used at the item's boundary
+// (a single front waits, a subtree's root publishes).
 template <typename R>
 __global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepArgs w, Queue q, const int32_t* seq,
                                                                  const int32_t* iptr) {
@@ -3390,14 +3390,19 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwd_sweep_waves(KArgs a, SweepA
     if (t < q.ntasks) {
       trace_wave(q, t, 0);
       const int it = t / a.nsys, s = t % a.nsys;
-      for (int e = iptr[it]; e < iptr[it + 1]; ++e) {
+      const int e0 = iptr[it], e1 = iptr[it + 1];
+      for (int e = e0; e < e1; ++e) {
         const int f = seq[e];
-        if (q.wait) sweep_wait_children(q, ep, a, w, s, f, threadIdx.x & 63, 64);
+        // A multi-front item holds every descendant of its root, swept just
+        // before by this wave: program order makes their update vectors
+        // visible, so only a single front waits and only the root publishes.
+        if (q.wait && e1 - e0 == 1) sweep_wait_children(q, ep, a, w, s, f, threadIdx.x & 63, 64);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if (e == iptr[it]) trace_wave(q, t, 1);
+        if (e == e0) trace_wave(q, t, 1);
         fwd_front_wave<R>(a, w, s, f, V, w.wave_ld);
-        publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+        if (e == e1 - 1) publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+        else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       }
       trace_wave(q, t, 2);
     }
@@ -3423,14 +3428,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_sweep_waves(KArgs a, SweepA
     if (t < q.ntasks) {
       trace_wave(q, t, 0);
       const int it = q.ntasks / a.nsys - 1 - t / a.nsys, s = t % a.nsys;
-      for (int e = iptr[it + 1] - 1; e >= iptr[it]; --e) {
+      const int e0 = iptr[it], e1 = iptr[it + 1];
+      for (int e = e1 - 1; e >= e0; --e) {
         const int f = seq[e];
-        if (q.wait && (threadIdx.x & 63) == 0) sweep_wait_parent(q, ep, a, w, s, f);
+        // Below the root of a multi-front item every parent is the item's own,
+        // swept just before by this wave; no other item waits for its fronts.
+        if (q.wait && e == e1 - 1 && (threadIdx.x & 63) == 0) sweep_wait_parent(q, ep, a, w, s, f);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if (e == iptr[it + 1] - 1) trace_wave(q, t, 1);
+        if (e == e1 - 1) trace_wave(q, t, 1);
         bwd_front_wave<R>(a, w, s, f, X, w.wave_ld);
-        publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+        if (e1 - e0 == 1) publish_wave(q, ep, (int64_t)s * a.nfronts + f);
+        else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       }
       trace_wave(q, t, 2);
     }
