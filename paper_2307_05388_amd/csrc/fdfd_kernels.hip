@@ -3309,23 +3309,46 @@ __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
   const C* L = (const C*)a.fac + (int64_t)s * a.fac_total + a.fac_off[f];
   C* Y = (C*)w.y + (int64_t)s * nrhs * a.N;
   const int32_t* ui = a.upd_idx + a.upd_ptr[f];
+  const int prow = lane < p ? a.perm[pb + lane] : 0;  // grid cell of pivot row lane
   for (int col = 0; col < nrhs; ++col)
 #pragma unroll 1
     for (int r = lane; r < m; r += 64)
       X[col * ldv + r] = ld_ag(Y + (int64_t)col * a.N + (r < p ? pb + r : ui[r - p]));
   wave_sync();
   const C* Lc = L + (int64_t)min(lane, max(p - 1, 0)) * m;
+  // t_j = sum_{i >= p} L_ij x_i on G lanes per column, so that a front of few
+  // pivots still keeps the wave's lanes loading: lane j + k p (k < G) takes
+  // the rows p + k, p + k + G, ... of column j; lane j then adds the G sums.
+  const int G = p > 0 && u > 0 ? max(1, min(64 / p, u)) : 1;
+  const int jc = p > 0 ? lane % p : 0, kc = p > 0 ? lane / p : G;
+  const int nr = kc < G ? (u - kc + G - 1) / G : 0;  // rows of this lane
+  const int nr0 = (u + G - 1) / G;                    // rows of lane k = 0, the most
+  // Loads past a lane's last row re-read that row (row p of column 0 for a
+  // lane without rows; it exists whenever u > 0) and count as zero, so a batch
+  // is one block of loads off a uniform base with 32-bit lane offsets.
+  const int nrl = max(nr - 1, 0);
+  const char* Lt = reinterpret_cast<const char*>(L + p);
+  const uint32_t lofs = nr > 0 ? (uint32_t)(jc * m + kc) * (uint32_t)sizeof(C) : 0u;
   double2* O = w.out + (int64_t)s * w.io_ld;
   for (int col = 0; col < nrhs; ++col) {
     const C* Xc = X + col * ldv;
+    const C* Xt = Xc + p + (nr > 0 ? kc : 0);
     C acc = czero<C>();
 #pragma unroll 1
-    for (int i0 = p; i0 < m; i0 += WB) {
+    for (int r0 = 0; r0 < nr0; r0 += WB) {
       C e[WB];
 #pragma unroll
-      for (int t = 0; t < WB; ++t) e[t] = lane < p && i0 + t < m ? Lc[i0 + t] : czero<C>();
+      for (int t = 0; t < WB; ++t)
+        e[t] = *reinterpret_cast<const C*>(Lt + (uint32_t)(min(r0 + t, nrl) * G) * (uint32_t)sizeof(C) + lofs);
 #pragma unroll
-      for (int t = 0; t < WB; ++t) acc = cadd(acc, cmul(e[t], i0 + t < m ? Xc[i0 + t] : czero<C>()));
+      for (int t = 0; t < WB; ++t) {
+        const C prod = cmul(e[t], Xt[min(r0 + t, nrl) * G]);
+        acc = r0 + t < nr ? cadd(acc, prod) : acc;
+      }
+    }
+    for (int k = 1; k < G; ++k) {
+      const C o = shfl_c(acc, min(lane + k * p, 63));
+      acc = lane < p ? cadd(acc, o) : acc;
     }
     C xj = lane < p ? csub(Xc[lane], acc) : czero<C>();
     // rows i = p-1 down to 1: lane i's value is final, lanes j < i take it
@@ -3335,7 +3358,9 @@ __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
 #pragma unroll
       for (int t = 0; t < WB; ++t) {
         const int i = i0 - t;
-        e[t] = i > lane && lane < p ? Lc[i] : czero<C>();
+        // a clamped row lies below the diagonal of the lane's column
+        const C l = Lc[min(max(i, lane + 1), m - 1)];
+        e[t] = i > lane && lane < p ? l : czero<C>();
       }
 #pragma unroll
       for (int t = 0; t < WB; ++t) {
@@ -3345,7 +3370,7 @@ __device__ void bwd_front_wave(const KArgs& a, const SweepArgs& w, int s, int f,
     }
     if (lane < p) {
       st_ag(Y + (int64_t)col * a.N + pb + lane, xj);
-      double2* o = O + (int64_t)col * a.N + a.perm[pb + lane];
+      double2* o = O + (int64_t)col * a.N + prow;
       const double2 xv = to_d2(xj);
       *o = w.accumulate ? dadd(*o, xv) : xv;
     }
