@@ -858,7 +858,13 @@ __device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsb = (nb + 15) / 16;
   if (wave < nsb) {
-    const int o = 16 * wave, b = min(16, nb - o), j = lane;
+    // j is made opaque here so that the identity column below is formed in
+    // the task, not hoisted out of the persistent loop: hoisted, its 16
+    // lane-dependent values lived across every task type and were spilled,
+    // and each step waited for their reloads from scratch memory
+    int j = lane;
+    asm volatile("" : "+v"(j));
+    const int o = 16 * wave, b = min(16, nb - o);
     // Right-looking: once x_k is final every later row takes its term
     // -L_ik x_k, so the dependent chain is one step per column (a row-by-row
     // form chains all i terms of a row).  Per entry the subtractions and
