@@ -855,15 +855,16 @@ __device__ void ldl_blocked(C* F, int ld, int m, int p, C* dd, C* invd, C* scrat
 // through the 16 x 16 scratch T (reads the X_ii left by invert_diag16).
 template <typename C>
 __device__ __forceinline__ void invert_diag16(C* F, int ld, int nb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // Lane and wave are made opaque here so that the identity column and the
+  // LDS addresses below are formed in the task, not hoisted out of the
+  // persistent task loop: hoisted, these lane-dependent values lived across
+  // every task type and were spilled, and each step waited for their
+  // reloads from scratch memory.
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  asm volatile("" : "+v"(lane), "+v"(wave));
   const int nsb = (nb + 15) / 16;
   if (wave < nsb) {
-    // j is made opaque here so that the identity column below is formed in
-    // the task, not hoisted out of the persistent loop: hoisted, its 16
-    // lane-dependent values lived across every task type and were spilled,
-    // and each step waited for their reloads from scratch memory
-    int j = lane;
-    asm volatile("" : "+v"(j));
+    const int j = lane;
     const int o = 16 * wave, b = min(16, nb - o);
     // Right-looking: once x_k is final every later row takes its term
     // -L_ik x_k, so the dependent chain is one step per column (a row-by-row
@@ -2158,15 +2159,19 @@ __device__ __forceinline__ void task_fused(const KArgs& a, int s, int f, int k, 
   }
   mfma_tile_abt_lower<R>(Xs, Ls, Xs);
   // tile (k, k) - product, into Ls (lower triangle), then DIAG(k) with its
-  // pivots and scratch in the Xs region
+  // pivots and scratch in the Xs region.  The lane index is made opaque here
+  // so that the sixteen LDS addresses are formed in the task: hoisted out of
+  // the persistent loop they were spilled, one scratch round trip each.
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int c = wave + 4 * q;
-    const bool keep = c < nb && lane < nb && lane >= c;
-    t[q] = keep ? csub(t[q], Xs[c * kBW + lane]) : czero<C>();
+    const bool keep = c < nb && ln < nb && ln >= c;
+    t[q] = keep ? csub(t[q], Xs[c * kBW + ln]) : czero<C>();
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) Ls[(wave + 4 * q) * kBW + lane] = t[q];
+  for (int q = 0; q < 16; ++q) Ls[(wave + 4 * q) * kBW + ln] = t[q];
   __syncthreads();
   C* dd = Xs;
   C* invd = dd + kBW;
