@@ -2767,20 +2767,27 @@ template <typename C> constexpr int kDotBatch = 16;
 
 template <int NR, typename C>
 __device__ __forceinline__ void bwd_dots(const C* Lc, bool colok, const C* X, int m, int r0, int r1, C* acc) {
-  const int q = (threadIdx.x & 63) >> 4, rq = (threadIdx.x >> 6) >> 2;
+  // q is made opaque so that the row offsets q + 4t are formed in the call:
+  // hoisted out of the persistent loop as 64-bit values, they were spilled,
+  // and each reload waited for every load already in flight
+  int q = (threadIdx.x & 63) >> 4;
+  asm volatile("" : "+v"(q));
+  const int rq = (threadIdx.x >> 6) >> 2;
   const int per = (r1 - r0 + kNQ - 1) / kNQ;
   const int q0 = r0 + rq * per, q1 = min(r1, q0 + per);
 #pragma unroll
   for (int c = 0; c < NR; ++c) acc[c] = czero<C>();
   for (int i = q0 + q; i < q1; i += 4 * kDotBatch<C>) {
+    const C* Li = Lc + i;
+    const C* Xi = X + i;
     C l[kDotBatch<C>];
 #pragma unroll
-    for (int t = 0; t < kDotBatch<C>; ++t) l[t] = colok && i + 4 * t < q1 ? Lc[i + 4 * t] : czero<C>();
+    for (int t = 0; t < kDotBatch<C>; ++t) l[t] = colok && i + 4 * t < q1 ? Li[4 * t] : czero<C>();
 #pragma unroll
     for (int c = 0; c < NR; ++c)
 #pragma unroll
       for (int t = 0; t < kDotBatch<C>; ++t)
-        acc[c] = cadd(acc[c], cmul(l[t], i + 4 * t < q1 ? X[c * m + i + 4 * t] : czero<C>()));
+        acc[c] = cadd(acc[c], cmul(l[t], i + 4 * t < q1 ? Xi[c * m + 4 * t] : czero<C>()));
   }
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
@@ -2821,7 +2828,12 @@ __device__ __forceinline__ void bwd_block(const C* L, int ldl, const C* X, C* re
 // the same lanes, rows and summation order as bwd_dots.
 template <typename C>
 __device__ __forceinline__ void bwd_tile_load(const C* Lc, bool colok, int r0, int r1, C (&l)[8]) {
-  const int q = (threadIdx.x & 63) >> 4, rq = (threadIdx.x >> 6) >> 2;
+  // q is made opaque so that the row offsets q + 4t are formed in the call:
+  // hoisted out of the persistent loop as 64-bit values, they were spilled,
+  // and each reload waited for every load already in flight
+  int q = (threadIdx.x & 63) >> 4;
+  asm volatile("" : "+v"(q));
+  const int rq = (threadIdx.x >> 6) >> 2;
   const int per = (r1 - r0 + kNQ - 1) / kNQ;  // at most 32 rows: eight per thread
   const int q0 = r0 + rq * per, q1 = min(r1, q0 + per);
 #pragma unroll
@@ -3056,13 +3068,14 @@ __device__ void bwd_chunk(const KArgs& a, const SweepArgs& w, int s, int f, int 
   for (int c0 = 16 * wave; c0 < p; c0 += 16 * kSW) {
     const int c = c0 + (lane & 15);
     const bool cok = c < p;
-    const C* Lc = L + (int64_t)(cok ? c : 0) * m + r0;
+    // one pointer per lane and immediate offsets: with the row indices
+    // q4 + 4t as 64-bit values, the compiler hoisted all sixteen out of the
+    // persistent loop, spilled them, and waited for each reload (and so for
+    // every load already in flight) before the next load
+    const C* Lq = L + (int64_t)(cok ? c : 0) * m + r0 + q4;
     C l[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int r = q4 + 4 * t;
-      l[t] = cok && r < nr ? Lc[r] : czero<C>();
-    }
+    for (int t = 0; t < 16; ++t) l[t] = cok && q4 + 4 * t < nr ? Lq[4 * t] : czero<C>();
     for (int col = 0; col < nrhs; ++col) {
       C acc = czero<C>();
 #pragma unroll
