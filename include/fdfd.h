@@ -150,6 +150,11 @@ typedef struct {
   int32_t split_kb;          /* all blocks / never)                              */
   int32_t block_split;
   int32_t small_lds;         /* the one-workgroup kernel's LDS budget in effect  */
+  int32_t reserved3;         /* 0                                                 */
+  double analyze_ms;         /* host time of fdfd_analyze's symbolic analysis    */
+                             /* (the nested-dissection ordering and the fronts)  */
+  double setup_ms;           /* host time of the rest of fdfd_analyze: schedule, */
+                             /* device arena allocation and table uploads        */
 } fdfd_info;
 
 /*

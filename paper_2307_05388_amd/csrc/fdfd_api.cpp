@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -502,6 +503,10 @@ const char* fdfd_last_error(fdfd_plan plan) {
 fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
   if (!out) return fail(nullptr, FDFD_ERR_ARG, "out is NULL");
   *out = nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto ms_since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+  };
   fdfd_status s = check_desc(desc);
   if (s != FDFD_OK) return s;
   fdfd_plan_s* h = new (std::nothrow) fdfd_plan_s();
@@ -533,6 +538,8 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     P.front_lbytes[f] = (p * (p + 1) / 2 + u * p) * (double)P.csize;
     P.factor_lbytes += P.front_lbytes[f];
   }
+  P.analyze_ms = ms_since(t_start);
+  const auto t_setup = std::chrono::steady_clock::now();
   P.profile = (desc->flags & FDFD_PROFILE) != 0;
   // FDFD_SYRK_GROUP: pivot blocks per Schur-complement task (0 = all of them)
   P.syrk_group = desc->syrk_group != 0 ? desc->syrk_group : env_int("FDFD_SYRK_GROUP", fdfd::kSyrkGroup);
@@ -546,6 +553,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
     P.tile_tasks_host = tasks;
     P.wave_levels = P.small_prefix;
     build_wave_items(P);
+    P.setup_ms = ms_since(t_setup);
     *out = h;
     return FDFD_OK;
   }
@@ -826,6 +834,7 @@ fdfd_status fdfd_analyze(const fdfd_desc* desc, fdfd_plan* out) {
 #undef TRY
   P.solve_lds_max = fdfd::solve_lds_bytes(P, fdfd::solve_rhs_group(P, desc->max_rhs));
   P.rhs_group = fdfd::solve_rhs_group(P, desc->max_rhs);
+  P.setup_ms = ms_since(t_setup);
   *out = h;
   return FDFD_OK;
 bad:
@@ -977,6 +986,8 @@ fdfd_status fdfd_query(fdfd_plan plan, fdfd_info* info) {
   info->split_kb = P.split_kb;
   info->block_split = P.block_split;
   info->small_lds = P.small_lds;
+  info->analyze_ms = P.analyze_ms;
+  info->setup_ms = P.setup_ms;
   if (P.host_only) return FDFD_OK;
   DeviceGuard guard(P.device);
   hipError_t e = hipMemcpyAsync(P.status_host, P.status, sizeof(fdfd::DevStatus), hipMemcpyDeviceToHost,

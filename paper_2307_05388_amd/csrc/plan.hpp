@@ -74,6 +74,7 @@ struct Plan {
   fdfd_desc desc{};
   Analysis an;
   bool host_only = false;
+  double analyze_ms = 0.0, setup_ms = 0.0;  // host time of fdfd_analyze's two phases
   int device = 0;
   bool is_c64 = false;
   size_t csize = 16;           // bytes of one factor scalar (complex)

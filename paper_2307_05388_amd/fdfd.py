@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                 ("device_flags", ctypes.c_int32), ("small_levels", ctypes.c_int32),
                 ("refactor_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
                 ("rhs_group", ctypes.c_int32), ("syrk_group", ctypes.c_int32), ("split_kb", ctypes.c_int32),
-                ("block_split", ctypes.c_int32), ("small_lds", ctypes.c_int32)]
+                ("block_split", ctypes.c_int32), ("small_lds", ctypes.c_int32), ("reserved3", ctypes.c_int32),
+                ("analyze_ms", ctypes.c_double), ("setup_ms", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):

@@ -109,6 +109,16 @@ def test_analysis_statistics_match_estimator(lib):
     assert info["max_front"] == 450 and info["max_pivots"] == 300
 
 
+def test_analyze_reports_its_phase_times(lib):
+    """fdfd_analyze times its two phases itself (symbolic analysis, then the
+    rest), which the caching comparison reports as SF and set-up; the info
+    struct's layout ends with them after an explicit pad."""
+    assert ctypes.sizeof(F.Info) == 192 and F.Info.analyze_ms.offset == 176
+    P = F.Plan(300, 300, 20, host_only=True, leaf=64)
+    info = P.query()
+    assert info["analyze_ms"] > 0.0 and info["setup_ms"] >= 0.0 and info["reserved3"] == 0
+
+
 def test_nested_dissection_separators_are_grid_lines(lib):
     """Top separator of an nx x ny grid (nx >= ny) is the middle column."""
     nx, ny = 20, 14
