@@ -1048,6 +1048,99 @@ __device__ __forceinline__ void small_front_stage(const KArgs& a, int s, int f, 
   for (int k = threadIdx.x; k < nch * m; k += kThreads) gl[k] = g[k];
 }
 
+// One 64 x 64 tile (ti, tj) of a small front's update block on the matrix
+// cores: U = the children's contributions - L_u D L_u^T.  Every wave owns
+// 16 x 16 blocks (bi, bj) of the tile (on a diagonal tile the ten on or
+// below its diagonal, three or two per wave; off it one block row per wave)
+// and accumulates their real and imaginary parts over the p pivot columns,
+// four at a time (depth zero-padded past p).  Rows past u read a valid row
+// and are zeroed.  Lane l holds entries (16 bi + (l & 15), 16 bj + row(l, r)).
+template <typename R>
+__device__ __forceinline__ void schur_tile_mfma(const typename Cx<R>::T* F, int m, int p, int u, int ti, int tj,
+                                                const typename Cx<R>::T* dd, const Kids<typename Cx<R>::T>& kids,
+                                                const int* gl, typename Cx<R>::T* U) {
+  typedef typename Cx<R>::T C;
+  typedef typename Mfma<R>::v4 v4;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = l & 15, kq = l >> 4;
+  int nblk, bi[4], bj[4];
+  if (ti == tj) {
+    nblk = wave < 2 ? 3 : 2;
+    bi[0] = wave < 2 ? 3 : 2;
+    bj[0] = wave == 0 ? 0 : wave == 1 ? 2 : wave == 2 ? 0 : 2;
+    bi[1] = wave < 2 ? 3 : wave == 2 ? 2 : 1;
+    bj[1] = wave == 0 ? 1 : wave == 1 ? 3 : 1;
+    bi[2] = wave == 0 ? 0 : 1;
+    bj[2] = 0;
+    bi[3] = 0;
+    bj[3] = 0;
+  } else {
+    nblk = 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      bi[t] = wave;
+      bj[t] = t;
+    }
+  }
+  v4 re[4], im[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    re[t] = v4{0, 0, 0, 0};
+    im[t] = v4{0, 0, 0, 0};
+  }
+  const C* Fu = F + p;  // the update rows of the pivot columns
+#pragma unroll 2
+  for (int k0 = 0; k0 < p; k0 += 4) {
+    const int q = k0 + kq;
+    const bool qok = q < p;
+    const int qc = qok ? q : p - 1;
+    const C dq = dd[qc];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < nblk) {  // uniform per wave
+        const int ra = ti + 16 * bi[t] + i, rb = tj + 16 * bj[t] + i;
+        const C a0 = Fu[qc * m + min(ra, u - 1)];
+        const C b0 = Fu[qc * m + min(rb, u - 1)];
+        const C av = csel(qok && ra < u, a0, czero<C>());
+        const C bv = csel(qok && rb < u, cmul(b0, dq), czero<C>());
+        re[t] = Mfma<R>::op(bv.x, av.x, re[t]);
+        im[t] = Mfma<R>::op(bv.y, av.x, im[t]);
+        re[t] = Mfma<R>::op(bv.y, -av.y, re[t]);
+        im[t] = Mfma<R>::op(bv.x, av.y, im[t]);
+      }
+    }
+  }
+  // the children's contributions and the store, two blocks (eight entries)
+  // per batch
+#pragma unroll
+  for (int t0 = 0; t0 < 4; t0 += 2) {
+    if (t0 < nblk) {  // uniform per wave
+      int rr[8], cc[8];
+      C v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = t0 + (e >> 2), r4 = e & 3;
+        const int rw = ti + 16 * bi[t] + i, cl = tj + 16 * bj[t] + Mfma<R>::row(l, r4);
+        const bool ok = t < nblk && rw < u && cl < u && rw >= cl;
+        rr[e] = ok ? p + rw : -1;
+        cc[e] = p + cl;
+        v[e] = czero<C>();
+      }
+      add_children_lds<C, 8>(kids, m, gl, rr, cc, v);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = t0 + (e >> 2), r4 = e & 3;
+        if (rr[e] >= 0) {
+          C acc;
+          acc.x = re[t][r4];
+          acc.y = im[t][r4];
+          st_ag(U + (int64_t)(cc[e] - p) * u + (rr[e] - p), csub(v[e], acc));
+        }
+      }
+    }
+  }
+}
+
 template <typename R>
 __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f, const Kids<typename Cx<R>::T>& kids,
                             unsigned char* smem_raw, PivotStats& ps) {
@@ -1096,56 +1189,8 @@ __device__ void small_front(const KArgs& a, const Queue& q, int ep, int s, int f
 
   // Schur complement: U = F22 - L_u D L_u^T over the update rows.
   C* U = (C*)a.upd + (int64_t)s * a.upd_total + a.upd_off[f];
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  for (int ti = 0; ti < u; ti += 64) {
-    for (int tj = 0; tj <= ti; tj += 64) {
-      C acc[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = czero<C>();
-      for (int k = 0; k < p; ++k) {
-        const C* col = F + k * m + p;
-        const C dk = dd[k];
-        C av[4], bv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int r = ti + tr + 16 * x;
-          av[x] = r < u ? col[r] : czero<C>();
-        }
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int c = tj + tc + 16 * y;
-          bv[y] = c < u ? cmul(col[c], dk) : czero<C>();
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = cadd(acc[x][y], cmul(av[x], bv[y]));
-      }
-      // children's contributions to the update block, two register columns per batch
-#pragma unroll
-      for (int y0 = 0; y0 < 4; y0 += 2) {
-        int rr[8], cc[8];
-        C v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int x = e & 3, y = y0 + (e >> 2);
-          const int r = ti + tr + 16 * x, c = tj + tc + 16 * y;
-          rr[e] = (r < u && c < u && r >= c) ? p + r : -1;
-          cc[e] = p + c;
-          v[e] = czero<C>();
-        }
-        add_children_lds<C, 8>(kids, m, gl, rr, cc, v);
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (rr[e] >= 0) {
-            const int r = rr[e] - p, c = cc[e] - p;
-            st_ag(U + (int64_t)c * u + r, csub(v[e], acc[e & 3][y0 + (e >> 2)]));
-          }
-      }
-    }
-  }
+  for (int ti = 0; ti < u; ti += 64)
+    for (int tj = 0; tj <= ti; tj += 64) schur_tile_mfma<R>(F, m, p, u, ti, tj, dd, kids, gl, U);
   // the parent needs only the update block: release it before the panel
   publish(q, ep, s * a.nfronts + f);
   // Stored panel of a small front (p <= 64): D on the diagonal and the
