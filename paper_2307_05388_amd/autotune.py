@@ -106,6 +106,10 @@ def time_iterations(plan, eps_list, b, c, omegas, max_ir=0, tol=1e-10, warmup=2)
     return e0.elapsed_time(e1) / len(eps_list)
 
 
+# relative timing noise below which the tuner times candidate rows again
+TIE = 0.005
+
+
 def autotune(p, prec="c128", max_ir=0, tol=1e-10, iters=6, leaves=LEAVES, small_lds=SMALL_LDS,
              syrk_groups=SYRK_GROUPS, split_kbs=SPLIT_KBS, block_splits=BLOCK_SPLITS, cache=None,
              verbose=False):
@@ -170,6 +174,24 @@ def autotune(p, prec="c128", max_ir=0, tol=1e-10, iters=6, leaves=LEAVES, small_
                 continue
             run(cfg)
         best = min(filter(good, table), key=lambda r: r["ms"])
+    # Rows within the timing noise of the best are timed again, three runs
+    # each, and the choice is the fastest of those (marked "retimed"): one
+    # run cannot order layouts a few tenths of a millisecond apart.
+    near = [r for r in table if good(r) and r["ms"] <= best["ms"] * (1.0 + TIE)]
+    if len(near) > 1:
+        final = []
+        for r in near:
+            cfg = {kk: r[kk] for kk in KNOBS}
+            plan = Plan(p.nx, p.ny, p.npml, nsys=p.nsys, max_rhs=p.nrhs, prec=prec, tuned=False, **cfg)
+            ms = float(np.mean([time_iterations(plan, eps_list, b, c, om, max_ir=max_ir, tol=tol) for _ in range(3)]))
+            info = plan.query()
+            plan.close()
+            row = dict(r, ms=ms, status=info["status_str"], retimed=True)
+            table.append(row)
+            final.append(row)
+            if verbose:
+                print("autotune", k, row, flush=True)
+        best = min(filter(good, final), key=lambda r: r["ms"])
     out = {kk: best[kk] for kk in KNOBS}
     out.update(ms=best["ms"], max_ir=max_ir, ir_tol=tol, arch=arch, table=table)
     if cache:

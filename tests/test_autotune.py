@@ -18,9 +18,11 @@ def test_committed_table_covers_standard_workloads():
             assert e["arch"] == ARCH
             assert e["leaf"] >= 4 and e["small_lds"] >= -1
             assert e["syrk_group"] >= -1 and e["split_kb"] >= -1 and e["block_split"] >= -1
-            # the choice is the fastest row the tuner measured
+            # the choice is the fastest row the tuner measured, or of the near
+            # ties it timed again
             ok = [r for r in e["table"] if r["status"] in ("ok", "pivots perturbed")]
-            assert min(r["ms"] for r in ok) == e["ms"]
+            rt = [r for r in ok if r.get("retimed")]
+            assert min(r["ms"] for r in (rt or ok)) == e["ms"]
             assert any(all(r[k] == e[k] for k in autotune.KNOBS) for r in ok)
             # every schedule knob was varied at the chosen front layout (one knob
             # at a time, from the best setting found before it)
